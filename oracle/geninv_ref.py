@@ -1,0 +1,198 @@
+"""Float64 CPU reference of the full-rank-Cholesky Moore-Penrose inverse.
+
+TEST INFRASTRUCTURE ONLY.  This module is the oracle that the GPU library is
+checked against.  Only the test-suite, the package smoke check and the CPU
+baseline leg of the benchmark may import it; the library itself never does.
+It shares no code with the GPU path.
+
+It follows the paper (P. Courrieu, "Fast Computation of Moore-Penrose Inverse
+Matrices") step by step, in plain NumPy float64, without blocking, fusion or
+reordering:
+
+1. transpose branch when m < n                      (Appendix, transpose test)
+2. Gram matrix A = G'G                              (Section 2, Eq. (1))
+3. tol = 1e-9 * (smallest positive diagonal of A)   (Appendix, tolerance)
+4. full-rank Cholesky of A, column by column, that
+   keeps column k only when its updated pivot is
+   strictly above tol                               (Section 2, Theorem 4 of
+                                                     its ref. [6]; Appendix)
+5. M = (L'L)^-1                                     (Theorem 1; Appendix)
+6. Y = L M M L' G'                                  (Theorem 1; Appendix)
+
+and the least-squares use of the result, W = G^+ F, from Section 1.
+
+Readings of points the paper leaves open are listed with each function.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg.lapack as _lapack
+
+TOL_FACTOR = 1e-9  # Appendix: tolerance is 1e-9 times the smallest positive Gram diagonal
+
+
+@dataclass
+class GeninvResult:
+    """Everything the oracle computes, kept for parity reports."""
+    Y: np.ndarray            # n x m pseudoinverse (m x n input)
+    rank: int
+    piv: np.ndarray          # int64[rank]: 0-based pivot (accepted) column of each L column
+    d: np.ndarray            # float64[n_eff]: updated pivot value d_k seen for every k
+    tol: float | None        # None when the Gram has no positive diagonal
+    L: np.ndarray            # n_eff x rank
+    M: np.ndarray            # rank x rank, (L'L)^-1
+    A: np.ndarray            # n_eff x n_eff Gram matrix actually factored
+    transposed: bool = False
+    extra: dict = field(default_factory=dict)
+
+
+def gram(G: np.ndarray) -> np.ndarray:
+    """A = G'G (Section 2, Eq. (1); Appendix)."""
+    G = np.asarray(G, dtype=np.float64)
+    return G.T @ G
+
+
+def paper_tol(A: np.ndarray) -> float | None:
+    """Default tolerance: 1e-9 times the smallest strictly positive diagonal
+    entry of A (Appendix).  Returns None when no diagonal entry is positive:
+    the paper's minimum over an empty set is empty, every pivot test then
+    fails and the rank is 0."""
+    dA = np.diag(A)
+    pos = dA[dA > 0]
+    if pos.size == 0:
+        return None
+    return float(pos.min()) * TOL_FACTOR
+
+
+def full_rank_cholesky(A: np.ndarray, tol: float | None, *, matlab_stale: bool = False):
+    """Full-rank Cholesky factor L (n x r) with A = L L' (Section 2, Eq. (1)).
+
+    Column k of A is processed in order k = 0..n-1 (Appendix):
+        v = A[k:, k] - L[k:, :r] L[k, :r]'
+        if v[0] > tol (strict): L[k, r] = sqrt(v[0]); L[k+1:, r] = v[1:] / L[k, r]; r += 1
+        otherwise column k is dropped.
+
+    Reading: a dropped column leaves nothing behind, so every L column is zero
+    above its pivot row and L is the paper's factor S' with its zero rows
+    removed.  ``matlab_stale=True`` instead keeps the rejected value v[0] in
+    row k of the next column, as the printed listing's in-place update would.
+
+    Returns (L, r, piv, d) where d[k] is the updated pivot value of column k.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    L = np.zeros((n, n), dtype=np.float64)
+    piv = []
+    d = np.zeros(n, dtype=np.float64)
+    r = 0
+    for k in range(n):
+        v = A[k:, k] - L[k:, :r] @ L[k, :r]
+        d[k] = v[0]
+        if tol is not None and v[0] > tol:
+            s = np.sqrt(v[0])
+            L[k, r] = s
+            L[k + 1:, r] = v[1:] / s
+            piv.append(k)
+            r += 1
+        elif matlab_stale:
+            L[k, r] = v[0]
+    return L[:, :r].copy(), r, np.array(piv, dtype=np.int64), d
+
+
+def spd_inverse(B: np.ndarray) -> np.ndarray:
+    """M = B^-1 for symmetric positive definite B (Theorem 1: B = L'L).
+
+    Reading: the inverse is taken through the Cholesky factor of B (LAPACK
+    potrf then potri), which equals the general inverse in exact arithmetic
+    and uses that B is SPD.  The result is symmetrised from its lower half.
+    """
+    r = B.shape[0]
+    if r == 0:
+        return np.zeros((0, 0))
+    c, info = _lapack.dpotrf(np.asarray(B, dtype=np.float64), lower=1, clean=1)
+    if info != 0:
+        raise np.linalg.LinAlgError(f"L'L is not positive definite (potrf info={info})")
+    inv, info = _lapack.dpotri(c, lower=1)
+    if info != 0:
+        raise np.linalg.LinAlgError(f"potri failed (info={info})")
+    low = np.tril(inv)
+    return low + np.tril(inv, -1).T
+
+
+def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = False) -> GeninvResult:
+    """Moore-Penrose inverse Y = G^+ (n x m) of a real m x n matrix G.
+
+    Follows the Appendix: if m < n the method factors A = G G' instead and
+    returns Y = G' L M M L' (the transpose branch); otherwise A = G'G and
+    Y = L M M L' G' (Theorem 1).
+
+    ``tol``: None or <= 0 selects the paper's default (``paper_tol``); a
+    positive value is used as given.
+    The product chain is evaluated left to right, as written in the Appendix.
+    """
+    G = np.asarray(G, dtype=np.float64)
+    if G.ndim != 2:
+        raise ValueError("G must be 2-D")
+    m, n = G.shape
+    transposed = m < n
+    Gw = G.T if transposed else G          # work matrix with rows >= cols
+    A = gram(Gw)
+    t = paper_tol(A) if (tol is None or tol <= 0) else float(tol)
+    L, r, piv, d = full_rank_cholesky(A, t, matlab_stale=matlab_stale)
+    M = spd_inverse(L.T @ L)
+    if r == 0:
+        Y = np.zeros((n, m))
+    elif transposed:
+        Y = (((G.T @ L) @ M) @ M) @ L.T
+    else:
+        Y = (((L @ M) @ M) @ L.T) @ G.T
+    return GeninvResult(Y=np.ascontiguousarray(Y), rank=r, piv=piv, d=d, tol=t, L=L, M=M, A=A,
+                        transposed=transposed)
+
+
+def lstsq(G: np.ndarray, F: np.ndarray, tol: float | None = None):
+    """Minimum-norm least-squares weights W = G^+ F (Section 1).
+
+    Reading: the printed "W = G^+ W" is a typo for W = G^+ F, the solution of
+    min ||G W - F||^2 stated just before it.  Returns (W, result)."""
+    res = geninv(G, tol)
+    F = np.asarray(F, dtype=np.float64)
+    return res.Y @ F, res
+
+
+def decision_margins(res: GeninvResult) -> dict:
+    """Smallest accepted and largest rejected pivot, relative to tol."""
+    if res.tol is None or res.d.size == 0:
+        return {"min_acc": None, "max_rej": None}
+    acc = np.zeros(res.d.size, bool)
+    acc[res.piv] = True
+    a = res.d[acc] / res.tol
+    j = res.d[~acc] / res.tol
+    return {"min_acc": float(a.min()) if a.size else None,
+            "max_rej": float(j.max()) if j.size else None}
+
+
+def penrose_errors(G: np.ndarray, Y: np.ndarray) -> dict:
+    """Max-abs entry of the four Penrose error matrices (Section 1 and the
+    accuracy criterion of Section 3)."""
+    G = np.asarray(G, np.float64)
+    Y = np.asarray(Y, np.float64)
+    GY = G @ Y
+    YG = Y @ G
+    return {
+        "GYG-G": float(np.max(np.abs(GY @ G - G), initial=0.0)),
+        "YGY-Y": float(np.max(np.abs(YG @ Y - Y), initial=0.0)),
+        "(GY)'-GY": float(np.max(np.abs(GY.T - GY), initial=0.0)),
+        "(YG)'-YG": float(np.max(np.abs(YG.T - YG), initial=0.0)),
+    }
+
+
+def rel_fro(X: np.ndarray, Ref: np.ndarray) -> float:
+    """||X - Ref||_F / ||Ref||_F (0 when both are zero)."""
+    num = float(np.linalg.norm(np.asarray(X, np.float64) - Ref))
+    den = float(np.linalg.norm(Ref))
+    if den == 0.0:
+        return num
+    return num / den
