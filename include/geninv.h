@@ -1,0 +1,153 @@
+/*
+ * libgeninv -- Moore-Penrose inverse by full-rank Cholesky factorization on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method (P. Courrieu, "Fast Computation of Moore-Penrose Inverse Matrices",
+ * Section 2 and Appendix):
+ *   A = G'G                      Gram matrix, Eq. (1)
+ *   tol = 1e-9 * min{A_kk > 0}   Appendix (or a caller-supplied tol > 0)
+ *   A = L L'                     full-rank Cholesky: column k of A is kept only
+ *                                when its updated pivot is strictly above tol;
+ *                                L is n x r, r = rank (Section 2, Eq. (1))
+ *   M = (L'L)^-1                 Theorem 1
+ *   Y = G^+ = L M M L' G'        Theorem 1
+ *   W = G^+ F                    least-squares use, Section 1
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are column-major (element (i,j) of X at X[i + j*ldx]), with
+ *   ld >= max(1, rows).  Unless stated otherwise, matrix pointers are DEVICE
+ *   pointers owned by the caller; the library never frees them.
+ * - Every call enqueues its kernels on the context's stream and returns
+ *   without waiting, except where a HOST output pointer is passed (then the
+ *   call waits for the stream before writing it).
+ * - The return value is a geninv_status code.  Nothing aborts or prints.
+ *   Argument errors are detected on the host before anything is enqueued.
+ *   Errors found on the device (non-finite data, a non-SPD L'L) are written
+ *   to a device status word; calls that synchronize return them, and
+ *   geninv_sync_status() returns them for asynchronous calls.
+ * - A workspace grows on demand inside the context (device memory owned by
+ *   the library, freed by geninv_destroy).  Calls on one context must not
+ *   overlap on different host threads.
+ * - m or n == 0 is valid: r = 0 and nothing is written.  A Gram matrix with
+ *   no positive diagonal entry (e.g. G = 0) gives r = 0 and Y = 0, as the
+ *   paper's minimum over an empty set makes every pivot test fail.
+ */
+#ifndef GENINV_H
+#define GENINV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct geninv_ctx geninv_ctx;
+
+typedef enum {
+    GENINV_OK = 0,
+    GENINV_EINVAL = -1,      /* bad argument (sizes, leading dimensions, null pointers) */
+    GENINV_ENOMEM = -2,      /* device workspace allocation failed */
+    GENINV_EHIP = -3,        /* a HIP runtime call failed */
+    GENINV_ENONFINITE = -4,  /* G (or its Gram matrix) holds Inf/NaN; r is set to 0 */
+    GENINV_ENOTSPD = -5,     /* L'L lost positive definiteness in the inverse */
+    GENINV_ENOTSUP = -6      /* valid request that this build does not support */
+} geninv_status;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL selects the legacy default stream).  *ctx receives the
+ * handle.  Returns EINVAL for a null ctx or bad device, EHIP on runtime errors. */
+int geninv_create(geninv_ctx **ctx, int device, void *hip_stream);
+
+/* Wait for the context's stream, free its workspace and the handle. NULL is a no-op. */
+int geninv_destroy(geninv_ctx *ctx);
+
+/* Switch the stream later calls enqueue on (same device). */
+int geninv_set_stream(geninv_ctx *ctx, void *hip_stream);
+
+/* Wait for the stream and return the device-side status of the calls made
+ * since the last geninv_sync_status() (GENINV_OK, ENONFINITE or ENOTSPD);
+ * the device status word is cleared. */
+int geninv_sync_status(geninv_ctx *ctx);
+
+/* Human-readable text for a status code (static storage). */
+const char *geninv_strerror(int status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int geninv_version(void);
+
+/* Device workspace (bytes) the float64 calls need for an m x n problem with
+ * k right-hand sides (k = 0 for geninv).  Calls grow the workspace to this
+ * size on first use. */
+size_t geninv_workspace_bytes(int m, int n, int k);
+
+/* ---- whole method, float64 --------------------------------------------- */
+
+/* Y = G^+ (Theorem 1; Appendix).
+ *   G    m x n, ldg >= m (device, read only)
+ *   tol  pivot threshold; <= 0 selects the paper's default 1e-9 * min positive A_kk
+ *   Y    n x m, ldy >= n (device, written)
+ *   rank HOST int* or NULL.  If non-NULL the call waits for the stream, writes
+ *        r, and returns any device-side error status.
+ *   piv  DEVICE int[max(1, min(m,n))] or NULL: piv[c] = 0-based index of the
+ *        column of A (of G when m >= n, of G' otherwise) behind column c of L,
+ *        for c < r.  Increasing.
+ * When m < n the method factors A = G G' and forms Y = G' L M M L' (the
+ * Appendix's transpose branch). */
+int geninv_dgeninv(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double tol,
+                   double *Y, int ldy, int *rank, int *piv);
+
+/* W = G^+ F, the minimum-norm least-squares solution of min ||G W - F|| (Section 1).
+ *   F m x k (ldf >= m), W n x k (ldw >= n); rank as in geninv_dgeninv.
+ * Evaluated as W = L (M (M (L' (G' F)))) without forming Y; requires m >= n
+ * (EINVAL otherwise; use geninv_dgeninv for wide G). */
+int geninv_dlstsq(geninv_ctx *ctx, int m, int n, int k, const double *G, int ldg,
+                  const double *F, int ldf, double tol, double *W, int ldw, int *rank);
+
+/* ---- individual steps, float64 (same kernels as the whole method) ------- */
+
+/* A = G'G, Eq. (1).  G m x n (ldg >= m), A n x n (lda >= n).  Writes the lower
+ * triangle (diagonal included) when full == 0, the whole matrix otherwise. */
+int geninv_dgram(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double *A, int lda,
+                 int full);
+
+/* Full-rank Cholesky of the symmetric PSD A (n x n, lower triangle read,
+ * not modified), Appendix loop:
+ *   tol   <= 0 selects 1e-9 * min positive A_kk
+ *   L     n x n (ldl >= n, device): columns 0..r-1 receive the factor, every
+ *         other entry of the n x n block is set to zero; column c is zero above
+ *         row piv[c]
+ *   piv   DEVICE int[n] or NULL (as in geninv_dgeninv)
+ *   d     DEVICE double[n] or NULL: d[k] = updated pivot value of column k
+ *         before the test against tol (diagnostics for parity checks)
+ *   tol_used  DEVICE double* or NULL: the threshold actually applied
+ *         (+Inf when A has no positive diagonal)
+ *   rank  HOST int* or NULL (waits), as in geninv_dgeninv. */
+int geninv_dfrchol(geninv_ctx *ctx, int n, const double *A, int lda, double tol, double *L,
+                   int ldl, int *piv, double *d, double *tol_used, int *rank);
+
+/* M = B^-1 for symmetric positive definite B (r x r, ldb >= r, whole matrix
+ * read, not modified); M r x r, ldm >= r, written in full and exactly
+ * symmetric (Theorem 1: B = L'L).  A non-positive pivot block sets the
+ * device status to ENOTSPD. */
+int geninv_dspdinv(geninv_ctx *ctx, int r, const double *B, int ldb, double *M, int ldm);
+
+/* Y = L M M L' G' (Theorem 1) for given factors: L n x r (ldl >= n),
+ * M r x r symmetric (ldm >= r), G m x n (ldg >= m), Y n x m (ldy >= n). */
+int geninv_dchain(geninv_ctx *ctx, int m, int n, int r, const double *L, int ldl,
+                  const double *M, int ldm, const double *G, int ldg, double *Y, int ldy);
+
+/* C = alpha * op(A) op(B) + beta * C with the library's float64 MFMA GEMM
+ * (the contraction every step above is built from).  op(X) = X or X'
+ * (transX = 0 / 1); C is M x N (ldc >= M).  Exposed for parity testing. */
+int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, double alpha,
+                 const double *A, int lda, const double *B, int ldb, double beta, double *C,
+                 int ldc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENINV_H */

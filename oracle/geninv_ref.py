@@ -48,10 +48,20 @@ class GeninvResult:
     extra: dict = field(default_factory=dict)
 
 
-def gram(G: np.ndarray) -> np.ndarray:
-    """A = G'G (Section 2, Eq. (1); Appendix)."""
+def gram(G: np.ndarray, row_blocks: int = 1) -> np.ndarray:
+    """A = G'G (Section 2, Eq. (1); Appendix).
+
+    ``row_blocks`` > 1 sums the Gram matrices of that many row blocks of G
+    instead: the same matrix in exact arithmetic, a different rounding order.
+    Used only to measure how far two correct float64 evaluations of the method
+    can drift apart on a given input (its self-spread)."""
     G = np.asarray(G, dtype=np.float64)
-    return G.T @ G
+    if row_blocks <= 1:
+        return G.T @ G
+    A = np.zeros((G.shape[1], G.shape[1]))
+    for blk in np.array_split(G, row_blocks, axis=0):
+        A += blk.T @ blk
+    return A
 
 
 def paper_tol(A: np.ndarray) -> float | None:
@@ -121,7 +131,8 @@ def spd_inverse(B: np.ndarray) -> np.ndarray:
     return low + np.tril(inv, -1).T
 
 
-def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = False) -> GeninvResult:
+def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = False,
+           gram_row_blocks: int = 1) -> GeninvResult:
     """Moore-Penrose inverse Y = G^+ (n x m) of a real m x n matrix G.
 
     Follows the Appendix: if m < n the method factors A = G G' instead and
@@ -138,7 +149,7 @@ def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = Fals
     m, n = G.shape
     transposed = m < n
     Gw = G.T if transposed else G          # work matrix with rows >= cols
-    A = gram(Gw)
+    A = gram(Gw, gram_row_blocks)
     t = paper_tol(A) if (tol is None or tol <= 0) else float(tol)
     L, r, piv, d = full_rank_cholesky(A, t, matlab_stale=matlab_stale)
     M = spd_inverse(L.T @ L)
@@ -152,12 +163,12 @@ def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = Fals
                         transposed=transposed)
 
 
-def lstsq(G: np.ndarray, F: np.ndarray, tol: float | None = None):
+def lstsq(G: np.ndarray, F: np.ndarray, tol: float | None = None, *, gram_row_blocks: int = 1):
     """Minimum-norm least-squares weights W = G^+ F (Section 1).
 
     Reading: the printed "W = G^+ W" is a typo for W = G^+ F, the solution of
     min ||G W - F||^2 stated just before it.  Returns (W, result)."""
-    res = geninv(G, tol)
+    res = geninv(G, tol, gram_row_blocks=gram_row_blocks)
     F = np.asarray(F, dtype=np.float64)
     return res.Y @ F, res
 
@@ -187,6 +198,18 @@ def penrose_errors(G: np.ndarray, Y: np.ndarray) -> dict:
         "(GY)'-GY": float(np.max(np.abs(GY.T - GY), initial=0.0)),
         "(YG)'-YG": float(np.max(np.abs(YG.T - YG), initial=0.0)),
     }
+
+
+def self_spread(G: np.ndarray, tol: float | None = None, base: GeninvResult | None = None) -> float:
+    """Relative Frobenius distance between the oracle's Y with the Gram summed
+    in one pass and in two row halves (same decisions expected).  It measures
+    the rounding sensitivity of the method on this input: for ill-conditioned
+    G (cond(L'L) near 1/u) no two float64 evaluations agree more closely."""
+    a = base if base is not None else geninv(G, tol)
+    b = geninv(G, tol, gram_row_blocks=2)
+    if a.rank != b.rank:
+        return float("inf")
+    return rel_fro(b.Y, a.Y)
 
 
 def rel_fro(X: np.ndarray, Ref: np.ndarray) -> float:

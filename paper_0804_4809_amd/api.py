@@ -1,0 +1,203 @@
+"""Python entry points of libgeninv, same names as the C ABI.
+
+Tensors are torch float64 tensors on a GPU.  Inputs may have any strides: a
+column-major tensor (strides (1, ld)) is passed straight through, any other
+layout is first copied to column-major (the paper's storage order).  Outputs
+are returned as column-major tensors of the mathematical shape.  torch
+supplies only device memory and the current stream; every step of the method
+runs in libgeninv's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from ._lib import GeninvError, load
+
+_ctxs: dict = {}
+
+
+def _ctx(device: torch.device):
+    """Per-device context, switched to torch's current stream on every call."""
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    lib = load()
+    c = _ctxs.get(idx)
+    if c is None:
+        h = ctypes.c_void_p()
+        st = lib.geninv_create(ctypes.byref(h), idx, ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream))
+        if st != 0:
+            raise GeninvError(st, "geninv_create")
+        c = h
+        _ctxs[idx] = c
+    lib.geninv_set_stream(c, ctypes.c_void_p(torch.cuda.current_stream(idx).cuda_stream))
+    return c
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise GeninvError(st, where)
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU (libgeninv has no CPU path)")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+
+
+def colmajor(t: torch.Tensor):
+    """(tensor, ld) with column-major storage: copies only when needed."""
+    r, c = t.shape
+    if t.stride(0) == 1 and (c <= 1 or t.stride(1) >= max(1, r)):
+        return t, max(1, t.stride(1) if c > 1 else r)
+    cm = t.t().contiguous().t()
+    return cm, max(1, r)
+
+
+def empty_colmajor(rows: int, cols: int, device, dtype=torch.float64):
+    return torch.empty_strided((rows, cols), (1, max(1, rows)), device=device, dtype=dtype)
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def geninv(G: torch.Tensor, tol: float | None = None, *, return_piv: bool = False):
+    """Y = G^+ (n x m) and the rank r (Theorem 1; Appendix).  Synchronizes to read r."""
+    _dev(G, "G")
+    m, n = G.shape
+    Gc, ldg = colmajor(G)
+    Y = empty_colmajor(n, m, G.device)
+    piv = torch.empty(max(1, min(m, n)), dtype=torch.int32, device=G.device)
+    r = ctypes.c_int(0)
+    st = load().geninv_dgeninv(_ctx(G.device), m, n, _p(Gc), ldg, float(tol or 0.0), _p(Y), max(1, n),
+                               ctypes.byref(r), _p(piv))
+    _check(st, "geninv_dgeninv")
+    if return_piv:
+        return Y, r.value, piv[: r.value]
+    return Y, r.value
+
+
+def lstsq(G: torch.Tensor, F: torch.Tensor, tol: float | None = None):
+    """W = G^+ F (n x k), minimum-norm least squares (Section 1); m >= n."""
+    _dev(G, "G")
+    _dev(F, "F")
+    m, n = G.shape
+    if F.shape[0] != m:
+        raise ValueError("F must have as many rows as G")
+    k = F.shape[1]
+    Gc, ldg = colmajor(G)
+    Fc, ldf = colmajor(F)
+    W = empty_colmajor(n, k, G.device)
+    r = ctypes.c_int(0)
+    st = load().geninv_dlstsq(_ctx(G.device), m, n, k, _p(Gc), ldg, _p(Fc), ldf, float(tol or 0.0), _p(W),
+                              max(1, n), ctypes.byref(r))
+    _check(st, "geninv_dlstsq")
+    return W, r.value
+
+
+def gram(G: torch.Tensor, full: bool = True):
+    """A = G'G (Section 2, Eq. (1)); lower triangle only when full=False (upper left unset)."""
+    _dev(G, "G")
+    m, n = G.shape
+    Gc, ldg = colmajor(G)
+    A = empty_colmajor(n, n, G.device)
+    if not full:
+        A.zero_()
+    _check(load().geninv_dgram(_ctx(G.device), m, n, _p(Gc), ldg, _p(A), max(1, n), 1 if full else 0),
+           "geninv_dgram")
+    return A
+
+
+@dataclass
+class FrCholResult:
+    L: torch.Tensor        # n x r
+    rank: int
+    piv: torch.Tensor      # int32 [r]
+    d: torch.Tensor        # float64 [n], updated pivot values
+    tol: float
+
+
+def frchol(A: torch.Tensor, tol: float | None = None) -> FrCholResult:
+    """Full-rank Cholesky with column dropping (Appendix loop) of the lower triangle of A."""
+    _dev(A, "A")
+    n = A.shape[0]
+    if A.shape[1] != n:
+        raise ValueError("A must be square")
+    Ac, lda = colmajor(A)
+    L = empty_colmajor(n, n, A.device)
+    piv = torch.empty(max(1, n), dtype=torch.int32, device=A.device)
+    d = torch.empty(max(1, n), dtype=torch.float64, device=A.device)
+    tu = torch.empty(1, dtype=torch.float64, device=A.device)
+    r = ctypes.c_int(0)
+    st = load().geninv_dfrchol(_ctx(A.device), n, _p(Ac), lda, float(tol or 0.0), _p(L), max(1, n), _p(piv),
+                               _p(d), _p(tu), ctypes.byref(r))
+    _check(st, "geninv_dfrchol")
+    rv = r.value
+    return FrCholResult(L[:, :rv], rv, piv[:rv], d[:n], float(tu.item()) if n else float("inf"))
+
+
+def spd_inverse(B: torch.Tensor):
+    """M = B^-1 for SPD B (Theorem 1, B = L'L), exactly symmetric."""
+    _dev(B, "B")
+    r = B.shape[0]
+    Bc, ldb = colmajor(B)
+    M = empty_colmajor(r, r, B.device)
+    lib = load()
+    c = _ctx(B.device)
+    _check(lib.geninv_dspdinv(c, r, _p(Bc), ldb, _p(M), max(1, r)), "geninv_dspdinv")
+    _check(lib.geninv_sync_status(c), "geninv_dspdinv (device status)")
+    return M
+
+
+def chain(L: torch.Tensor, M: torch.Tensor, G: torch.Tensor):
+    """Y = L M M L' G' for given factors (Theorem 1)."""
+    for t, nm in ((L, "L"), (M, "M"), (G, "G")):
+        _dev(t, nm)
+    m, n = G.shape
+    r = L.shape[1]
+    Lc, ldl = colmajor(L) if r > 0 else (L, max(1, n))
+    Mc, ldm = colmajor(M) if r > 0 else (M, 1)
+    Gc, ldg = colmajor(G)
+    Y = empty_colmajor(n, m, G.device)
+    _check(load().geninv_dchain(_ctx(G.device), m, n, r, _p(Lc), ldl, _p(Mc), ldm, _p(Gc), ldg, _p(Y), max(1, n)),
+           "geninv_dchain")
+    return Y
+
+
+def dgemm(A: torch.Tensor, B: torch.Tensor, transA: bool = False, transB: bool = False, alpha: float = 1.0,
+          beta: float = 0.0, C: torch.Tensor | None = None):
+    """C = alpha op(A) op(B) + beta C with the library's float64 MFMA GEMM."""
+    _dev(A, "A")
+    _dev(B, "B")
+    M = A.shape[1] if transA else A.shape[0]
+    K = A.shape[0] if transA else A.shape[1]
+    N = B.shape[0] if transB else B.shape[1]
+    Kb = B.shape[1] if transB else B.shape[0]
+    if K != Kb:
+        raise ValueError("inner dimensions differ")
+    Ac, lda = colmajor(A)
+    Bc, ldb = colmajor(B)
+    if C is None:
+        C = empty_colmajor(M, N, A.device)
+        beta = 0.0
+    else:
+        _dev(C, "C")
+        if C.stride(0) != 1:
+            raise ValueError("C must be column-major")
+    _check(load().geninv_dgemm(_ctx(A.device), int(transA), int(transB), M, N, K, float(alpha), _p(Ac), lda,
+                               _p(Bc), ldb, float(beta), _p(C), max(1, C.stride(1) if N > 1 else M)),
+           "geninv_dgemm")
+    return C
+
+
+def sync_status(device=None):
+    """Wait for the stream; device-side status of the calls since the last check."""
+    dev = torch.device("cuda", device if device is not None else torch.cuda.current_device())
+    return load().geninv_sync_status(_ctx(dev))

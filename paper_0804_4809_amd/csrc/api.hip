@@ -1,0 +1,447 @@
+// libgeninv C ABI: context, workspace and the orchestration of the method's
+// steps on one HIP stream (declarations and contracts in include/geninv.h).
+#include <algorithm>
+#include <cstring>
+
+#include "common.h"
+#include "geninv.h"
+
+using namespace geninv;
+
+struct geninv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int *status = nullptr;     // device status word (separate from the workspace: survives regrowth)
+};
+
+namespace {
+
+constexpr int PART_S = 16;     // maximum split-K factor
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) return GENINV_EHIP;  \
+    } while (0)
+
+#define CHK(x)                   \
+    do {                         \
+        int s_ = (x);            \
+        if (s_ != GENINV_OK) return s_; \
+    } while (0)
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Workspace carve-up for a problem whose factored dimension is nn (the
+// smaller of m, n) with k right-hand sides.
+struct Layout {
+    size_t slotA, slotL, slotK, slotP, part, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, total;
+};
+
+Layout make_layout(int nn, int k) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t n2 = (size_t)nn * nn * sizeof(double);
+    L.slotA = take(n2);
+    L.slotL = take(n2);
+    L.slotK = take(n2);
+    L.slotP = take(n2);
+    L.part = take((size_t)PART_S * nn * std::max(FR_NB, k) * sizeof(double));
+    L.dbuf = take((size_t)GJ_NB * GJ_NB * sizeof(double));
+    L.rrow = take((size_t)GJ_NB * nn * sizeof(double));
+    L.ccol = take((size_t)nn * GJ_NB * sizeof(double));
+    L.dvals = take((size_t)nn * sizeof(double));
+    L.tol = take(sizeof(double));
+    L.rank = take((size_t)(nn / FR_NB + 2) * sizeof(int));
+    L.piv = take((size_t)std::max(nn, 1) * sizeof(int));
+    L.t0 = take((size_t)nn * std::max(k, 1) * sizeof(double));
+    L.t1 = take((size_t)nn * std::max(k, 1) * sizeof(double));
+    L.t2 = take((size_t)nn * std::max(k, 1) * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int ensure_ws(geninv_ctx *c, size_t bytes) {
+    if (bytes <= c->ws_bytes) return GENINV_OK;
+    if (c->ws) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(c->ws));
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return GENINV_ENOMEM;
+    }
+    c->ws = static_cast<char *>(p);
+    c->ws_bytes = bytes;
+    return GENINV_OK;
+}
+
+template <class T>
+T *at(geninv_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+GemmArgs gemm(const double *A, long lda, int tA, const double *B, long ldb, int tB, double *C, long ldc, Dim M,
+              Dim N, Dim K, double alpha, double beta, int uplo = GEMM_FULL) {
+    GemmArgs g{};
+    g.A = A; g.lda = lda; g.transA = tA;
+    g.B = B; g.ldb = ldb; g.transB = tB;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.K = K;
+    g.alpha = alpha; g.beta = beta;
+    g.uplo = uplo;
+    g.splitk = 1;
+    g.strideC = 0;
+    return g;
+}
+
+// C (M x N) = op(A) op(B) with split-K through the partial buffer when the
+// output has too few tiles to fill the chip.
+int gemm_splitk(geninv_ctx *c, const Layout &lay, GemmArgs g, int min_tiles = 256) {
+    const int tiles = ((g.M.host + 63) / 64) * ((g.N.host + 63) / 64);
+    int S = 1;
+    // the partial buffer holds PART_S * nn * max(64, k) doubles and M.host <= nn
+    if (tiles < min_tiles && g.K.host >= 512)
+        S = std::min({PART_S, (min_tiles + tiles - 1) / tiles, g.K.host / 256});
+    if (S <= 1) {
+        HIPCHK(launch_dgemm(g, c->stream));
+        return GENINV_OK;
+    }
+    double *part = at<double>(c, lay.part);
+    const double alpha = g.alpha, beta = g.beta;
+    double *C = g.C;
+    const long ldc = g.ldc;
+    GemmArgs p = g;
+    p.C = part;
+    p.ldc = g.M.host;
+    p.splitk = S;
+    p.strideC = (long)g.M.host * g.N.host;
+    HIPCHK(launch_dgemm(p, c->stream));
+    HIPCHK(launch_splitk_reduce(part, g.M.host, p.strideC, S, C, ldc, g.M, g.N, alpha, beta, g.uplo, c->stream));
+    return GENINV_OK;
+}
+
+// Steps 2-3: tolerance and full-rank Cholesky of the lower triangle of A
+// (nn x nn).  L (nn x nn, ldl) is zeroed and receives the compacted factor.
+int run_frchol(geninv_ctx *c, const Layout &lay, const double *A, long lda, int nn, double user_tol, double *L,
+               long ldl, int *piv, double *dvals) {
+    double *tolp = at<double>(c, lay.tol);
+    int *rank_buf = at<int>(c, lay.rank);
+    double *part = at<double>(c, lay.part);
+    const int np = (nn + FR_NB - 1) / FR_NB;
+    HIPCHK(launch_tol(A, lda, nn, user_tol, tolp, c->status, c->stream));
+    HIPCHK(launch_fill(L, ldl, nn, nn, 0.0, c->stream));
+    HIPCHK(launch_fill_int(rank_buf, np + 1, 0, c->stream));
+    const long ldp = nn;
+    const long strideP = (long)nn * FR_NB;
+    for (int p = 0; p < np; ++p) {
+        const int k0 = p * FR_NB;
+        const int w = std::min(FR_NB, nn - k0);
+        const int rows = nn - k0;
+        int S = 0;
+        if (p > 0) {
+            const int tiles = (rows + 63) / 64;
+            S = std::max(1, std::min({PART_S, (512 + tiles - 1) / tiles, std::max(1, k0 / 128)}));
+            GemmArgs g = gemm(L + k0, ldl, 0, L + k0, ldl, 1, part, ldp, hdim(rows), hdim(w),
+                              ddim(k0, rank_buf + p), 1.0, 0.0);
+            g.splitk = S;
+            g.strideC = strideP;
+            HIPCHK(launch_dgemm(g, c->stream));
+        }
+        HIPCHK(launch_frchol_panel(A, lda, part, ldp, strideP, S, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals,
+                                   c->stream));
+    }
+    return GENINV_OK;
+}
+
+// M = B^-1 in place (B r x r full symmetric, ldb), r on device (bound rb).
+int run_spdinv(geninv_ctx *c, const Layout &lay, double *B, long ldb, Dim r) {
+    double *D = at<double>(c, lay.dbuf);
+    double *R = at<double>(c, lay.rrow);
+    double *Cc = at<double>(c, lay.ccol);
+    const int nbk = (r.host + GJ_NB - 1) / GJ_NB;
+    for (int b = 0; b < nbk; ++b) {
+        HIPCHK(launch_gj_panel(B, ldb, r, b, D, R, Cc, c->status, c->stream));
+        HIPCHK(launch_gj_update(B, ldb, r, b, D, R, Cc, c->stream));
+    }
+    HIPCHK(launch_mirror_lower(B, ldb, r, c->stream));
+    return GENINV_OK;
+}
+
+// B = L'L (r x r, full) into dst; then M = B^-1 in place.
+int run_factor_inverse(geninv_ctx *c, const Layout &lay, const double *L, long ldl, int nn, const int *rdev,
+                       double *dst, long ldd) {
+    const Dim r = ddim(nn, rdev);
+    GemmArgs g = gemm(L, ldl, 1, L, ldl, 0, dst, ldd, r, r, hdim(nn), 1.0, 0.0, GEMM_LOWER);
+    HIPCHK(launch_dgemm(g, c->stream));
+    HIPCHK(launch_mirror_lower(dst, ldd, r, c->stream));
+    return run_spdinv(c, lay, dst, ldd, r);
+}
+
+int finish_rank(geninv_ctx *c, const int *rdev, int *rank) {
+    if (!rank) return GENINV_OK;
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(rank, rdev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (st != 0) {
+        int zero = 0;
+        HIPCHK(hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    }
+    return st;
+}
+
+bool bad_ld(long ld, int rows) { return ld < std::max(1, rows); }
+
+}  // namespace
+
+extern "C" {
+
+int geninv_version(void) { return 100; }
+
+const char *geninv_strerror(int s) {
+    switch (s) {
+        case GENINV_OK: return "success";
+        case GENINV_EINVAL: return "invalid argument";
+        case GENINV_ENOMEM: return "device workspace allocation failed";
+        case GENINV_EHIP: return "HIP runtime error";
+        case GENINV_ENONFINITE: return "input holds Inf or NaN (or its Gram matrix overflows)";
+        case GENINV_ENOTSPD: return "L'L is not positive definite in floating point";
+        case GENINV_ENOTSUP: return "not supported by this build";
+        default: return "unknown status";
+    }
+}
+
+int geninv_create(geninv_ctx **ctx, int device, void *hip_stream) {
+    if (!ctx) return GENINV_EINVAL;
+    *ctx = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return GENINV_EHIP;
+    if (device < 0 || device >= ndev) return GENINV_EINVAL;
+    DeviceGuard g(device);
+    geninv_ctx *c = new geninv_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    void *p = nullptr;
+    if (hipMalloc(&p, 256) != hipSuccess) {
+        delete c;
+        return GENINV_ENOMEM;
+    }
+    c->status = static_cast<int *>(p);
+    if (hipMemset(c->status, 0, 256) != hipSuccess) {
+        (void)hipFree(p);
+        delete c;
+        return GENINV_EHIP;
+    }
+    *ctx = c;
+    return GENINV_OK;
+}
+
+int geninv_destroy(geninv_ctx *c) {
+    if (!c) return GENINV_OK;
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->status) (void)hipFree(c->status);
+    delete c;
+    return GENINV_OK;
+}
+
+int geninv_set_stream(geninv_ctx *c, void *hip_stream) {
+    if (!c) return GENINV_EINVAL;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return GENINV_OK;
+}
+
+int geninv_sync_status(geninv_ctx *c) {
+    if (!c) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (st != 0) {
+        int zero = 0;
+        HIPCHK(hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    }
+    return st;
+}
+
+size_t geninv_workspace_bytes(int m, int n, int k) {
+    if (m <= 0 || n <= 0 || k < 0) return 0;
+    return make_layout(std::min(m, n), k).total;
+}
+
+int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, double alpha, const double *A,
+                 int lda, const double *B, int ldb, double beta, double *C, int ldc) {
+    if (!c || M < 0 || N < 0 || K < 0) return GENINV_EINVAL;
+    if (M == 0 || N == 0) return GENINV_OK;
+    if (!C || bad_ld(ldc, M)) return GENINV_EINVAL;
+    if (K > 0 && (!A || !B || bad_ld(lda, transA ? K : M) || bad_ld(ldb, transB ? N : K))) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    GemmArgs a = gemm(A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0, C, ldc, hdim(M), hdim(N), hdim(K), alpha,
+                      beta);
+    HIPCHK(launch_dgemm(a, c->stream));
+    return GENINV_OK;
+}
+
+int geninv_dgram(geninv_ctx *c, int m, int n, const double *G, int ldg, double *A, int lda, int full) {
+    if (!c || m < 0 || n < 0) return GENINV_EINVAL;
+    if (n == 0) return GENINV_OK;
+    if (!A || bad_ld(lda, n) || (m > 0 && (!G || bad_ld(ldg, m)))) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    GemmArgs a = gemm(G, ldg, 1, G, ldg, 0, A, lda, hdim(n), hdim(n), hdim(m), 1.0, 0.0,
+                      full ? GEMM_FULL : GEMM_LOWER);
+    HIPCHK(launch_dgemm(a, c->stream));
+    return GENINV_OK;
+}
+
+int geninv_dfrchol(geninv_ctx *c, int n, const double *A, int lda, double tol, double *L, int ldl, int *piv,
+                   double *d, double *tol_used, int *rank) {
+    if (!c || n < 0) return GENINV_EINVAL;
+    if (n == 0) {
+        if (rank) *rank = 0;
+        return GENINV_OK;
+    }
+    if (!A || !L || bad_ld(lda, n) || bad_ld(ldl, n)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const Layout lay = make_layout(n, 0);
+    CHK(ensure_ws(c, lay.total));
+    int *pv = piv ? piv : at<int>(c, lay.piv);
+    double *dv = d ? d : at<double>(c, lay.dvals);
+    CHK(run_frchol(c, lay, A, lda, n, tol, L, ldl, pv, dv));
+    const int np = (n + FR_NB - 1) / FR_NB;
+    if (tol_used) HIPCHK(launch_copy(at<double>(c, lay.tol), 1, tol_used, 1, hdim(1), hdim(1), c->stream));
+    return finish_rank(c, at<int>(c, lay.rank) + np, rank);
+}
+
+int geninv_dspdinv(geninv_ctx *c, int r, const double *B, int ldb, double *M, int ldm) {
+    if (!c || r < 0) return GENINV_EINVAL;
+    if (r == 0) return GENINV_OK;
+    if (!B || !M || bad_ld(ldb, r) || bad_ld(ldm, r)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const Layout lay = make_layout(r, 0);
+    CHK(ensure_ws(c, lay.total));
+    HIPCHK(launch_copy(B, ldb, M, ldm, hdim(r), hdim(r), c->stream));
+    return run_spdinv(c, lay, M, ldm, hdim(r));
+}
+
+int geninv_dchain(geninv_ctx *c, int m, int n, int r, const double *L, int ldl, const double *M, int ldm,
+                  const double *G, int ldg, double *Y, int ldy) {
+    if (!c || m < 0 || n < 0 || r < 0 || r > n) return GENINV_EINVAL;
+    if (m == 0 || n == 0) return GENINV_OK;
+    if (!G || !Y || bad_ld(ldg, m) || bad_ld(ldy, n)) return GENINV_EINVAL;
+    if (r > 0 && (!L || !M || bad_ld(ldl, n) || bad_ld(ldm, r))) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const Layout lay = make_layout(n, 0);
+    CHK(ensure_ws(c, lay.total));
+    double *K = at<double>(c, lay.slotK);
+    double *P = at<double>(c, lay.slotP);
+    HIPCHK(launch_dgemm(gemm(L, ldl, 0, M, ldm, 0, K, n, hdim(n), hdim(r), hdim(r), 1.0, 0.0), c->stream));
+    HIPCHK(launch_dgemm(gemm(K, n, 0, K, n, 1, P, n, hdim(n), hdim(n), hdim(r), 1.0, 0.0, GEMM_LOWER), c->stream));
+    HIPCHK(launch_mirror_lower(P, n, hdim(n), c->stream));
+    HIPCHK(launch_dgemm(gemm(P, n, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
+    return GENINV_OK;
+}
+
+int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double tol, double *Y, int ldy,
+                   int *rank, int *piv) {
+    if (!c || m < 0 || n < 0) return GENINV_EINVAL;
+    if (m == 0 || n == 0) {
+        if (rank) *rank = 0;
+        return GENINV_OK;
+    }
+    if (!G || !Y || bad_ld(ldg, m) || bad_ld(ldy, n)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const bool tr = m < n;              // Appendix: factor G G' when m < n
+    const int nn = tr ? m : n;
+    const Layout lay = make_layout(nn, 0);
+    CHK(ensure_ws(c, lay.total));
+    double *A = at<double>(c, lay.slotA);
+    double *L = at<double>(c, lay.slotL);
+    double *K = at<double>(c, lay.slotK);
+    double *P = at<double>(c, lay.slotP);
+    int *pv = piv ? piv : at<int>(c, lay.piv);
+    const long ld = nn;
+
+    // 1. Gram matrix, lower triangle: A = G'G, or G G' in the transpose branch
+    if (!tr) HIPCHK(launch_dgemm(gemm(G, ldg, 1, G, ldg, 0, A, ld, hdim(nn), hdim(nn), hdim(m), 1.0, 0.0, GEMM_LOWER), c->stream));
+    else HIPCHK(launch_dgemm(gemm(G, ldg, 0, G, ldg, 1, A, ld, hdim(nn), hdim(nn), hdim(n), 1.0, 0.0, GEMM_LOWER), c->stream));
+    // 2-3. tolerance and full-rank Cholesky
+    CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, pv, at<double>(c, lay.dvals)));
+    const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
+    const Dim r = ddim(nn, rdev);
+    // 4. M = (L'L)^-1 into the Gram's slot
+    CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
+    // 5. K = L M, P = K K' (= (G'G)^+), then Y = P G' or Y = G' P
+    HIPCHK(launch_dgemm(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0), c->stream));
+    HIPCHK(launch_dgemm(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER), c->stream));
+    HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
+    if (!tr) HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
+    else HIPCHK(launch_dgemm(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0), c->stream));
+    return finish_rank(c, rdev, rank);
+}
+
+int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf,
+                  double tol, double *W, int ldw, int *rank) {
+    if (!c || m < 0 || n < 0 || k < 0) return GENINV_EINVAL;
+    if (n == 0 || m == 0) {
+        // G^+ is n x 0 or 0 x m: W = 0 (n x k)
+        if (n > 0 && k > 0) {
+            if (!W || bad_ld(ldw, n)) return GENINV_EINVAL;
+            DeviceGuard g(c->device);
+            HIPCHK(launch_fill(W, ldw, n, k, 0.0, c->stream));
+        }
+        if (rank) *rank = 0;
+        return GENINV_OK;
+    }
+    if (m < n) return GENINV_EINVAL;
+    if (!G || !F || !W || bad_ld(ldg, m) || bad_ld(ldf, m) || bad_ld(ldw, n)) return GENINV_EINVAL;
+    if (k > 4096) return GENINV_ENOTSUP;
+    DeviceGuard g(c->device);
+    const int nn = n;
+    const Layout lay = make_layout(nn, k);
+    CHK(ensure_ws(c, lay.total));
+    double *A = at<double>(c, lay.slotA);
+    double *L = at<double>(c, lay.slotL);
+    double *T0 = at<double>(c, lay.t0);
+    double *T1 = at<double>(c, lay.t1);
+    double *T2 = at<double>(c, lay.t2);
+    const long ld = nn;
+
+    HIPCHK(launch_dgemm(gemm(G, ldg, 1, G, ldg, 0, A, ld, hdim(nn), hdim(nn), hdim(m), 1.0, 0.0, GEMM_LOWER), c->stream));
+    CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, at<int>(c, lay.piv), at<double>(c, lay.dvals)));
+    const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
+    const Dim r = ddim(nn, rdev);
+    CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
+    if (k > 0) {
+        // W = L (M (M (L' (G' F))))
+        CHK(gemm_splitk(c, lay, gemm(G, ldg, 1, F, ldf, 0, T0, ld, hdim(nn), hdim(k), hdim(m), 1.0, 0.0)));
+        HIPCHK(launch_dgemm(gemm(L, ld, 1, T0, ld, 0, T1, ld, r, hdim(k), hdim(nn), 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(A, ld, 0, T1, ld, 0, T2, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(A, ld, 0, T2, ld, 0, T1, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(L, ld, 0, T1, ld, 0, W, ldw, hdim(nn), hdim(k), r, 1.0, 0.0), c->stream));
+    }
+    return finish_rank(c, rdev, rank);
+}
+
+}  // extern "C"

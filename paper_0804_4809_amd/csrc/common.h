@@ -1,0 +1,64 @@
+// Internal declarations shared by the libgeninv HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace geninv {
+
+// A matrix dimension that is either fixed on the host or read from device
+// memory at kernel start (the rank r is only known on the device, so the
+// kernels that depend on it are launched for an upper bound and read the
+// actual value themselves; no host read-back is needed between steps).
+struct Dim {
+    int host;          // value used when dev == nullptr, and the launch upper bound
+    const int *dev;    // optional device location of the actual value (<= host)
+    __device__ __forceinline__ int get() const { return dev ? *dev : host; }
+};
+
+static inline Dim hdim(int v) { return Dim{v, nullptr}; }
+static inline Dim ddim(int bound, const int *p) { return Dim{bound, p}; }
+
+// Output modes of the GEMM epilogue.
+enum GemmUplo { GEMM_FULL = 0, GEMM_LOWER = 1 };
+
+struct GemmArgs {
+    const double *A; long lda; int transA;
+    const double *B; long ldb; int transB;
+    double *C; long ldc;
+    Dim M, N, K;
+    double alpha, beta;
+    int uplo;          // GemmUplo; GEMM_LOWER skips tiles above the diagonal and elements with row < col
+    int splitk;        // > 1: gridDim.z slices of K, raw partial sums written to C + z*strideC
+    long strideC;
+};
+
+// Device status word values (match geninv_status).
+enum { ST_OK = 0, ST_NONFINITE = -4, ST_NOTSPD = -5 };
+
+// ---- launchers (kernels.hip) -------------------------------------------------
+hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s);
+hipError_t launch_splitk_reduce(const double *part, long ldp, long strideP, int S, double *C, long ldc,
+                                Dim M, Dim N, double alpha, double beta, int uplo, hipStream_t s);
+hipError_t launch_fill(double *X, long ldx, int rows, int cols, double v, hipStream_t s);
+hipError_t launch_fill_int(int *x, int n, int v, hipStream_t s);
+hipError_t launch_copy(const double *X, long ldx, double *Yp, long ldy, Dim rows, Dim cols, hipStream_t s);
+hipError_t launch_mirror_lower(double *X, long ldx, Dim n, hipStream_t s);
+hipError_t launch_transpose(const double *X, long ldx, double *Yp, long ldy, int rows, int cols, hipStream_t s);
+
+// full-rank Cholesky (frchol.hip)
+constexpr int FR_NB = 64;          // panel width
+hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double *tol_out, int *status,
+                      hipStream_t s);
+hipError_t launch_frchol_panel(const double *A, long lda, const double *part, long ldp, long strideP,
+                               int S, double *L, long ldl, int *rank_buf, int p, int k0, int w, int n,
+                               const double *tol, int *piv, double *dvals, hipStream_t s);
+
+// SPD inverse by block Gauss-Jordan (spdinv.hip)
+constexpr int GJ_NB = 64;
+hipError_t launch_gj_panel(const double *B, long ldb, Dim r, int b, double *D, double *Rrow, double *Ccol,
+                           int *status, hipStream_t s);
+hipError_t launch_gj_update(double *B, long ldb, Dim r, int b, const double *D, const double *Rrow,
+                            const double *Ccol, hipStream_t s);
+
+}  // namespace geninv

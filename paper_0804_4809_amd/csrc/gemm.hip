@@ -1,0 +1,274 @@
+// Float64 MFMA GEMM for gfx950 and small memory-bound helpers.
+//
+// Every dense contraction of the method runs through this kernel: the Gram
+// matrix A = G'G (Section 2, Eq. (1)), the panel updates of the full-rank
+// Cholesky (Appendix loop), L'L, and the product chain L M M L' G'
+// (Theorem 1).  Column-major operands, optional transposes, device-resident
+// dimensions (the rank r), a lower-triangle-only mode for symmetric outputs
+// and split-K for skinny products.
+//
+// Tiling: a workgroup owns a BM x BN tile of C, made of WM x WN wavefronts
+// (64 lanes each); each wavefront owns (BM/WM) x (BN/WN) and issues
+// v_mfma_f64_16x16x4_f64 on 16 x 16 blocks.  K is consumed in chunks of BK
+// staged through double-buffered LDS; the next chunk's global loads are in
+// flight while the current chunk feeds the matrix cores.
+//
+// MFMA operand roles are swapped (the instruction computes the transposed
+// tile C' = op(B)' op(A)') so that the 16 lanes of a row group hold 16
+// consecutive rows of one column of C: every store of the epilogue is a
+// 128-byte contiguous run of the column-major output.
+#include "common.h"
+
+namespace geninv {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int BK, int WM, int WN>
+__global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
+    constexpr int NT = WM * WN * 64;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 16, FN = TN / 16;
+    constexpr int LA = BM + 1, LB = BN + 1;   // one double of padding per LDS row
+    constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
+    static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile/thread mismatch");
+    static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
+
+    __shared__ double As[2][BK][LA];
+    __shared__ double Bs[2][BK][LB];
+
+    const int M = p.M.get(), N = p.N.get(), K = p.K.get();
+    const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
+    if (row0 >= M || col0 >= N) return;
+    if (p.uplo == GEMM_LOWER && col0 >= row0 + BM) return;
+
+    int kbeg = 0, kend = K;
+    double *C = p.C;
+    if (p.splitk > 1) {
+        const int chunk = (((K + p.splitk - 1) / p.splitk) + BK - 1) / BK * BK;
+        kbeg = blockIdx.z * chunk;
+        kend = min(K, kbeg + chunk);
+        C += (long)blockIdx.z * p.strideC;
+    }
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const double *__restrict__ A = p.A;
+    const double *__restrict__ B = p.B;
+    const long lda = p.lda, ldb = p.ldb;
+    const int tA = p.transA, tB = p.transB;
+
+    double ra[EA], rb[EB];
+
+    // element e of a chunk -> (row-or-col index, k index), chosen so that
+    // consecutive threads read consecutive addresses of global memory
+    auto a_idx = [&](int e, int &i, int &k) {
+        if (!tA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
+    };
+    auto b_idx = [&](int e, int &j, int &k) {
+        if (tB) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
+    };
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < EA; ++q) {
+            int i, k;
+            a_idx(tid + NT * q, i, k);
+            const int gi = row0 + i, gk = kc + k;
+            double v = 0.0;
+            if (gi < M && gk < kend) v = tA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
+            ra[q] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < EB; ++q) {
+            int j, k;
+            b_idx(tid + NT * q, j, k);
+            const int gj = col0 + j, gk = kc + k;
+            double v = 0.0;
+            if (gj < N && gk < kend) v = tB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb];
+            rb[q] = v;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < EA; ++q) {
+            int i, k;
+            a_idx(tid + NT * q, i, k);
+            As[buf][k][i] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < EB; ++q) {
+            int j, k;
+            b_idx(tid + NT * q, j, k);
+            Bs[buf][k][j] = rb[q];
+        }
+    };
+
+    d4 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nchunks = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+    if (nchunks > 0) {
+        gload(kbeg);
+        sstore(0);
+        __syncthreads();
+        for (int c = 0; c < nchunks; ++c) {
+            const int buf = c & 1;
+            const bool more = c + 1 < nchunks;
+            if (more) gload(kbeg + (c + 1) * BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                double af[FM], bf[FN];
+                const int kr = kk + (lane >> 4);
+#pragma unroll
+                for (int a = 0; a < FM; ++a) af[a] = As[buf][kr][wm * TM + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < FN; ++b) bf[b] = Bs[buf][kr][wn * TN + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+            }
+            if (more) sstore(buf ^ 1);
+            __syncthreads();
+        }
+    }
+
+    const bool lower = p.uplo == GEMM_LOWER;
+    const long ldc = p.ldc;
+    const double alpha = p.alpha, beta = p.beta;
+    const bool raw = p.splitk > 1;
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+        const int r = row0 + wm * TM + a * 16 + (lane & 15);
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = col0 + wn * TN + b * 16 + 4 * (lane >> 4) + v;
+                if (r < M && c < N && (!lower || r >= c)) {
+                    double *dst = C + r + (long)c * ldc;
+                    const double val = acc[a][b][v];
+                    if (raw) *dst = val;
+                    else *dst = (beta != 0.0) ? alpha * val + beta * (*dst) : alpha * val;
+                }
+            }
+        }
+    }
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s) {
+    const int S = a.splitk > 1 ? a.splitk : 1;
+    dim3 grid((a.M.host + BM - 1) / BM, (a.N.host + BN - 1) / BN, S);
+    if (grid.x == 0 || grid.y == 0) return hipSuccess;
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s) {
+    if (a.M.host <= 0 || a.N.host <= 0) return hipSuccess;
+    const long big_tiles = (long)((a.M.host + 127) / 128) * ((a.N.host + 127) / 128) *
+                           (a.splitk > 1 ? a.splitk : 1);
+    if (big_tiles >= 512 && a.K.host >= 256) return launch_cfg<128, 128, 16, 2, 2>(a, s);
+    return launch_cfg<64, 64, 16, 2, 2>(a, s);
+}
+
+// ---------------------------------------------------------------------------
+// split-K reduction: C = alpha * sum_z part[z] + beta * C
+// ---------------------------------------------------------------------------
+__global__ void splitk_reduce_kernel(const double *part, long ldp, long strideP, int S, double *C, long ldc,
+                                     Dim Md, Dim Nd, double alpha, double beta, int uplo) {
+    const int M = Md.get(), N = Nd.get();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= M || j >= N) return;
+    if (uplo == GEMM_LOWER && i < j) return;
+    double sum = 0.0;
+    for (int z = 0; z < S; ++z) sum += part[z * strideP + i + (long)j * ldp];
+    double *dst = C + i + (long)j * ldc;
+    *dst = (beta != 0.0) ? alpha * sum + beta * (*dst) : alpha * sum;
+}
+
+hipError_t launch_splitk_reduce(const double *part, long ldp, long strideP, int S, double *C, long ldc, Dim M,
+                                Dim N, double alpha, double beta, int uplo, hipStream_t s) {
+    if (M.host <= 0 || N.host <= 0) return hipSuccess;
+    dim3 grid((M.host + 255) / 256, N.host);
+    hipLaunchKernelGGL(splitk_reduce_kernel, grid, dim3(256), 0, s, part, ldp, strideP, S, C, ldc, M, N, alpha,
+                       beta, uplo);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fills and copies (no hipMemsetAsync: every step stays capturable in a graph)
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(double *X, long ldx, int rows, int cols, double v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < rows && j < cols) X[i + (long)j * ldx] = v;
+}
+
+hipError_t launch_fill(double *X, long ldx, int rows, int cols, double v, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    dim3 grid((rows + 255) / 256, cols);
+    hipLaunchKernelGGL(fill_kernel, grid, dim3(256), 0, s, X, ldx, rows, cols, v);
+    return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int *x, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+hipError_t launch_fill_int(int *x, int n, int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
+__global__ void copy_kernel(const double *X, long ldx, double *Yp, long ldy, Dim Rd, Dim Cd) {
+    const int rows = Rd.get(), cols = Cd.get();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < rows && j < cols) Yp[i + (long)j * ldy] = X[i + (long)j * ldx];
+}
+
+hipError_t launch_copy(const double *X, long ldx, double *Yp, long ldy, Dim rows, Dim cols, hipStream_t s) {
+    if (rows.host <= 0 || cols.host <= 0) return hipSuccess;
+    dim3 grid((rows.host + 255) / 256, cols.host);
+    hipLaunchKernelGGL(copy_kernel, grid, dim3(256), 0, s, X, ldx, Yp, ldy, rows, cols);
+    return hipGetLastError();
+}
+
+// Upper triangle := transpose of the lower triangle, through 32 x 32 LDS tiles
+// so that both the read and the write are column-contiguous.
+__global__ void mirror_lower_kernel(double *X, long ldx, Dim nd) {
+    __shared__ double t[32][33];
+    const int n = nd.get();
+    const int bi = blockIdx.x, bj = blockIdx.y;    // source tile (bi, bj) with bi >= bj
+    if (bi < bj) return;
+    const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int i = bi * 32 + tx, j = bj * 32 + yy;
+        t[yy][tx] = (i < n && j < n) ? X[i + (long)j * ldx] : 0.0;
+    }
+    __syncthreads();
+    // destination (j, i) for source (i, j) with i > j
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int di = bj * 32 + tx;   // destination row = source column
+        const int dj = bi * 32 + yy;   // destination column = source row
+        if (di < n && dj < n && dj > di) X[di + (long)dj * ldx] = t[tx][yy];
+    }
+}
+
+hipError_t launch_mirror_lower(double *X, long ldx, Dim n, hipStream_t s) {
+    if (n.host <= 0) return hipSuccess;
+    const int nt = (n.host + 31) / 32;
+    hipLaunchKernelGGL(mirror_lower_kernel, dim3(nt, nt), dim3(32, 8), 0, s, X, ldx, n);
+    return hipGetLastError();
+}
+
+}  // namespace geninv
