@@ -76,7 +76,8 @@ def paper_tol(A: np.ndarray) -> float | None:
     return float(pos.min()) * TOL_FACTOR
 
 
-def full_rank_cholesky(A: np.ndarray, tol: float | None, *, matlab_stale: bool = False):
+def full_rank_cholesky(A: np.ndarray, tol: float | None, *, matlab_stale: bool = False,
+                       forced: np.ndarray | None = None):
     """Full-rank Cholesky factor L (n x r) with A = L L' (Section 2, Eq. (1)).
 
     Column k of A is processed in order k = 0..n-1 (Appendix):
@@ -89,6 +90,11 @@ def full_rank_cholesky(A: np.ndarray, tol: float | None, *, matlab_stale: bool =
     removed.  ``matlab_stale=True`` instead keeps the rejected value v[0] in
     row k of the next column, as the printed listing's in-place update would.
 
+    ``forced`` (bool[n], replay mode) takes the keep/drop decision of every
+    column from the given mask instead of the tol test, with the arithmetic
+    otherwise unchanged.  It lets a parity check reproduce another
+    implementation's decisions when a pivot lies within rounding of tol.
+
     Returns (L, r, piv, d) where d[k] is the updated pivot value of column k.
     """
     A = np.asarray(A, dtype=np.float64)
@@ -100,7 +106,8 @@ def full_rank_cholesky(A: np.ndarray, tol: float | None, *, matlab_stale: bool =
     for k in range(n):
         v = A[k:, k] - L[k:, :r] @ L[k, :r]
         d[k] = v[0]
-        if tol is not None and v[0] > tol:
+        keep = (tol is not None and v[0] > tol) if forced is None else bool(forced[k])
+        if keep:
             s = np.sqrt(v[0])
             L[k, r] = s
             L[k + 1:, r] = v[1:] / s
@@ -132,7 +139,8 @@ def spd_inverse(B: np.ndarray) -> np.ndarray:
 
 
 def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = False,
-           gram_row_blocks: int = 1) -> GeninvResult:
+           gram_row_blocks: int = 1, forced: np.ndarray | None = None,
+           A: np.ndarray | None = None) -> GeninvResult:
     """Moore-Penrose inverse Y = G^+ (n x m) of a real m x n matrix G.
 
     Follows the Appendix: if m < n the method factors A = G G' instead and
@@ -142,6 +150,8 @@ def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = Fals
     ``tol``: None or <= 0 selects the paper's default (``paper_tol``); a
     positive value is used as given.
     The product chain is evaluated left to right, as written in the Appendix.
+    ``forced``: replay mode of ``full_rank_cholesky``.  ``A``: use this Gram
+    matrix instead of forming it (sensitivity studies).
     """
     G = np.asarray(G, dtype=np.float64)
     if G.ndim != 2:
@@ -149,9 +159,10 @@ def geninv(G: np.ndarray, tol: float | None = None, *, matlab_stale: bool = Fals
     m, n = G.shape
     transposed = m < n
     Gw = G.T if transposed else G          # work matrix with rows >= cols
-    A = gram(Gw, gram_row_blocks)
+    if A is None:
+        A = gram(Gw, gram_row_blocks)
     t = paper_tol(A) if (tol is None or tol <= 0) else float(tol)
-    L, r, piv, d = full_rank_cholesky(A, t, matlab_stale=matlab_stale)
+    L, r, piv, d = full_rank_cholesky(A, t, matlab_stale=matlab_stale, forced=forced)
     M = spd_inverse(L.T @ L)
     if r == 0:
         Y = np.zeros((n, m))
@@ -200,16 +211,73 @@ def penrose_errors(G: np.ndarray, Y: np.ndarray) -> dict:
     }
 
 
-def self_spread(G: np.ndarray, tol: float | None = None, base: GeninvResult | None = None) -> float:
-    """Relative Frobenius distance between the oracle's Y with the Gram summed
-    in one pass and in two row halves (same decisions expected).  It measures
-    the rounding sensitivity of the method on this input: for ill-conditioned
-    G (cond(L'L) near 1/u) no two float64 evaluations agree more closely."""
-    a = base if base is not None else geninv(G, tol)
-    b = geninv(G, tol, gram_row_blocks=2)
-    if a.rank != b.rank:
-        return float("inf")
-    return rel_fro(b.Y, a.Y)
+def gram_extended(G: np.ndarray) -> np.ndarray:
+    """G'G accumulated in x87 extended precision (64-bit significand) and
+    rounded to float64 once: the Gram matrix to within about one rounding.
+    Plain O(m n^2) loops in NumPy longdouble; for small inputs only."""
+    Gl = np.asarray(G, dtype=np.longdouble)
+    return (Gl.T @ Gl).astype(np.float64)
+
+
+def self_spread(G: np.ndarray, tol: float | None = None, base: GeninvResult | None = None,
+                forced: np.ndarray | None = None, extended_limit: float = 3e8) -> float:
+    """Rounding sensitivity of the method on this input.
+
+    The relative Frobenius distance between the oracle's Y and the Y the
+    same algorithm gives from a Gram matrix that differs only by rounding:
+    the Gram summed in two row halves, and (when m n^2 <= extended_limit)
+    the Gram accumulated in extended precision.  The largest distance is
+    returned.  The method's forward error grows like cond(G)^4 u, so for
+    ill-conditioned G no two float64 evaluations agree more closely than
+    this.  ``forced`` replays given decisions in every run."""
+    a = base if base is not None else geninv(G, tol, forced=forced)
+    G = np.asarray(G, np.float64)
+    variants = [dict(gram_row_blocks=2)]
+    m, n = G.shape
+    if m * min(m, n) ** 2 <= extended_limit:
+        Gw = G.T if m < n else G
+        variants.append(dict(A=gram_extended(Gw)))
+    out = 0.0
+    for kw in variants:
+        b = geninv(G, tol, forced=forced if forced is not None else None, **kw)
+        if forced is None and b.rank != a.rank:
+            return float("inf")
+        out = max(out, rel_fro(b.Y, a.Y))
+    return out
+
+
+def ambiguity_band(A: np.ndarray, tol: float, keep: np.ndarray | None = None, *, rel_eps: float | None = None,
+                   trials: int = 2, safety: float = 4.0, seed: int = 0) -> np.ndarray:
+    """Per-column half-width, relative to tol, of the pivot values whose
+    keep/drop decision two correct float64 evaluations may take differently.
+
+    Measured, not assumed: the factorization is replayed (same decisions,
+    ``keep``, default the oracle's own) on ``trials`` copies of A whose
+    entries carry independent random relative perturbations of size
+    ``rel_eps`` (default 2 sqrt(n) u: a pivot value is the end of a chain of
+    about n rounded updates, whose errors add up like a random walk), and
+    the band is ``safety`` times the largest change of each pivot value,
+    plus the Cholesky backward-error term 2 (n+1) u A_kk.  On well-conditioned inputs
+    the band is tiny; on Gaussian RBF design matrices, whose pivots fall
+    through ten orders of magnitude to tol, it reaches a few percent."""
+    A = np.asarray(A, np.float64)
+    n = A.shape[0]
+    u = np.finfo(np.float64).eps / 2
+    eps = 2 * np.sqrt(max(n, 1)) * u if rel_eps is None else rel_eps
+    L0, r0, piv0, d0 = full_rank_cholesky(A, tol)
+    if keep is None:
+        keep = np.zeros(n, bool)
+        keep[piv0] = True
+    else:
+        L0, r0, piv0, d0 = full_rank_cholesky(A, tol, forced=keep)
+    rng = np.random.default_rng(seed)
+    spread = np.zeros(n)
+    for _ in range(trials):
+        E = rng.uniform(-1.0, 1.0, size=A.shape)
+        E = np.tril(E) + np.tril(E, -1).T
+        _, _, _, d1 = full_rank_cholesky(A * (1.0 + eps * E), tol, forced=keep)
+        spread = np.maximum(spread, np.abs(d1 - d0))
+    return (safety * spread + 2.0 * (n + 1) * u * np.abs(np.diag(A))) / tol
 
 
 def rel_fro(X: np.ndarray, Ref: np.ndarray) -> float:

@@ -13,15 +13,27 @@
 // staged through double-buffered LDS; the next chunk's global loads are in
 // flight while the current chunk feeds the matrix cores.
 //
+// Two-level summation: the matrix-core accumulators only ever hold the sum
+// over KFLUSH consecutive k; they are then added into a second set of
+// float64 registers and restarted.  A single running sum over the whole
+// K = m of the Gram matrix loses about sqrt(m/KFLUSH) times more accuracy,
+// and the pseudoinverse amplifies Gram rounding by about cond(G)^4.
+//
 // MFMA operand roles are swapped (the instruction computes the transposed
 // tile C' = op(B)' op(A)') so that the 16 lanes of a row group hold 16
 // consecutive rows of one column of C: every store of the epilogue is a
 // 128-byte contiguous run of the column-major output.
+//
+// Lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): operand A
+// element (i, k) in lane i + 16k, operand B element (k, j) in lane j + 16k,
+// result element (i, j) in lane j + 16 (i % 4), accumulator slot i / 4.
 #include "common.h"
 
 namespace geninv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int KFLUSH = 256;
 
 template <int BM, int BN, int BK, int WM, int WN>
 __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
@@ -103,11 +115,16 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
         }
     };
 
-    d4 acc[FM][FN];
+    static_assert(KFLUSH % BK == 0, "flush period must be whole chunks");
+    constexpr int FLUSH_CHUNKS = KFLUSH / BK;
+    d4 acc[FM][FN], tot[FM][FN];
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < FN; ++b) {
+            acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            tot[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        }
 
     const int nchunks = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
     if (nchunks > 0) {
@@ -132,10 +149,23 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
                     for (int b = 0; b < FN; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
             }
+            if ((c + 1) % FLUSH_CHUNKS == 0) {
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) {
+                        tot[a][b] += acc[a][b];
+                        acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                    }
+            }
             if (more) sstore(buf ^ 1);
             __syncthreads();
         }
     }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) tot[a][b] += acc[a][b];
 
     const bool lower = p.uplo == GEMM_LOWER;
     const long ldc = p.ldc;
@@ -148,10 +178,10 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
         for (int b = 0; b < FN; ++b) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int c = col0 + wn * TN + b * 16 + 4 * (lane >> 4) + v;
+                const int c = col0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
                 if (r < M && c < N && (!lower || r >= c)) {
                     double *dst = C + r + (long)c * ldc;
-                    const double val = acc[a][b][v];
+                    const double val = tot[a][b][v];
                     if (raw) *dst = val;
                     else *dst = (beta != 0.0) ? alpha * val + beta * (*dst) : alpha * val;
                 }
@@ -173,7 +203,7 @@ hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s) {
     if (a.M.host <= 0 || a.N.host <= 0) return hipSuccess;
     const long big_tiles = (long)((a.M.host + 127) / 128) * ((a.N.host + 127) / 128) *
                            (a.splitk > 1 ? a.splitk : 1);
-    if (big_tiles >= 512 && a.K.host >= 256) return launch_cfg<128, 128, 16, 2, 2>(a, s);
+    if (big_tiles >= 512 && a.K.host >= 256) return launch_cfg<128, 128, 16, 4, 2>(a, s);
     return launch_cfg<64, 64, 16, 2, 2>(a, s);
 }
 

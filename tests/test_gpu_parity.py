@@ -1,12 +1,21 @@
 """GPU parity of libgeninv (float64 form) against the CPU oracle.
 
-Every case feeds identical seeded inputs to both sides.  Integer results
-(rank, pivot columns) must match exactly; floating-point results within the
-float64 tolerance 1e-10 relative Frobenius, except where the input itself
-is so ill-conditioned that two correct float64 evaluations differ by more:
-then the bound is 10x the oracle's own self-spread (the oracle with the Gram
-summed in a different order), and backward-stable quantities (Penrose
-residual, least-squares residual) are checked as well.
+Every case feeds identical seeded inputs to both sides.
+
+Decisions (rank, pivot columns) must match the oracle exactly, with one
+admissible exception: a column whose updated pivot lies within the rounding
+band of tol (oracle.ambiguity_band) may be decided either way by two correct
+float64 evaluations.  Then the first differing decision must lie inside the
+band, the oracle is re-run with the GPU's decisions (replay), every GPU
+decision must agree with the replayed pivot values outside the band, and the
+floating-point results are compared with that replay.
+
+Floating-point results must agree within 1e-10 relative Frobenius, or within
+10x the oracle's own rounding sensitivity on that input (oracle.self_spread)
+when that is larger: the method's forward error grows like cond(G)^4 u, so
+on ill-conditioned inputs no two float64 evaluations agree to 1e-10.  There,
+backward-stable quantities (G Y G = G, least-squares residuals) are checked
+as well.
 """
 import numpy as np
 import pytest
@@ -35,8 +44,8 @@ def down(T):
     return T.detach().cpu().numpy().astype(np.float64)
 
 
-def _print_case(name, **kw):
-    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+def _print_case(label, **kw):
+    print(f"[case] {label} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
 
 
 # ---------------------------------------------------------------------------
@@ -74,6 +83,34 @@ def test_gram_parity(m, n):
     assert np.array_equal(np.tril(Al), np.tril(A))
 
 
+def _mask(piv, n):
+    a = np.zeros(n, bool)
+    a[np.asarray(piv, dtype=np.int64)] = True
+    return a
+
+
+def decisions_or_replay(G, ref, piv_gpu, tol=None):
+    """Oracle result to compare with: ref itself when the GPU took the same
+    decisions, else the oracle replayed with the GPU's decisions after
+    checking that every difference is a legitimate rounding-band case.
+    Returns (result, number of ambiguous decisions)."""
+    n = ref.A.shape[0]
+    acc_o = _mask(ref.piv, n)
+    acc_g = _mask(piv_gpu, n)
+    if np.array_equal(acc_o, acc_g):
+        return ref, 0
+    band = o.ambiguity_band(ref.A, ref.tol, acc_o)
+    k = int(np.nonzero(acc_o != acc_g)[0][0])
+    print(f"  ambiguous decision at column {k}: oracle d/tol={ref.d[k] / ref.tol:.6f}, band={band[k]:.3e}",
+          flush=True)
+    assert abs(ref.d[k] / ref.tol - 1.0) <= band[k]
+    rep = o.geninv(G, tol, forced=acc_g)
+    band = np.maximum(band, o.ambiguity_band(rep.A, rep.tol, acc_g))
+    consistent = ((rep.d > rep.tol) == acc_g) | (np.abs(rep.d / rep.tol - 1.0) <= band)
+    assert consistent.all(), np.nonzero(~consistent)[0][:10]
+    return rep, int((acc_o != acc_g).sum())
+
+
 def _frchol_case(G):
     A = o.gram(G)
     tol = o.paper_tol(A)
@@ -97,18 +134,42 @@ def test_frchol_parity_same_gram(name):
         G, _ = w.lowrank_uv(300, 150, 90, seed=5)
         G[:, [0, 7, 64, 65, 149]] = 0.0
     A, tol, Lr, r, piv, d, res = _frchol_case(G)
-    assert res.rank == r
-    assert np.array_equal(down(res.piv).astype(np.int64), piv)
     assert res.tol == pytest.approx(tol, rel=1e-15)
+    n = A.shape[0]
+    pg = down(res.piv).astype(np.int64)
+    acc_o, acc_g = _mask(piv, n), _mask(pg, n)
+    band = o.ambiguity_band(A, tol, acc_o)
+    if not np.array_equal(acc_o, acc_g):
+        k = int(np.nonzero(acc_o != acc_g)[0][0])
+        print(f"  ambiguous decision at column {k}: d/tol={d[k] / tol:.6f} band={band[k]:.3e}", flush=True)
+        assert abs(d[k] / tol - 1.0) <= band[k]
+        Lr, r, piv, d = o.full_rank_cholesky(A, tol, forced=acc_g)
+        band = np.maximum(band, o.ambiguity_band(A, tol, acc_g))
+        assert (((d > tol) == acc_g) | (np.abs(d / tol - 1.0) <= band)).all()
+    assert res.rank == r
+    assert np.array_equal(pg, piv)
     Lg = down(res.L)
-    assert o.rel_fro(Lg, Lr) <= 1e-9 if name == "rbf_small" else o.rel_fro(Lg, Lr) <= 1e-11
+    # backward error on the kept columns: L[piv] is lower triangular and
+    # L[piv] L[piv]' = A[piv, piv] up to the Cholesky rounding (n+1) u |L||L'|
+    u = np.finfo(np.float64).eps / 2
+    maxdiag = np.abs(np.diag(A)).max()
+    Lp = Lg[piv]
+    assert np.abs(Lp @ Lp.T - A[np.ix_(piv, piv)]).max() <= 4 * (n + 1) * u * maxdiag
+    # forward error: column c of L is computed from its pivot d_c, so its
+    # rounding error grows like n u max(A_kk) / d_c
+    for c in range(r):
+        bound = max(1e-12, 200 * n * u * maxdiag / d[piv[c]])
+        ec = np.linalg.norm(Lg[:, c] - Lr[:, c]) / np.linalg.norm(Lr[:, c])
+        assert ec <= bound, (c, ec, bound)
+    if name != "rbf_small":
+        assert o.rel_fro(Lg, Lr) <= 1e-11
     # exactly zero above each pivot
     for c in range(r):
         assert not Lg[: piv[c], c].any()
-    acc = np.zeros(len(d), bool)
-    acc[piv] = True
+    # every pivot value agrees within the rounding band of the decision
     dg = down(res.d)
-    assert np.allclose(dg[acc], d[acc], rtol=1e-6, atol=0)
+    bad = np.nonzero(np.abs(dg - d) / tol > band)[0]
+    assert bad.size == 0, [(int(k), dg[k] / tol, d[k] / tol, band[k], bool(_mask(piv, n)[k])) for k in bad[:8]]
 
 
 def test_spdinv_parity():
@@ -136,22 +197,27 @@ def test_chain_parity_same_factors():
 # whole method
 # ---------------------------------------------------------------------------
 def _compare(G, tol=None, check_penrose=None):
-    ref = o.geninv(G, tol)
+    """Whole-method parity; returns (relF(Y), bound, oracle result, Y_gpu)."""
+    ref0 = o.geninv(G, tol)
     Y, r, piv = api.geninv(up(G), tol, return_piv=True)
     Yg = down(Y)
+    pg = down(piv).astype(np.int64)
+    assert len(pg) == r
+    ref, amb = decisions_or_replay(G, ref0, pg, tol)
     assert r == ref.rank
-    assert np.array_equal(down(piv).astype(np.int64), ref.piv)
+    forced = _mask(pg, ref.A.shape[0]) if amb else None
+    bound = max(FP64_TOL, 10 * o.self_spread(G, tol, base=ref, forced=forced))
     err = o.rel_fro(Yg, ref.Y)
     if check_penrose is not None:
         assert max(o.penrose_errors(G, Yg).values()) <= check_penrose
-    return err, ref, Yg
+    return err, bound, ref, Yg
 
 
 def test_geninv_c1():
     _print_case("geninv", cfg="c1 200x50 rank 40")
     G, F = w.c1_problem(0)
-    err, ref, Yg = _compare(G)
-    assert err <= FP64_TOL
+    err, bound, ref, Yg = _compare(G)
+    assert bound == FP64_TOL and err <= FP64_TOL
     assert o.rel_fro(Yg, np.linalg.pinv(G, rcond=1e-10)) <= FP64_TOL
 
 
@@ -160,17 +226,17 @@ def test_geninv_c1():
 def test_geninv_lowrank_ragged(m, n, r, seed):
     _print_case("geninv", m=m, n=n, r=r, seed=seed)
     G, _ = w.lowrank_uv(m, n, r, seed)
-    err, ref, Yg = _compare(G)
-    assert err <= FP64_TOL
+    err, bound, ref, Yg = _compare(G)
+    assert err <= bound
 
 
 @pytest.mark.parametrize("n", [64, 256, 512])
 def test_geninv_table1_family_penrose(n):
     _print_case("geninv", cfg=f"table1 n={n}")
     G = w.table1(n, seed=n + 1)
-    err, ref, Yg = _compare(G, check_penrose=2e-10)
+    err, bound, ref, Yg = _compare(G, check_penrose=2e-10)
     assert ref.rank == 7 * n // 8
-    assert err <= FP64_TOL
+    assert bound == FP64_TOL and err <= FP64_TOL
 
 
 def test_geninv_user_tol_and_strictness():
@@ -199,15 +265,16 @@ def test_geninv_nonfinite_reports_error():
     assert e.value.status == -4
     # the context is usable afterwards
     G2, _ = w.c1_problem(0)
-    err, _, _ = _compare(G2)
+    err, bound, _, _ = _compare(G2)
     assert err <= FP64_TOL
 
 
 def test_geninv_duplicate_columns_rejected():
     _print_case("geninv", cfg="rbf duplicates")
     G, _, idx = w.rbf_design(3000, 4, 400, 100, 0.3, seed=12)
-    ref = o.geninv(G)
+    ref0 = o.geninv(G)
     Y, r, piv = api.geninv(up(G), return_piv=True)
+    ref, _ = decisions_or_replay(G, ref0, down(piv).astype(np.int64))
     assert r == ref.rank
     seen, dups = set(), []
     for j, c in enumerate(idx):
@@ -233,31 +300,37 @@ def test_lstsq_ragged(m, n, k, r):
     Wr, ref = o.lstsq(G, F)
     W, rg = api.lstsq(up(G), up(F))
     assert rg == ref.rank
-    assert o.rel_fro(down(W), Wr) <= FP64_TOL
+    bound = max(FP64_TOL, 10 * o.self_spread(G, base=ref))
+    assert o.rel_fro(down(W), Wr) <= bound
 
 
 def test_geninv_c2_full_size():
     """RBF design 8192 x 2048 (256 duplicate centers) at the benchmark's size."""
     _print_case("geninv", cfg="c2 rbf 8192x2048")
     G, F, idx = w.c2_problem()
-    ref = o.geninv(G)
-    spread = o.self_spread(G, base=ref)
-    margins = o.decision_margins(ref)
+    ref0 = o.geninv(G)
     Y, r, piv = api.geninv(up(G), return_piv=True)
     Yg = down(Y)
-    print(f"  oracle r={ref.rank} gpu r={r} margins={margins} self_spread={spread:.3e}", flush=True)
+    pg = down(piv).astype(np.int64)
+    ref, amb = decisions_or_replay(G, ref0, pg)
+    forced = _mask(pg, G.shape[1]) if amb else None
+    spread = o.self_spread(G, base=ref, forced=forced)
+    print(f"  oracle r={ref0.rank} gpu r={r} ambiguous={amb} margins={o.decision_margins(ref0)} "
+          f"self_spread={spread:.3e}", flush=True)
     assert r == ref.rank
-    assert np.array_equal(down(piv).astype(np.int64), ref.piv)
     err = o.rel_fro(Yg, ref.Y)
     print(f"  relF(Y)={err:.3e} bound={max(FP64_TOL, 10 * spread):.3e}", flush=True)
     assert err <= max(FP64_TOL, 10 * spread)
     # backward-stable checks: G Y G = G and least-squares residuals agree
-    GYG = G @ (Yg @ G)
     ref_res = o.rel_fro(G @ (ref.Y @ G), G)
-    assert o.rel_fro(GYG, G) <= max(1e-6, 10 * ref_res)
+    gpu_res = o.rel_fro(G @ (Yg @ G), G)
+    print(f"  relF(GYG-G): gpu {gpu_res:.3e} oracle {ref_res:.3e}", flush=True)
+    assert gpu_res <= max(1e-6, 10 * ref_res)
     Wg, _ = api.lstsq(up(G), up(F))
     Wg = down(Wg)
-    Wr = ref.Y @ F
     rg = np.linalg.norm(G @ Wg - F)
-    rr = np.linalg.norm(G @ Wr - F)
-    assert abs(rg - rr) <= 1e-8 * rr
+    rr = np.linalg.norm(G @ (ref.Y @ F) - F)
+    print(f"  LS residual: gpu {rg:.12e} oracle {rr:.12e}", flush=True)
+    # the GPU's least-squares residual is no larger than the oracle's, up to
+    # the method's own rounding sensitivity on this input
+    assert rg <= rr * (1.0 + 10 * spread)
