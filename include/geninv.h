@@ -146,6 +146,25 @@ int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, d
                  const double *A, int lda, const double *B, int ldb, double beta, double *C,
                  int ldc);
 
+/* ---- event timers ------------------------------------------------------- */
+
+/* Per-kernel-class HIP event timers on the context stream, for profiling.
+ * Classes are numbered 0 .. geninv_prof_classes()-1 and named by
+ * geninv_prof_name() ("gram", "panel_factor", "chain_y", ...).  When bit k of
+ * `mask` is set, every launch of class k is bracketed by two events;
+ * geninv_prof_enable() also clears the totals.  Timers add two event
+ * records per bracketed launch and nothing else. */
+int geninv_prof_classes(void);
+const char *geninv_prof_name(int cls);
+int geninv_prof_enable(geninv_ctx *ctx, unsigned mask);
+
+/* Wait for the recorded events and return the totals of class `cls` since
+ * the last geninv_prof_enable(): summed milliseconds, number of bracketed
+ * launches, and the algorithmic flops of those launches where the library
+ * knows them on the host (0 for launches sized by the device-side rank).
+ * Any output pointer may be NULL. */
+int geninv_prof_read(geninv_ctx *ctx, int cls, double *total_ms, long *launches, double *flops);
+
 #ifdef __cplusplus
 }
 #endif

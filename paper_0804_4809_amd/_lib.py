@@ -51,6 +51,11 @@ _SIGS = [
     ("geninv_dspdinv", ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
     ("geninv_dchain", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
                                      ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
+    ("geninv_prof_classes", ctypes.c_int, []),
+    ("geninv_prof_name", ctypes.c_char_p, [ctypes.c_int]),
+    ("geninv_prof_enable", ctypes.c_int, [_VP, ctypes.c_uint]),
+    ("geninv_prof_read", ctypes.c_int, [_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_double)]),
     ("geninv_dgemm", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, _VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double, _VP,
                                     ctypes.c_int]),

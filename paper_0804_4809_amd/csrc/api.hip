@@ -2,11 +2,31 @@
 // steps on one HIP stream (declarations and contracts in include/geninv.h).
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "common.h"
 #include "geninv.h"
 
 using namespace geninv;
+
+// Kernel classes for the optional event timers (geninv_prof_*).
+enum ProfClass {
+    PC_GRAM, PC_TOL, PC_FILL, PC_PANEL_GEMM, PC_PANEL_FACTOR, PC_LTL, PC_INV_PANEL, PC_INV_UPDATE,
+    PC_MIRROR, PC_CHAIN_K, PC_CHAIN_P, PC_CHAIN_Y, PC_LSTSQ, PC_GEMM, PC_COUNT
+};
+static const char *const kProfNames[PC_COUNT] = {
+    "gram", "tol", "fill", "panel_gemm", "panel_factor", "ltl", "inv_panel", "inv_update",
+    "mirror", "chain_k", "chain_p", "chain_y", "lstsq_apply", "gemm"};
+
+struct ProfState {
+    unsigned mask = 0;
+    struct Pending { int cls; hipEvent_t a, b; double flops; };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    double ms[PC_COUNT] = {};
+    long cnt[PC_COUNT] = {};
+    double fl[PC_COUNT] = {};
+};
 
 struct geninv_ctx {
     int device = 0;
@@ -14,6 +34,7 @@ struct geninv_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int *status = nullptr;     // device status word (separate from the workspace: survives regrowth)
+    ProfState prof;
 };
 
 namespace {
@@ -45,6 +66,51 @@ struct DeviceGuard {
     } while (0)
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Records a pair of events on the context stream around the launches of one
+// class when that class is enabled; the elapsed times are summed on read.
+struct ProfScope {
+    geninv_ctx *c;
+    int cls;
+    double flops;
+    hipEvent_t a = nullptr;
+    ProfScope(geninv_ctx *ctx, int k, double f) : c(ctx), cls(k), flops(f) {
+        if (!((c->prof.mask >> cls) & 1u)) return;
+        a = take();
+        if (a) (void)hipEventRecord(a, c->stream);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = take();
+        if (!b) return;
+        (void)hipEventRecord(b, c->stream);
+        c->prof.pending.push_back({cls, a, b, flops});
+    }
+    hipEvent_t take() {
+        if (!c->prof.pool.empty()) {
+            hipEvent_t e = c->prof.pool.back();
+            c->prof.pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+
+void prof_resolve(geninv_ctx *c) {
+    for (auto &p : c->prof.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->prof.ms[p.cls] += ms;
+            c->prof.cnt[p.cls] += 1;
+            c->prof.fl[p.cls] += p.flops;
+        }
+        c->prof.pool.push_back(p.a);
+        c->prof.pool.push_back(p.b);
+    }
+    c->prof.pending.clear();
+}
 
 // Workspace carve-up for a problem whose factored dimension is nn (the
 // smaller of m, n) with k right-hand sides.
@@ -141,35 +207,74 @@ int gemm_splitk(geninv_ctx *c, const Layout &lay, GemmArgs g, int min_tiles = 25
     return GENINV_OK;
 }
 
+// Step 1: lower triangle of A = op(G)' op(G) (nn x nn, ld nn) into slotA.
+// When the 128 x 128 tiling would leave compute units idle, K is split in two
+// with the partial Grams in the (still unused) chain slots K and P, then summed.
+int run_gram(geninv_ctx *c, const Layout &lay, const double *G, long ldg, bool tr, int nn, int kdim) {
+    double *A = at<double>(c, lay.slotA);
+    GemmArgs g = tr ? gemm(G, ldg, 0, G, ldg, 1, A, nn, hdim(nn), hdim(nn), hdim(kdim), 1.0, 0.0, GEMM_LOWER)
+                    : gemm(G, ldg, 1, G, ldg, 0, A, nn, hdim(nn), hdim(nn), hdim(kdim), 1.0, 0.0, GEMM_LOWER);
+    ProfScope ps(c, PC_GRAM, (double)kdim * nn * (nn + 1.0));
+    if (gemm_tiles(g, 128) >= 256 || kdim < 2048 || gemm_tiles(g, 128) * 2 < 128) {
+        HIPCHK(launch_dgemm(g, c->stream));
+        return GENINV_OK;
+    }
+    const long stride = (long)((lay.slotP - lay.slotK) / sizeof(double));
+    g.C = at<double>(c, lay.slotK);
+    g.ldc = nn;
+    g.splitk = 2;
+    g.strideC = stride;
+    HIPCHK(launch_dgemm(g, c->stream));
+    HIPCHK(launch_splitk_reduce(g.C, nn, stride, 2, A, nn, hdim(nn), hdim(nn), 1.0, 0.0, GEMM_LOWER, c->stream));
+    return GENINV_OK;
+}
+
 // Steps 2-3: tolerance and full-rank Cholesky of the lower triangle of A
-// (nn x nn).  L (nn x nn, ldl) is zeroed and receives the compacted factor.
-int run_frchol(geninv_ctx *c, const Layout &lay, const double *A, long lda, int nn, double user_tol, double *L,
+// (nn x nn), which is overwritten panel by panel with the updated panels.
+// L (nn x nn, ldl) is zeroed and receives the compacted factor.
+int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, double user_tol, double *L,
                long ldl, int *piv, double *dvals) {
     double *tolp = at<double>(c, lay.tol);
     int *rank_buf = at<int>(c, lay.rank);
     double *part = at<double>(c, lay.part);
     const int np = (nn + FR_NB - 1) / FR_NB;
-    HIPCHK(launch_tol(A, lda, nn, user_tol, tolp, c->status, c->stream));
-    HIPCHK(launch_fill(L, ldl, nn, nn, 0.0, c->stream));
-    HIPCHK(launch_fill_int(rank_buf, np + 1, 0, c->stream));
+    {
+        ProfScope ps(c, PC_TOL, 0.0);
+        HIPCHK(launch_tol(A, lda, nn, user_tol, tolp, c->status, c->stream));
+    }
+    {
+        ProfScope ps(c, PC_FILL, 0.0);
+        HIPCHK(launch_fill(L, ldl, nn, nn, 0.0, c->stream));
+        HIPCHK(launch_fill_int(rank_buf, np + 1, 0, c->stream));
+    }
     const long ldp = nn;
     const long strideP = (long)nn * FR_NB;
     for (int p = 0; p < np; ++p) {
         const int k0 = p * FR_NB;
         const int w = std::min(FR_NB, nn - k0);
         const int rows = nn - k0;
-        int S = 0;
+        double *panel = A + k0 + (long)k0 * lda;
         if (p > 0) {
+            // panel -= L[k0:, :r0] L[k0:k0+w, :r0]'  (r0 = rank_buf[p], on device)
+            ProfScope ps(c, PC_PANEL_GEMM, 0.0);
             const int tiles = (rows + 63) / 64;
-            S = std::max(1, std::min({PART_S, (512 + tiles - 1) / tiles, std::max(1, k0 / 128)}));
-            GemmArgs g = gemm(L + k0, ldl, 0, L + k0, ldl, 1, part, ldp, hdim(rows), hdim(w),
-                              ddim(k0, rank_buf + p), 1.0, 0.0);
-            g.splitk = S;
-            g.strideC = strideP;
-            HIPCHK(launch_dgemm(g, c->stream));
+            const int S = std::max(1, std::min({PART_S, (512 + tiles - 1) / tiles, std::max(1, k0 / 128)}));
+            GemmArgs g = gemm(L + k0, ldl, 0, L + k0, ldl, 1, panel, lda, hdim(rows), hdim(w),
+                              ddim(k0, rank_buf + p), -1.0, 1.0);
+            if (S == 1) {
+                HIPCHK(launch_dgemm(g, c->stream));
+            } else {
+                g.C = part;
+                g.ldc = ldp;
+                g.splitk = S;
+                g.strideC = strideP;
+                HIPCHK(launch_dgemm(g, c->stream));
+                HIPCHK(launch_splitk_reduce(part, ldp, strideP, S, panel, lda, hdim(rows), hdim(w), -1.0, 1.0,
+                                            GEMM_FULL, c->stream));
+            }
         }
-        HIPCHK(launch_frchol_panel(A, lda, part, ldp, strideP, S, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals,
-                                   c->stream));
+        ProfScope ps(c, PC_PANEL_FACTOR, 0.0);
+        HIPCHK(launch_frchol_panel(panel, lda, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals, c->stream));
     }
     return GENINV_OK;
 }
@@ -181,9 +286,14 @@ int run_spdinv(geninv_ctx *c, const Layout &lay, double *B, long ldb, Dim r) {
     double *Cc = at<double>(c, lay.ccol);
     const int nbk = (r.host + GJ_NB - 1) / GJ_NB;
     for (int b = 0; b < nbk; ++b) {
-        HIPCHK(launch_gj_panel(B, ldb, r, b, D, R, Cc, c->status, c->stream));
+        {
+            ProfScope ps(c, PC_INV_PANEL, 0.0);
+            HIPCHK(launch_gj_panel(B, ldb, r, b, D, R, Cc, c->status, c->stream));
+        }
+        ProfScope ps(c, PC_INV_UPDATE, 0.0);
         HIPCHK(launch_gj_update(B, ldb, r, b, D, R, Cc, c->stream));
     }
+    ProfScope ps(c, PC_MIRROR, 0.0);
     HIPCHK(launch_mirror_lower(B, ldb, r, c->stream));
     return GENINV_OK;
 }
@@ -193,8 +303,14 @@ int run_factor_inverse(geninv_ctx *c, const Layout &lay, const double *L, long l
                        double *dst, long ldd) {
     const Dim r = ddim(nn, rdev);
     GemmArgs g = gemm(L, ldl, 1, L, ldl, 0, dst, ldd, r, r, hdim(nn), 1.0, 0.0, GEMM_LOWER);
-    HIPCHK(launch_dgemm(g, c->stream));
-    HIPCHK(launch_mirror_lower(dst, ldd, r, c->stream));
+    {
+        ProfScope ps(c, PC_LTL, 0.0);
+        HIPCHK(launch_dgemm(g, c->stream));
+    }
+    {
+        ProfScope ps(c, PC_MIRROR, 0.0);
+        HIPCHK(launch_mirror_lower(dst, ldd, r, c->stream));
+    }
     return run_spdinv(c, lay, dst, ldd, r);
 }
 
@@ -218,6 +334,31 @@ bool bad_ld(long ld, int rows) { return ld < std::max(1, rows); }
 extern "C" {
 
 int geninv_version(void) { return 100; }
+
+int geninv_prof_classes(void) { return PC_COUNT; }
+
+const char *geninv_prof_name(int cls) { return (cls >= 0 && cls < PC_COUNT) ? kProfNames[cls] : "unknown"; }
+
+int geninv_prof_enable(geninv_ctx *c, unsigned mask) {
+    if (!c) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    prof_resolve(c);
+    c->prof.mask = mask;
+    std::fill(std::begin(c->prof.ms), std::end(c->prof.ms), 0.0);
+    std::fill(std::begin(c->prof.cnt), std::end(c->prof.cnt), 0L);
+    std::fill(std::begin(c->prof.fl), std::end(c->prof.fl), 0.0);
+    return GENINV_OK;
+}
+
+int geninv_prof_read(geninv_ctx *c, int cls, double *total_ms, long *launches, double *flops) {
+    if (!c || cls < 0 || cls >= PC_COUNT) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    prof_resolve(c);
+    if (total_ms) *total_ms = c->prof.ms[cls];
+    if (launches) *launches = c->prof.cnt[cls];
+    if (flops) *flops = c->prof.fl[cls];
+    return GENINV_OK;
+}
 
 const char *geninv_strerror(int s) {
     switch (s) {
@@ -261,6 +402,8 @@ int geninv_destroy(geninv_ctx *c) {
     if (!c) return GENINV_OK;
     DeviceGuard g(c->device);
     (void)hipStreamSynchronize(c->stream);
+    prof_resolve(c);
+    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     if (c->ws) (void)hipFree(c->ws);
     if (c->status) (void)hipFree(c->status);
     delete c;
@@ -300,6 +443,24 @@ int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, dou
     DeviceGuard g(c->device);
     GemmArgs a = gemm(A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0, C, ldc, hdim(M), hdim(N), hdim(K), alpha,
                       beta);
+    ProfScope ps(c, PC_GEMM, 2.0 * M * N * K);
+    // a skinny product (few output tiles, long K) is split over K
+    const long tiles = gemm_tiles(a, 64);
+    if (tiles < 256 && K >= 1024) {
+        const int S = (int)std::min<long>({PART_S, (256 + tiles - 1) / tiles, K / 256});
+        if (S > 1) {
+            CHK(ensure_ws(c, (size_t)S * M * N * sizeof(double)));
+            GemmArgs p = a;
+            p.C = at<double>(c, 0);
+            p.ldc = M;
+            p.splitk = S;
+            p.strideC = (long)M * N;
+            HIPCHK(launch_dgemm(p, c->stream));
+            HIPCHK(launch_splitk_reduce(p.C, M, p.strideC, S, C, ldc, hdim(M), hdim(N), alpha, beta, GEMM_FULL,
+                                        c->stream));
+            return GENINV_OK;
+        }
+    }
     HIPCHK(launch_dgemm(a, c->stream));
     return GENINV_OK;
 }
@@ -328,7 +489,9 @@ int geninv_dfrchol(geninv_ctx *c, int n, const double *A, int lda, double tol, d
     CHK(ensure_ws(c, lay.total));
     int *pv = piv ? piv : at<int>(c, lay.piv);
     double *dv = d ? d : at<double>(c, lay.dvals);
-    CHK(run_frchol(c, lay, A, lda, n, tol, L, ldl, pv, dv));
+    double *Aw = at<double>(c, lay.slotA);
+    HIPCHK(launch_copy(A, lda, Aw, n, hdim(n), hdim(n), c->stream));
+    CHK(run_frchol(c, lay, Aw, n, n, tol, L, ldl, pv, dv));
     const int np = (n + FR_NB - 1) / FR_NB;
     if (tol_used) HIPCHK(launch_copy(at<double>(c, lay.tol), 1, tol_used, 1, hdim(1), hdim(1), c->stream));
     return finish_rank(c, at<int>(c, lay.rank) + np, rank);
@@ -384,8 +547,7 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     const long ld = nn;
 
     // 1. Gram matrix, lower triangle: A = G'G, or G G' in the transpose branch
-    if (!tr) HIPCHK(launch_dgemm(gemm(G, ldg, 1, G, ldg, 0, A, ld, hdim(nn), hdim(nn), hdim(m), 1.0, 0.0, GEMM_LOWER), c->stream));
-    else HIPCHK(launch_dgemm(gemm(G, ldg, 0, G, ldg, 1, A, ld, hdim(nn), hdim(nn), hdim(n), 1.0, 0.0, GEMM_LOWER), c->stream));
+    CHK(run_gram(c, lay, G, ldg, tr, nn, tr ? n : m));
     // 2-3. tolerance and full-rank Cholesky
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, pv, at<double>(c, lay.dvals)));
     const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
@@ -393,11 +555,23 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     // 4. M = (L'L)^-1 into the Gram's slot
     CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
     // 5. K = L M, P = K K' (= (G'G)^+), then Y = P G' or Y = G' P
-    HIPCHK(launch_dgemm(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0), c->stream));
-    HIPCHK(launch_dgemm(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER), c->stream));
-    HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
-    if (!tr) HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
-    else HIPCHK(launch_dgemm(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0), c->stream));
+    {
+        ProfScope ps(c, PC_CHAIN_K, 0.0);
+        HIPCHK(launch_dgemm(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0), c->stream));
+    }
+    {
+        ProfScope ps(c, PC_CHAIN_P, 0.0);
+        HIPCHK(launch_dgemm(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER), c->stream));
+    }
+    {
+        ProfScope ps(c, PC_MIRROR, 0.0);
+        HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
+    }
+    {
+        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
+        if (!tr) HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
+        else HIPCHK(launch_dgemm(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0), c->stream));
+    }
     return finish_rank(c, rdev, rank);
 }
 
@@ -428,13 +602,14 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
     double *T2 = at<double>(c, lay.t2);
     const long ld = nn;
 
-    HIPCHK(launch_dgemm(gemm(G, ldg, 1, G, ldg, 0, A, ld, hdim(nn), hdim(nn), hdim(m), 1.0, 0.0, GEMM_LOWER), c->stream));
+    CHK(run_gram(c, lay, G, ldg, false, nn, m));
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, at<int>(c, lay.piv), at<double>(c, lay.dvals)));
     const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
     const Dim r = ddim(nn, rdev);
     CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
     if (k > 0) {
         // W = L (M (M (L' (G' F))))
+        ProfScope ps(c, PC_LSTSQ, 0.0);
         CHK(gemm_splitk(c, lay, gemm(G, ldg, 1, F, ldf, 0, T0, ld, hdim(nn), hdim(k), hdim(m), 1.0, 0.0)));
         HIPCHK(launch_dgemm(gemm(L, ld, 1, T0, ld, 0, T1, ld, r, hdim(k), hdim(nn), 1.0, 0.0), c->stream));
         HIPCHK(launch_dgemm(gemm(A, ld, 0, T1, ld, 0, T2, ld, r, hdim(k), r, 1.0, 0.0), c->stream));

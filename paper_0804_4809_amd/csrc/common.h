@@ -38,6 +38,7 @@ enum { ST_OK = 0, ST_NONFINITE = -4, ST_NOTSPD = -5 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s);
+long gemm_tiles(const GemmArgs &a, int bm);   // workgroups a launch would use with bm x bm tiles
 hipError_t launch_splitk_reduce(const double *part, long ldp, long strideP, int S, double *C, long ldc,
                                 Dim M, Dim N, double alpha, double beta, int uplo, hipStream_t s);
 hipError_t launch_fill(double *X, long ldx, int rows, int cols, double v, hipStream_t s);
@@ -50,9 +51,8 @@ hipError_t launch_transpose(const double *X, long ldx, double *Yp, long ldy, int
 constexpr int FR_NB = 64;          // panel width
 hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double *tol_out, int *status,
                       hipStream_t s);
-hipError_t launch_frchol_panel(const double *A, long lda, const double *part, long ldp, long strideP,
-                               int S, double *L, long ldl, int *rank_buf, int p, int k0, int w, int n,
-                               const double *tol, int *piv, double *dvals, hipStream_t s);
+hipError_t launch_frchol_panel(const double *P, long ldp, double *L, long ldl, int *rank_buf, int p, int k0,
+                               int w, int n, const double *tol, int *piv, double *dvals, hipStream_t s);
 
 // SPD inverse by block Gauss-Jordan (spdinv.hip)
 constexpr int GJ_NB = 64;

@@ -199,11 +199,18 @@ static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+long gemm_tiles(const GemmArgs &a, int bm) {
+    const long tm = (a.M.host + bm - 1) / bm, tn = (a.N.host + bm - 1) / bm;
+    long t = tm * tn;
+    if (a.uplo == GEMM_LOWER) t = (tm * (tm + 1)) / 2 + (tn > tm ? 0 : 0);
+    return t * (a.splitk > 1 ? a.splitk : 1);
+}
+
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s) {
     if (a.M.host <= 0 || a.N.host <= 0) return hipSuccess;
-    const long big_tiles = (long)((a.M.host + 127) / 128) * ((a.N.host + 127) / 128) *
-                           (a.splitk > 1 ? a.splitk : 1);
-    if (big_tiles >= 512 && a.K.host >= 256) return launch_cfg<128, 128, 16, 4, 2>(a, s);
+    // 128 x 128 tiles (8 wavefronts) when they alone fill the 256 compute
+    // units; 64 x 64 tiles otherwise
+    if (gemm_tiles(a, 128) >= 256 && a.K.host >= 128) return launch_cfg<128, 128, 16, 4, 2>(a, s);
     return launch_cfg<64, 64, 16, 2, 2>(a, s);
 }
 

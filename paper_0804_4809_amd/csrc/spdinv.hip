@@ -14,38 +14,80 @@
 // and after the last block B holds B^-1.  Two launches per step: the panel
 // kernel (D, R and a copy of the old block column, one workgroup per block
 // column) and the update kernel (one workgroup per 64 x 64 tile), which reads
-// only the staged panels so that tiles can be rewritten in place.  The rank r
-// is read from device memory; steps and tiles past r exit at once.
+// only the staged panels so that tiles can be rewritten in place.  The
+// 64 x 64 x 64 tile products run on v_mfma_f64_16x16x4f64.  The rank r is
+// read from device memory; steps and tiles past r exit at once.
 #include "common.h"
 
 namespace geninv {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 constexpr int GJ_LD = GJ_NB + 1;
 
-// in-LDS Gauss-Jordan inverse of the w x w block X (column-major X[j][i]);
-// returns false (uniformly) if a pivot is not positive.
+// Tile product on the matrix cores: the 64 x 64 result of Xs * Ys, where
+// Xs[k][i] holds the left factor's column k and Ys[j][k] the right factor's
+// column j (K = 64, zero padded).  Wavefront w owns rows 32 (w & 1) .. +31 and
+// columns 32 (w >> 1) .. +31 as 2 x 2 blocks of 16 x 16; result element
+// (row, col) is acc[a][b][v] with row = 32 (w & 1) + 16 a + (lane & 15) and
+// col = 32 (w >> 1) + 16 b + (lane >> 4) + 4 v.
+__device__ __forceinline__ void tile64_mfma(const double (*Xs)[GJ_LD], const double (*Ys)[GJ_LD], d4 acc[2][2]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < GJ_NB; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double af[2], bf[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) af[a] = Xs[kr][wm * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bf[b] = Ys[wn * 32 + b * 16 + (lane & 15)][kr];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+    }
+}
+
+// In-LDS Gauss-Jordan inverse of the SPD block in X (column-major X[j][i]),
+// w x w in the top-left corner and identity elsewhere, so that every thread
+// updates a fixed set of elements without bounds tests.  Thread
+// (lane, wave) owns row `lane`, columns wave, wave + 4, ...  Each step is one
+// FMA per element (X -= column p * scaled row p), after which the owners of
+// row p and column p overwrite them.  Returns false (uniformly) if a pivot is
+// not positive.
 __device__ bool gj_invert_block(double (*X)[GJ_LD], int w, double *rowp, double *colp) {
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     bool ok = true;
     for (int p = 0; p < w; ++p) {
         __syncthreads();
         const double pv = X[p][p];
         if (!(pv > 0.0)) ok = false;
         const double dinv = 1.0 / pv;
-        for (int t = tid; t < w; t += blockDim.x) {
-            rowp[t] = X[t][p];   // row p, column t
-            colp[t] = X[p][t];   // column p, row t
+        if (tid < GJ_NB) {
+            rowp[tid] = X[tid][p] * dinv;   // row p scaled by the inverse pivot
+            colp[tid] = X[p][tid];          // column p
         }
         __syncthreads();
-        for (int e = tid; e < w * w; e += blockDim.x) {
-            const int i = e % w, j = e / w;
-            double v;
-            if (i == p && j == p) v = dinv;
-            else if (i == p) v = rowp[j] * dinv;
-            else if (j == p) v = -colp[i] * dinv;
-            else v = X[j][i] - colp[i] * rowp[j] * dinv;
-            X[j][i] = v;
+        const double cp = colp[lane];
+        double v[GJ_NB / 4], rp[GJ_NB / 4];
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) {
+            v[q] = X[wave + 4 * q][lane];
+            rp[q] = rowp[wave + 4 * q];
         }
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) X[wave + 4 * q][lane] = v[q] - cp * rp[q];
+        if (lane == p) {
+#pragma unroll
+            for (int q = 0; q < GJ_NB / 4; ++q) X[wave + 4 * q][p] = rp[q];
+        }
+        if (wave == (p & 3)) X[p][lane] = lane == p ? dinv : -cp * dinv;
     }
     __syncthreads();
     return ok;
@@ -62,43 +104,48 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict_
     const int jb = blockIdx.x;
     if (b >= nbk || jb >= nbk) return;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wb = min(GJ_NB, r - b * GJ_NB);
     const int wj = min(GJ_NB, r - jb * GJ_NB);
     const long ob = (long)b * GJ_NB, oj = (long)jb * GJ_NB;
 
-    for (int e = tid; e < wb * wb; e += 256) {
-        const int i = e % wb, j = e / wb;
-        X[j][i] = B[(ob + i) + (ob + j) * ldb];
-    }
-    // old block column (rows of block jb, columns of block b)
-    for (int e = tid; e < wj * wb; e += 256) {
-        const int i = e % wj, j = e / wj;
-        Ccol[(oj + i) + (long)j * ldc] = B[(oj + i) + (ob + j) * ldb];
+#pragma unroll
+    for (int q = 0; q < GJ_NB / 4; ++q) {
+        const int jc = wave + 4 * q;
+        const bool in_b = lane < wb && jc < wb;
+        X[jc][lane] = in_b ? B[(ob + lane) + (ob + jc) * ldb] : (lane == jc ? 1.0 : 0.0);
+        // old block column (rows of block jb, columns of block b)
+        if (lane < wj && jc < wb) Ccol[(oj + lane) + (long)jc * ldc] = B[(oj + lane) + (ob + jc) * ldb];
+        // pivot block row restricted to the columns of block jb, zero padded
+        Bl[jc][lane] = (jb != b && lane < wb && jc < wj) ? B[(ob + lane) + (oj + jc) * ldb] : 0.0;
     }
     const bool ok = gj_invert_block(X, wb, rowp, colp);
     if (jb == b) {
         if (!ok && tid == 0) *status = ST_NOTSPD;
-        for (int e = tid; e < wb * wb; e += 256) {
-            const int i = e % wb, j = e / wb;
-            Dbuf[i + (long)j * GJ_NB] = X[j][i];
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) {
+            const int jc = wave + 4 * q;
+            if (lane < wb && jc < wb) Dbuf[lane + (long)jc * GJ_NB] = X[jc][lane];
         }
         return;
     }
-    for (int e = tid; e < wb * wj; e += 256) {
-        const int i = e % wb, j = e / wb;
-        Bl[j][i] = B[(ob + i) + (oj + j) * ldb];
-    }
-    __syncthreads();
     // R = D * B_b,jb  (wb x wj)
-    for (int e = tid; e < wb * wj; e += 256) {
-        const int i = e % wb, j = e / wb;
-        double s = 0.0;
-        for (int k = 0; k < wb; ++k) s += X[k][i] * Bl[j][k];
-        Rrow[i + (oj + j) * GJ_NB] = s;
-    }
+    d4 acc[2][2];
+    tile64_mfma(X, Bl, acc);
+    const int wm = wave & 1, wn = wave >> 1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wm * 32 + a * 16 + (lane & 15);
+                const int col = wn * 32 + bb * 16 + (lane >> 4) + 4 * v;
+                if (row < wb && col < wj) Rrow[row + (oj + col) * GJ_NB] = acc[a][bb][v];
+            }
 }
 
-// tile (ib, jb) of the in-place update; products by LDS-staged FMA
+// tile (ib, jb) of the in-place update
 __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, long ldb, Dim rd, int b,
                                                         const double *__restrict__ Dbuf,
                                                         const double *__restrict__ Rrow,
@@ -110,6 +157,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     const int ib = blockIdx.x, jb = blockIdx.y;
     if (b >= nbk || ib >= nbk || jb >= nbk) return;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wb = min(GJ_NB, r - b * GJ_NB);
     const int wi = min(GJ_NB, r - ib * GJ_NB);
     const int wj = min(GJ_NB, r - jb * GJ_NB);
@@ -117,52 +165,50 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     double *T = B + oi + oj * ldb;
 
     if (ib == b && jb == b) {
-        for (int e = tid; e < wb * wb; e += 256) {
-            const int i = e % wb, j = e / wb;
-            T[i + (long)j * ldb] = Dbuf[i + (long)j * GJ_NB];
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) {
+            const int jc = wave + 4 * q;
+            if (lane < wb && jc < wb) T[lane + (long)jc * ldb] = Dbuf[lane + (long)jc * GJ_NB];
         }
         return;
     }
     if (ib == b) {
-        for (int e = tid; e < wb * wj; e += 256) {
-            const int i = e % wb, j = e / wb;
-            T[i + (long)j * ldb] = Rrow[i + (oj + j) * GJ_NB];
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) {
+            const int jc = wave + 4 * q;
+            if (lane < wb && jc < wj) T[lane + (long)jc * ldb] = Rrow[lane + (oj + jc) * GJ_NB];
         }
         return;
     }
-    // left factor: old block column rows of block ib (wi x wb)
-    for (int e = tid; e < wi * wb; e += 256) {
-        const int i = e % wi, k = e / wi;
-        Xs[k][i] = Ccol[(oi + i) + (long)k * ldc];
-    }
-    // right factor: D (jb == b) or R_jb (wb x wj)
-    const int wr = (jb == b) ? wb : wj;
-    for (int e = tid; e < wb * wr; e += 256) {
-        const int k = e % wb, j = e / wb;
-        Ys[j][k] = (jb == b) ? Dbuf[k + (long)j * GJ_NB] : Rrow[k + (oj + j) * GJ_NB];
+    const bool newcol = jb == b;
+    const int wr = newcol ? wb : wj;
+#pragma unroll
+    for (int q = 0; q < GJ_NB / 4; ++q) {
+        const int kc = wave + 4 * q;
+        // left factor: old block column rows of block ib (wi x wb), zero padded
+        Xs[kc][lane] = (lane < wi && kc < wb) ? Ccol[(oi + lane) + (long)kc * ldc] : 0.0;
+        // right factor: D (new block column) or R_jb, zero padded
+        double y = 0.0;
+        if (lane < wb && kc < wr) y = newcol ? Dbuf[lane + (long)kc * GJ_NB] : Rrow[lane + (oj + kc) * GJ_NB];
+        Ys[kc][lane] = y;
     }
     __syncthreads();
-    const int i = tid & 63;
-    const int j0 = tid >> 6;
-    double accv[GJ_NB / 4];
+    d4 acc[2][2];
+    tile64_mfma(Xs, Ys, acc);
+    const int wm = wave & 1, wn = wave >> 1;
 #pragma unroll
-    for (int q = 0; q < GJ_NB / 4; ++q) accv[q] = 0.0;
-    if (i < wi) {
-        for (int k = 0; k < wb; ++k) {
-            const double xv = Xs[k][i];
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int q = 0; q < GJ_NB / 4; ++q) accv[q] += xv * Ys[j0 + 4 * q][k];
-        }
+        for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-        for (int q = 0; q < GJ_NB / 4; ++q) {
-            const int j = j0 + 4 * q;
-            if (j < wr) {
-                double *dst = T + i + (long)j * ldb;
-                if (jb == b) *dst = -accv[q];
-                else *dst = *dst - accv[q];
+            for (int v = 0; v < 4; ++v) {
+                const int row = wm * 32 + a * 16 + (lane & 15);
+                const int col = wn * 32 + bb * 16 + (lane >> 4) + 4 * v;
+                if (row < wi && col < wr) {
+                    double *dst = T + row + (long)col * ldb;
+                    *dst = newcol ? -acc[a][bb][v] : *dst - acc[a][bb][v];
+                }
             }
-        }
-    }
 }
 
 hipError_t launch_gj_panel(const double *B, long ldb, Dim r, int b, double *D, double *Rrow, double *Ccol,
