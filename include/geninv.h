@@ -146,6 +146,39 @@ int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, d
                  const double *A, int lda, const double *B, int ldb, double beta, double *C,
                  int ldc);
 
+/* ---- mixed precision: error-free split products on bfloat16 matrix cores - */
+
+/* Y = G^+ (Theorem 1) with the two dense products on the bfloat16 matrix
+ * cores as exact products of 8-bit operand slices (the error-free splitting of
+ * Ozaki, Ogita, Oishi and Rump): every column of G (every row of P and G in the
+ * chain) is scaled by a power of two and cut into `slices` signed 8-bit
+ * integer slices; every pair of slices is multiplied exactly (float32
+ * accumulation over chunks of 256, float64 totals).  The Gram matrix is thus
+ * the exactly rounded Gram matrix of the 8*slices-bit representation of G.
+ * The tolerance, the pivot decisions, the Cholesky factor and (L'L)^-1 are
+ * float64, as in geninv_dgeninv.
+ *   slices        1..6, slices of G in the Gram matrix (4: 32-bit representation)
+ *   chain_slices  0..6, slices of P and G in Y = P G'; 0 evaluates it in float64
+ *   ns_steps      >= 0 Newton-Schulz steps X <- X (2I - G X), taken in the
+ *                 factored form P <- 2P - P A P (X = P G') in float64 with the
+ *                 sliced Gram matrix A
+ * Other arguments as in geninv_dgeninv.  Requires m >= n (ENOTSUP otherwise). */
+int geninv_mixed(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double tol, int slices,
+                 int chain_slices, int ns_steps, double *Y, int ldy, int *rank, int *piv);
+
+/* The slicing step on its own, for parity testing.  transposed == 0: column
+ * exponents e[cols] and planes[t][i + j*ldp] = slice t of X(i, j) (ldp >= rows,
+ * rows rows..ldp-1 zero).  transposed != 0: row exponents e[rows] and
+ * planes[t][k + i*ldp] = slice t of X(i, k) (ldp >= cols, columns cols..ldp-1
+ * zero).  planes: DEVICE bfloat16 array of slices*ldp*(cols or rows) elements;
+ * e: DEVICE int array. */
+int geninv_bslice(geninv_ctx *ctx, int rows, int cols, const double *X, int ldx, int slices,
+                  int transposed, void *planes, int ldp, int *e);
+
+/* Lower triangle of the sliced Gram matrix G_s'G_s (n x n, lda >= n), as used by
+ * geninv_mixed, for parity testing. */
+int geninv_bgram(geninv_ctx *ctx, int m, int n, const double *G, int ldg, int slices, double *A, int lda);
+
 /* ---- event timers ------------------------------------------------------- */
 
 /* Per-kernel-class HIP event timers on the context stream, for profiling.

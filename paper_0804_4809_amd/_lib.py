@@ -51,6 +51,12 @@ _SIGS = [
     ("geninv_dspdinv", ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
     ("geninv_dchain", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
                                      ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
+    ("geninv_mixed", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _c_int_p, _VP]),
+    ("geninv_bslice", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _VP, ctypes.c_int, _VP]),
+    ("geninv_bgram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int, _VP,
+                                    ctypes.c_int]),
     ("geninv_prof_classes", ctypes.c_int, []),
     ("geninv_prof_name", ctypes.c_char_p, [ctypes.c_int]),
     ("geninv_prof_enable", ctypes.c_int, [_VP, ctypes.c_uint]),

@@ -84,6 +84,51 @@ def geninv(G: torch.Tensor, tol: float | None = None, *, return_piv: bool = Fals
     return Y, r.value
 
 
+def mixed(G: torch.Tensor, tol: float | None = None, slices: int = 4, chain_slices: int = 4, ns_steps: int = 0,
+          *, return_piv: bool = False):
+    """Y = G^+ with the Gram matrix and Y = P G' as exact sliced bfloat16
+    products (geninv_mixed); pivots and (L'L)^-1 in float64.  m >= n."""
+    _dev(G, "G")
+    m, n = G.shape
+    Gc, ldg = colmajor(G)
+    Y = empty_colmajor(n, m, G.device)
+    piv = torch.empty(max(1, min(m, n)), dtype=torch.int32, device=G.device)
+    r = ctypes.c_int(0)
+    st = load().geninv_mixed(_ctx(G.device), m, n, _p(Gc), ldg, float(tol or 0.0), int(slices), int(chain_slices),
+                             int(ns_steps), _p(Y), max(1, n), ctypes.byref(r), _p(piv))
+    _check(st, "geninv_mixed")
+    if return_piv:
+        return Y, r.value, piv[: r.value]
+    return Y, r.value
+
+
+def bslice(X: torch.Tensor, slices: int = 4, transposed: bool = False):
+    """(planes, exponents): the 8-bit slices of X by column (or by row,
+    transposed storage) as bfloat16 planes, and the exponents."""
+    _dev(X, "X")
+    rows, cols = X.shape
+    Xc, ldx = colmajor(X)
+    inner = cols if transposed else rows
+    outer = rows if transposed else cols
+    ldp = max(1, (inner + 63) // 64 * 64)
+    planes = torch.empty((slices, outer, ldp), dtype=torch.bfloat16, device=X.device)
+    e = torch.empty(max(1, outer), dtype=torch.int32, device=X.device)
+    _check(load().geninv_bslice(_ctx(X.device), rows, cols, _p(Xc), ldx, int(slices), int(transposed), _p(planes),
+                                ldp, _p(e)), "geninv_bslice")
+    return planes, e[:outer]
+
+
+def bgram(G: torch.Tensor, slices: int = 4):
+    """Lower triangle (upper set to zero) of the sliced Gram matrix G_s'G_s."""
+    _dev(G, "G")
+    m, n = G.shape
+    Gc, ldg = colmajor(G)
+    A = empty_colmajor(n, n, G.device)
+    A.zero_()
+    _check(load().geninv_bgram(_ctx(G.device), m, n, _p(Gc), ldg, int(slices), _p(A), max(1, n)), "geninv_bgram")
+    return A
+
+
 def lstsq(G: torch.Tensor, F: torch.Tensor, tol: float | None = None):
     """W = G^+ F (n x k), minimum-norm least squares (Section 1); m >= n."""
     _dev(G, "G")

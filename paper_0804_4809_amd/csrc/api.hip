@@ -1,6 +1,7 @@
 // libgeninv C ABI: context, workspace and the orchestration of the method's
 // steps on one HIP stream (declarations and contracts in include/geninv.h).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -12,11 +13,11 @@ using namespace geninv;
 // Kernel classes for the optional event timers (geninv_prof_*).
 enum ProfClass {
     PC_GRAM, PC_TOL, PC_FILL, PC_PANEL_GEMM, PC_PANEL_FACTOR, PC_LTL, PC_INV_PANEL, PC_INV_UPDATE,
-    PC_MIRROR, PC_CHAIN_K, PC_CHAIN_P, PC_CHAIN_Y, PC_LSTSQ, PC_GEMM, PC_COUNT
+    PC_MIRROR, PC_CHAIN_K, PC_CHAIN_P, PC_CHAIN_Y, PC_LSTSQ, PC_GEMM, PC_SLICE, PC_NS, PC_COUNT
 };
 static const char *const kProfNames[PC_COUNT] = {
     "gram", "tol", "fill", "panel_gemm", "panel_factor", "ltl", "inv_panel", "inv_update",
-    "mirror", "chain_k", "chain_p", "chain_y", "lstsq_apply", "gemm"};
+    "mirror", "chain_k", "chain_p", "chain_y", "lstsq_apply", "gemm", "slice", "newton_schulz"};
 
 struct ProfState {
     unsigned mask = 0;
@@ -329,6 +330,59 @@ int finish_rank(geninv_ctx *c, const int *rdev, int *rank) {
 
 bool bad_ld(long ld, int rows) { return ld < std::max(1, rows); }
 
+// ---- mixed precision (sliced bfloat16 products) --------------------------
+
+inline long pad64(long x) { return (x + 63) / 64 * 64; }
+
+struct MixedLayout {
+    size_t gc, gt, pc, ecg, erg, ep, gram, total;
+};
+
+// extra workspace of the mixed form, placed after the float64 layout
+MixedLayout make_mixed_layout(size_t base, int m, int n, int s, int sy, bool keep_gram) {
+    MixedLayout L{};
+    size_t off = base;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.gc = take((size_t)s * pad64(m) * n * sizeof(__bf16));
+    L.gt = take((size_t)sy * pad64(n) * m * sizeof(__bf16));
+    L.pc = take((size_t)sy * pad64(n) * n * sizeof(__bf16));
+    L.ecg = take((size_t)n * sizeof(int));
+    L.erg = take((size_t)m * sizeof(int));
+    L.ep = take((size_t)n * sizeof(int));
+    L.gram = keep_gram ? take((size_t)n * n * sizeof(double)) : 0;
+    L.total = off;
+    return L;
+}
+
+SlicedGemmArgs sliced(const __bf16 *A, long lda, long sa, int sA, const __bf16 *B, long ldb, long sb, int sB,
+                      const int *ea, const int *eb, double *C, long ldc, int M, int N, int Kpad, int lower) {
+    SlicedGemmArgs g{};
+    g.A = A; g.lda = lda; g.sa = sa;
+    g.B = B; g.ldb = ldb; g.sb = sb;
+    g.ea = ea; g.eb = eb;
+    g.C = C; g.ldc = ldc;
+    g.M = M; g.N = N; g.Kpad = Kpad;
+    g.lower = lower;
+    g.beta = 0.0;
+    int np = 0;
+    // every slice pair, most significant first
+    for (int sum = 0; sum <= (sA - 1) + (sB - 1); ++sum)
+        for (int t = 0; t < sA; ++t) {
+            const int u = sum - t;
+            if (u < 0 || u >= sB) continue;
+            g.pt[np] = t;
+            g.pu[np] = u;
+            g.pw[np] = std::ldexp(1.0, -8 * (t + u + 2));
+            ++np;
+        }
+    g.npairs = np;
+    return g;
+}
+
 }  // namespace
 
 extern "C" {
@@ -615,6 +669,138 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
         HIPCHK(launch_dgemm(gemm(A, ld, 0, T1, ld, 0, T2, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
         HIPCHK(launch_dgemm(gemm(A, ld, 0, T2, ld, 0, T1, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
         HIPCHK(launch_dgemm(gemm(L, ld, 0, T1, ld, 0, W, ldw, hdim(nn), hdim(k), r, 1.0, 0.0), c->stream));
+    }
+    return finish_rank(c, rdev, rank);
+}
+
+int geninv_bslice(geninv_ctx *c, int rows, int cols, const double *X, int ldx, int slices, int transposed,
+                  void *planes, int ldp, int *e) {
+    if (!c || rows < 0 || cols < 0 || slices < 1 || slices > 6) return GENINV_EINVAL;
+    if (rows == 0 || cols == 0) return GENINV_OK;
+    if (!X || !planes || !e || bad_ld(ldx, rows)) return GENINV_EINVAL;
+    if (bad_ld(ldp, transposed ? cols : rows)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    __bf16 *P = static_cast<__bf16 *>(planes);
+    if (!transposed) {
+        HIPCHK(launch_col_exponents(X, ldx, rows, cols, e, c->stream));
+        HIPCHK(launch_slice_cols(X, ldx, rows, cols, e, slices, P, ldp, (long)ldp * cols, c->stream));
+    } else {
+        HIPCHK(launch_row_exponents(X, ldx, rows, cols, e, c->stream));
+        HIPCHK(launch_slice_rows_t(X, ldx, rows, cols, e, slices, P, ldp, (long)ldp * rows, c->stream));
+    }
+    return GENINV_OK;
+}
+
+int geninv_bgram(geninv_ctx *c, int m, int n, const double *G, int ldg, int slices, double *A, int lda) {
+    if (!c || m < 0 || n < 0 || slices < 1 || slices > 6) return GENINV_EINVAL;
+    if (n == 0) return GENINV_OK;
+    if (!A || bad_ld(lda, n) || (m > 0 && (!G || bad_ld(ldg, m)))) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const MixedLayout ml = make_mixed_layout(0, std::max(m, 1), n, slices, 0, false);
+    CHK(ensure_ws(c, ml.total));
+    __bf16 *Gc = at<__bf16>(c, ml.gc);
+    int *ecg = at<int>(c, ml.ecg);
+    const long mp = pad64(std::max(m, 1));
+    if (m == 0) {
+        HIPCHK(launch_fill(A, lda, n, n, 0.0, c->stream));
+        return GENINV_OK;
+    }
+    HIPCHK(launch_col_exponents(G, ldg, m, n, ecg, c->stream));
+    HIPCHK(launch_slice_cols(G, ldg, m, n, ecg, slices, Gc, mp, mp * n, c->stream));
+    ProfScope ps(c, PC_GRAM, (double)slices * slices * m * n * (n + 1.0));
+    HIPCHK(launch_sliced_gemm(sliced(Gc, mp, mp * n, slices, Gc, mp, mp * n, slices, ecg, ecg, A, lda, n, n, (int)mp, 1),
+                              c->stream));
+    return GENINV_OK;
+}
+
+int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double tol, int slices, int chain_slices,
+                 int ns_steps, double *Y, int ldy, int *rank, int *piv) {
+    if (!c || m < 0 || n < 0 || slices < 1 || slices > 6 || chain_slices < 0 || chain_slices > 6 || ns_steps < 0)
+        return GENINV_EINVAL;
+    if (m == 0 || n == 0) {
+        if (rank) *rank = 0;
+        return GENINV_OK;
+    }
+    if (m < n) return GENINV_ENOTSUP;
+    if (!G || !Y || bad_ld(ldg, m) || bad_ld(ldy, n)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const int nn = n;
+    const Layout lay = make_layout(nn, 0);
+    const MixedLayout ml = make_mixed_layout(lay.total, m, n, slices, chain_slices, ns_steps > 0);
+    CHK(ensure_ws(c, ml.total));
+    double *A = at<double>(c, lay.slotA);
+    double *L = at<double>(c, lay.slotL);
+    double *K = at<double>(c, lay.slotK);
+    double *P = at<double>(c, lay.slotP);
+    int *pv = piv ? piv : at<int>(c, lay.piv);
+    __bf16 *Gc = at<__bf16>(c, ml.gc);
+    int *ecg = at<int>(c, ml.ecg);
+    const long ld = nn;
+    const long mp = pad64(m), np = pad64(n);
+
+    // 1. Gram matrix of the sliced G on the bfloat16 matrix cores (lower triangle)
+    {
+        ProfScope ps(c, PC_SLICE, 0.0);
+        HIPCHK(launch_col_exponents(G, ldg, m, n, ecg, c->stream));
+        HIPCHK(launch_slice_cols(G, ldg, m, n, ecg, slices, Gc, mp, mp * n, c->stream));
+    }
+    {
+        ProfScope ps(c, PC_GRAM, (double)m * nn * (nn + 1.0));
+        HIPCHK(launch_sliced_gemm(sliced(Gc, mp, mp * n, slices, Gc, mp, mp * n, slices, ecg, ecg, A, ld, n, n,
+                                         (int)mp, 1), c->stream));
+    }
+    double *Gram = nullptr;
+    if (ns_steps > 0) {
+        Gram = at<double>(c, ml.gram);
+        HIPCHK(launch_copy(A, ld, Gram, ld, hdim(nn), hdim(nn), c->stream));
+        HIPCHK(launch_mirror_lower(Gram, ld, hdim(nn), c->stream));
+    }
+    // 2-4. tolerance, full-rank Cholesky, (L'L)^-1 in float64
+    CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, pv, at<double>(c, lay.dvals)));
+    const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
+    const Dim r = ddim(nn, rdev);
+    CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
+    // 5. K = L M, P = K K' (float64)
+    {
+        ProfScope ps(c, PC_CHAIN_K, 0.0);
+        HIPCHK(launch_dgemm(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0), c->stream));
+    }
+    {
+        ProfScope ps(c, PC_CHAIN_P, 0.0);
+        HIPCHK(launch_dgemm(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER), c->stream));
+        HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
+    }
+    // 6. Newton-Schulz steps on P = (G'G)^+ in factored form: P <- 2P - P A P
+    //    (X = P G' follows the iteration X <- 2X - X G X)
+    for (int it = 0; it < ns_steps; ++it) {
+        ProfScope ps(c, PC_NS, 4.0 * nn * nn * nn);
+        double *T = L;   // L is no longer needed
+        HIPCHK(launch_dgemm(gemm(Gram, ld, 0, P, ld, 0, T, ld, hdim(nn), hdim(nn), hdim(nn), 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(P, ld, 0, T, ld, 0, K, ld, hdim(nn), hdim(nn), hdim(nn), -1.0, 0.0), c->stream));
+        // K = -P A P;  P <- 2P + K, kept exactly symmetric from its lower half
+        HIPCHK(launch_axpby(K, ld, P, ld, hdim(nn), hdim(nn), 1.0, 2.0, c->stream));
+        HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
+    }
+    // 7. Y = P G'
+    if (chain_slices > 0) {
+        __bf16 *Gt = at<__bf16>(c, ml.gt);
+        __bf16 *Pc = at<__bf16>(c, ml.pc);
+        int *erg = at<int>(c, ml.erg);
+        int *ep = at<int>(c, ml.ep);
+        {
+            ProfScope ps(c, PC_SLICE, 0.0);
+            HIPCHK(launch_row_exponents(G, ldg, m, n, erg, c->stream));
+            HIPCHK(launch_slice_rows_t(G, ldg, m, n, erg, chain_slices, Gt, np, np * m, c->stream));
+            // P is symmetric: its column slices are its row slices
+            HIPCHK(launch_col_exponents(P, ld, nn, nn, ep, c->stream));
+            HIPCHK(launch_slice_cols(P, ld, nn, nn, ep, chain_slices, Pc, np, np * nn, c->stream));
+        }
+        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
+        HIPCHK(launch_sliced_gemm(sliced(Pc, np, np * nn, chain_slices, Gt, np, np * m, chain_slices, ep, erg, Y, ldy,
+                                         n, m, (int)np, 0), c->stream));
+    } else {
+        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
+        HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
     }
     return finish_rank(c, rdev, rank);
 }

@@ -33,6 +33,21 @@ struct GemmArgs {
     long strideC;
 };
 
+// Sliced (error-free split) GEMM on bfloat16 matrix cores, ozaki.hip.
+constexpr int SG_MAX_PAIRS = 36;
+struct SlicedGemmArgs {
+    const __bf16 *A; long lda; long sa;   // opA(i, k) = A[t sa + k + i lda]
+    const __bf16 *B; long ldb; long sb;   // opB(k, j) = B[u sb + k + j ldb]
+    const int *ea; const int *eb;         // row exponents of opA, column exponents of opB
+    double *C; long ldc;
+    int M, N, Kpad;                       // Kpad: multiple of 64, zero padded in the planes
+    int npairs;
+    int pt[SG_MAX_PAIRS], pu[SG_MAX_PAIRS];
+    double pw[SG_MAX_PAIRS];              // 2^(-8 (t + u + 2))
+    int lower;
+    double beta;
+};
+
 // Device status word values (match geninv_status).
 enum { ST_OK = 0, ST_NONFINITE = -4, ST_NOTSPD = -5 };
 
@@ -45,6 +60,8 @@ hipError_t launch_fill(double *X, long ldx, int rows, int cols, double v, hipStr
 hipError_t launch_fill_int(int *x, int n, int v, hipStream_t s);
 hipError_t launch_copy(const double *X, long ldx, double *Yp, long ldy, Dim rows, Dim cols, hipStream_t s);
 hipError_t launch_mirror_lower(double *X, long ldx, Dim n, hipStream_t s);
+hipError_t launch_axpby(const double *X, long ldx, double *Yp, long ldy, Dim rows, Dim cols, double a, double b,
+                        hipStream_t s);   // Y = a X + b Y
 hipError_t launch_transpose(const double *X, long ldx, double *Yp, long ldy, int rows, int cols, hipStream_t s);
 
 // full-rank Cholesky (frchol.hip)
@@ -60,5 +77,14 @@ hipError_t launch_gj_panel(const double *B, long ldb, Dim r, int b, double *D, d
                            int *status, hipStream_t s);
 hipError_t launch_gj_update(double *B, long ldb, Dim r, int b, const double *D, const double *Rrow,
                             const double *Ccol, hipStream_t s);
+
+// operand slicing and sliced GEMM (ozaki.hip)
+hipError_t launch_col_exponents(const double *X, long ldx, int rows, int cols, int *e, hipStream_t s);
+hipError_t launch_row_exponents(const double *X, long ldx, int rows, int cols, int *e, hipStream_t s);
+hipError_t launch_slice_cols(const double *X, long ldx, int rows, int cols, const int *e, int nslices,
+                             __bf16 *planes, long ldp, long sp, hipStream_t s);
+hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, const int *e, int nslices,
+                               __bf16 *planes, long ldp, long sp, hipStream_t s);
+hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s);
 
 }  // namespace geninv

@@ -280,6 +280,21 @@ hipError_t launch_copy(const double *X, long ldx, double *Yp, long ldy, Dim rows
     return hipGetLastError();
 }
 
+__global__ void axpby_kernel(const double *X, long ldx, double *Yp, long ldy, Dim Rd, Dim Cd, double a, double b) {
+    const int rows = Rd.get(), cols = Cd.get();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i < rows && j < cols) Yp[i + (long)j * ldy] = a * X[i + (long)j * ldx] + b * Yp[i + (long)j * ldy];
+}
+
+hipError_t launch_axpby(const double *X, long ldx, double *Yp, long ldy, Dim rows, Dim cols, double a, double b,
+                        hipStream_t s) {
+    if (rows.host <= 0 || cols.host <= 0) return hipSuccess;
+    dim3 grid((rows.host + 255) / 256, cols.host);
+    hipLaunchKernelGGL(axpby_kernel, grid, dim3(256), 0, s, X, ldx, Yp, ldy, rows, cols, a, b);
+    return hipGetLastError();
+}
+
 // Upper triangle := transpose of the lower triangle, through 32 x 32 LDS tiles
 // so that both the read and the write are column-contiguous.
 __global__ void mirror_lower_kernel(double *X, long ldx, Dim nd) {

@@ -1,0 +1,125 @@
+"""GPU parity of the mixed-precision form (sliced bfloat16 products).
+
+* slicing is integer work: planes and exponents must be bit-identical to
+  the oracle's;
+* the sliced Gram matrix must equal the exactly rounded Gram matrix of the
+  sliced representation up to the float64 rounding of the pair/chunk totals
+  (bit-exact when every partial sum is exact);
+* the whole mixed method must give the oracle's rank and Y within 1e-6
+  relative Frobenius (the accuracy target of the mixed form).
+"""
+import numpy as np
+import pytest
+
+from oracle import geninv_ref as o
+from oracle import ozaki_ref as z
+from paper_0804_4809_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0804_4809_amd import api  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+MIXED_TOL = 1e-6
+
+
+def up(X):
+    return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(DEV)
+
+
+def down(T):
+    torch.cuda.synchronize()
+    return T.detach().cpu().numpy()
+
+
+def _case(label, **kw):
+    print(f"[case] {label} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.mark.parametrize("rows,cols,s", [(100, 7, 4), (257, 33, 3), (64, 64, 6), (1, 5, 2), (1000, 130, 4)])
+def test_slice_columns_bit_exact(rows, cols, s):
+    _case("bslice cols", rows=rows, cols=cols, s=s)
+    rng = np.random.default_rng(rows + cols)
+    X = rng.standard_normal((rows, cols)) * 10.0 ** rng.uniform(-5, 5, size=cols)
+    X[:, 0] = 0.0
+    S, e = z.slice_columns(X, s)
+    planes, eg = api.bslice(up(X), s)
+    eg = down(eg).astype(np.int64)
+    assert np.array_equal(eg, e)
+    P = down(planes.float()).astype(np.float64)          # (s, cols, ldp)
+    assert np.array_equal(P[:, :, :rows], np.transpose(S, (0, 2, 1)).astype(np.float64))
+    assert not P[:, :, rows:].any()
+
+
+@pytest.mark.parametrize("rows,cols,s", [(100, 7, 4), (33, 257, 3), (64, 64, 5)])
+def test_slice_rows_transposed_bit_exact(rows, cols, s):
+    _case("bslice rows", rows=rows, cols=cols, s=s)
+    rng = np.random.default_rng(rows * cols)
+    X = rng.standard_normal((rows, cols)) * 10.0 ** rng.uniform(-4, 4, size=(rows, 1))
+    S, e = z.slice_columns(X.T.copy(), s)               # row slicing = column slicing of X'
+    planes, eg = api.bslice(up(X), s, transposed=True)
+    assert np.array_equal(down(eg).astype(np.int64), e)
+    P = down(planes.float()).astype(np.float64)          # (s, rows, ldp): planes[t][i][k]
+    assert np.array_equal(P[:, :, :cols], np.transpose(S, (0, 2, 1)).astype(np.float64))
+    assert not P[:, :, cols:].any()
+
+
+def test_sliced_gram_integer_input_bit_exact():
+    _case("bgram exact integers")
+    rng = np.random.default_rng(9)
+    G = rng.integers(-100, 101, size=(777, 70)).astype(np.float64)
+    A = down(api.bgram(up(G), 4))
+    ref = G.T @ G          # exact: integer sums below 2^53
+    assert np.array_equal(np.tril(A), np.tril(ref))
+
+
+@pytest.mark.parametrize("m,n,s", [(300, 40, 4), (513, 129, 3), (2000, 200, 4)])
+def test_sliced_gram_matches_exact_representation_gram(m, n, s):
+    _case("bgram", m=m, n=n, s=s)
+    G, _ = w.lowrank_uv(m, n, max(1, n // 2), seed=m)
+    S, e = z.slice_columns(G, s)
+    Gs = z.reconstruct(S, e)
+    A = np.tril(down(api.bgram(up(G), s)))
+    ref = np.tril(z.sliced_gram(G, s)) if m * n * n <= 3e6 else np.tril(Gs.T @ Gs)
+    # float64 totals of s^2 pairs over ceil(m/256) exact chunks, plus one final scaling
+    nterms = s * s * ((m + 255) // 256) + 2
+    bound = nterms * 2.0 ** -53 * np.tril(np.abs(Gs).T @ np.abs(Gs))
+    assert np.all(np.abs(A - ref) <= bound + 1e-300)
+
+
+def test_mixed_c1_matches_oracle():
+    _case("mixed", cfg="c1")
+    G, F = w.c1_problem(0)
+    ref = o.geninv(G)
+    Y, r, piv = api.mixed(up(G), return_piv=True)
+    assert r == ref.rank
+    assert np.array_equal(down(piv).astype(np.int64), ref.piv)
+    assert o.rel_fro(down(Y), ref.Y) <= MIXED_TOL
+
+
+@pytest.mark.parametrize("chain_slices,ns", [(4, 0), (0, 0), (4, 1)])
+def test_mixed_svd_family(chain_slices, ns):
+    """G = P diag(s) Q', 8192 x 1024, rank 768, s in [1e-3, 1]: the mixed-form
+    workload at reduced size."""
+    _case("mixed", cfg="svd 8192x1024 r768", chain_slices=chain_slices, ns=ns)
+    G, _, P, sv, Q = w.svd_family(8192, 1024, 768, 1e-3, seed=2)
+    ref = o.geninv(G)
+    Y, r, piv = api.mixed(up(G), chain_slices=chain_slices, ns_steps=ns, return_piv=True)
+    Yg = down(Y)
+    err = o.rel_fro(Yg, ref.Y)
+    print(f"  rank gpu {r} oracle {ref.rank}; relF(Y) vs oracle {err:.3e}; "
+          f"vs closed form {o.rel_fro(Yg, (Q / sv) @ P.T):.3e}", flush=True)
+    assert r == ref.rank == 768
+    assert np.array_equal(down(piv).astype(np.int64), ref.piv)
+    assert err <= MIXED_TOL
+
+
+def test_mixed_rejects_wide_input():
+    G = up(np.ones((3, 5)))
+    with pytest.raises(api.GeninvError) as e:
+        api.mixed(G)
+    assert e.value.status == -6

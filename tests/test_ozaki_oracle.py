@@ -1,0 +1,85 @@
+"""Pins of the slicing reference (oracle/ozaki_ref.py) against exact facts."""
+import numpy as np
+import pytest
+
+from oracle import ozaki_ref as z
+from paper_0804_4809_amd import workloads as w
+
+
+def test_exponents_bound_column_max():
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((50, 7)) * np.array([1e-3, 1, 1e3, 0.5, 1.0, 2.0, 3.999])
+    X[:, 4] = 0.0
+    e = z.column_exponents(X)
+    mx = np.abs(X).max(axis=0)
+    for j in range(7):
+        if mx[j] == 0:
+            assert e[j] == 0
+        else:
+            assert mx[j] < 2.0 ** e[j] <= 2 * mx[j]
+    # exact powers of two: max = 2^k  ->  e = k + 1
+    assert z.column_exponents(np.array([[4.0], [-1.0]]))[0] == 3
+
+
+def test_slices_are_bounded_integers():
+    G, _ = w.lowrank_uv(64, 9, 5, seed=1)
+    S, e = z.slice_columns(G, 4)
+    assert S.dtype == np.int64 and np.abs(S).max() <= 255
+    # truncation toward zero: every slice has the sign of its element (or is 0)
+    assert np.all((S * np.sign(G)[None]) >= 0)
+
+
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 5, 6])
+def test_reconstruction_error_bound(s):
+    rng = np.random.default_rng(s)
+    G = rng.standard_normal((200, 11)) * 10.0 ** rng.uniform(-3, 3, size=11)
+    S, e = z.slice_columns(G, s)
+    Gs = z.reconstruct(S, e)
+    # |G - G_s| < 2^(e_j - 8 s) elementwise, and G_s is G truncated toward zero
+    assert np.all(np.abs(G - Gs) < np.ldexp(1.0, e[None, :] - 8 * s))
+    assert np.all(np.abs(Gs) <= np.abs(G))
+
+
+def test_short_mantissas_are_represented_exactly():
+    # entries with at most 16 significant bits below the column bound are exact with 2 slices
+    rng = np.random.default_rng(3)
+    ints = rng.integers(-2 ** 15, 2 ** 15, size=(40, 5)).astype(np.float64)
+    G = ints * 2.0 ** -10
+    S, e = z.slice_columns(G, 2)
+    assert np.array_equal(z.reconstruct(S, e), G)
+
+
+def test_sliced_gram_equals_gram_of_representation():
+    # the sliced product of the representation is the exact Gram of G_s,
+    # checked against float64 G_s'G_s computed in exact rational arithmetic
+    from fractions import Fraction
+    rng = np.random.default_rng(4)
+    G = rng.standard_normal((12, 4))
+    S, e = z.slice_columns(G, 3)
+    Gs = z.reconstruct(S, e)
+    A = z.sliced_gram(G, 3)
+    for i in range(4):
+        for j in range(4):
+            exact = sum(Fraction(Gs[k, i]) * Fraction(Gs[k, j]) for k in range(12))
+            assert A[i, j] == float(exact)
+
+
+def test_sliced_gram_approaches_gram():
+    G, _ = w.lowrank_uv(300, 20, 12, seed=5)
+    A = G.T @ G
+    for s, tol in [(2, 1e-4), (3, 1e-6), (4, 1e-8)]:
+        As = z.sliced_gram(G, s)
+        assert np.linalg.norm(As - A) / np.linalg.norm(A) < tol
+
+
+def test_chunk_of_256_pair_products_is_exact_in_float32():
+    # the accumulation argument of the GPU kernel: 256 products of slices
+    # bounded by 255 sum to less than 2^24, so float32 partial sums are exact
+    assert 256 * 255 * 255 < 2 ** 24
+    rng = np.random.default_rng(6)
+    a = rng.integers(-255, 256, size=256)
+    b = rng.integers(-255, 256, size=256)
+    acc = np.float32(0.0)
+    for x, y in zip(a, b):
+        acc = np.float32(acc + np.float32(x) * np.float32(y))
+    assert int(acc) == int(np.dot(a, b))
