@@ -179,6 +179,44 @@ int geninv_bslice(geninv_ctx *ctx, int rows, int cols, const double *X, int ldx,
  * geninv_mixed, for parity testing. */
 int geninv_bgram(geninv_ctx *ctx, int m, int n, const double *G, int ldg, int slices, double *A, int lda);
 
+/* ---- batched least squares ---------------------------------------------- */
+
+/* A plan solves `batch` independent small problems W_b = G_b^+ F_b (Section 1)
+ * in one persistent launch: each workgroup takes problems from a device work
+ * queue, largest first, and runs the whole method on one problem (Gram matrix
+ * and G'F with float64 accumulation, tol, full-rank Cholesky, (L'L)^-1,
+ * W = L M M L' G'F).
+ *   m, n, ldg, ldf, ldw   HOST int[batch]; 1 <= n_b <= 256, m_b >= n_b
+ *   G, F                  HOST arrays of DEVICE pointers: G_b m_b x n_b and
+ *                         F_b m_b x k, float32, column-major
+ *   W                     HOST array of DEVICE pointers: W_b n_b x k, float64
+ *   k                     1..16 right-hand sides (the same for every problem)
+ *   tol                   <= 0: the paper's default per problem
+ *   rank                  DEVICE int[batch]: r_b, written by every run
+ * The pointers are fixed for the plan's lifetime; inputs may change between
+ * runs.  The plan keeps its own device copies of the descriptors. */
+typedef struct geninv_batch_plan geninv_batch_plan;
+int geninv_batch_plan_create(geninv_ctx *ctx, geninv_batch_plan **plan, int batch, const int *m,
+                             const int *n, int k, const float *const *G, const int *ldg,
+                             const float *const *F, const int *ldf, double *const *W,
+                             const int *ldw, double tol, int *rank);
+int geninv_batch_plan_destroy(geninv_batch_plan *plan);
+
+/* Enqueue one solve of every problem on the context stream.  use_graph != 0
+ * captures the launch into a HIP graph on first use (on a non-default
+ * stream) and replays it afterwards. */
+int geninv_batch_plan_run(geninv_batch_plan *plan, int use_graph);
+
+/* Autotuner: times each launch configuration (LDS threshold below which a
+ * problem's Gram matrix and L'L live in LDS, and workgroups per compute unit)
+ * `reps` times and keeps the fastest; outputs may be NULL.  Synchronizes. */
+int geninv_batch_plan_autotune(geninv_batch_plan *plan, int reps, int *best_nl, int *best_grid,
+                               double *best_ms);
+
+/* Set or read the launch configuration directly (e.g. from a cached tuning). */
+int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid);
+int geninv_batch_plan_get_config(geninv_batch_plan *plan, int *nl, int *grid);
+
 /* ---- event timers ------------------------------------------------------- */
 
 /* Per-kernel-class HIP event timers on the context stream, for profiling.

@@ -57,6 +57,15 @@ _SIGS = [
                                      ctypes.c_int, _VP, ctypes.c_int, _VP]),
     ("geninv_bgram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int, _VP,
                                     ctypes.c_int]),
+    ("geninv_batch_plan_create", ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int, _c_int_p, _c_int_p,
+                                                ctypes.c_int, ctypes.POINTER(_VP), _c_int_p, ctypes.POINTER(_VP),
+                                                _c_int_p, ctypes.POINTER(_VP), _c_int_p, ctypes.c_double, _VP]),
+    ("geninv_batch_plan_destroy", ctypes.c_int, [_VP]),
+    ("geninv_batch_plan_run", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("geninv_batch_plan_autotune", ctypes.c_int, [_VP, ctypes.c_int, _c_int_p, _c_int_p,
+                                                  ctypes.POINTER(ctypes.c_double)]),
+    ("geninv_batch_plan_config", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
+    ("geninv_batch_plan_get_config", ctypes.c_int, [_VP, _c_int_p, _c_int_p]),
     ("geninv_prof_classes", ctypes.c_int, []),
     ("geninv_prof_name", ctypes.c_char_p, [ctypes.c_int]),
     ("geninv_prof_enable", ctypes.c_int, [_VP, ctypes.c_uint]),

@@ -246,3 +246,91 @@ def sync_status(device=None):
     """Wait for the stream; device-side status of the calls since the last check."""
     dev = torch.device("cuda", device if device is not None else torch.cuda.current_device())
     return load().geninv_sync_status(_ctx(dev))
+
+
+class BatchPlan:
+    """Batched least squares W_b = G_b^+ F_b (geninv_batch_plan_*).
+
+    G_b (m_b x n_b) and F_b (m_b x k) are float32; they are packed
+    column-major into two device buffers owned by the plan (``load`` refills
+    them in place).  W_b (n_b x k, float64) and the ranks are outputs.
+    """
+
+    def __init__(self, Gs, Fs, tol: float | None = None, device=None):
+        import numpy as np
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.batch = len(Gs)
+        if self.batch != len(Fs):
+            raise ValueError("Gs and Fs differ in length")
+        self.m = np.array([g.shape[0] for g in Gs], dtype=np.int32)
+        self.n = np.array([g.shape[1] for g in Gs], dtype=np.int32)
+        ks = {f.shape[1] for f in Fs}
+        if len(ks) != 1:
+            raise ValueError("every F_b needs the same number of columns")
+        self.k = ks.pop()
+        self.g_off = np.concatenate([[0], np.cumsum(self.m.astype(np.int64) * self.n)])
+        self.f_off = np.concatenate([[0], np.cumsum(self.m.astype(np.int64) * self.k)])
+        self.w_off = np.concatenate([[0], np.cumsum(self.n.astype(np.int64) * self.k)])
+        self.Gbuf = torch.empty(int(self.g_off[-1]), dtype=torch.float32, device=self.device)
+        self.Fbuf = torch.empty(int(self.f_off[-1]), dtype=torch.float32, device=self.device)
+        self.Wbuf = torch.zeros(int(self.w_off[-1]), dtype=torch.float64, device=self.device)
+        self.rank = torch.zeros(max(1, self.batch), dtype=torch.int32, device=self.device)
+        self.load(Gs, Fs)
+        lib = load()
+        vp = ctypes.c_void_p
+        gb, fb, wb = self.Gbuf.data_ptr(), self.Fbuf.data_ptr(), self.Wbuf.data_ptr()
+        Gp = (vp * self.batch)(*[gb + 4 * int(o) for o in self.g_off[:-1]])
+        Fp = (vp * self.batch)(*[fb + 4 * int(o) for o in self.f_off[:-1]])
+        Wp = (vp * self.batch)(*[wb + 8 * int(o) for o in self.w_off[:-1]])
+        ci = ctypes.c_int * self.batch
+        m_c, n_c = ci(*self.m.tolist()), ci(*self.n.tolist())
+        h = vp()
+        self._lib = lib
+        self._ctx = _ctx(self.device)
+        _check(lib.geninv_batch_plan_create(self._ctx, ctypes.byref(h), self.batch, m_c, n_c, self.k, Gp, m_c, Fp,
+                                            m_c, Wp, n_c, float(tol or 0.0), _p(self.rank)),
+               "geninv_batch_plan_create")
+        self._plan = h
+
+    def load(self, Gs, Fs):
+        """Copy new G_b, F_b (same shapes) into the plan's packed buffers."""
+        import numpy as np
+        g = np.concatenate([np.asarray(x, np.float32).ravel(order="F") for x in Gs]) if self.batch else np.zeros(0)
+        f = np.concatenate([np.asarray(x, np.float32).ravel(order="F") for x in Fs]) if self.batch else np.zeros(0)
+        self.Gbuf.copy_(torch.from_numpy(g.astype(np.float32)))
+        self.Fbuf.copy_(torch.from_numpy(f.astype(np.float32)))
+
+    def run(self, use_graph: bool = True):
+        _ctx(self.device)   # follow torch's current stream
+        _check(self._lib.geninv_batch_plan_run(self._plan, int(use_graph)), "geninv_batch_plan_run")
+
+    def autotune(self, reps: int = 3):
+        _ctx(self.device)
+        nl, grid, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+        _check(self._lib.geninv_batch_plan_autotune(self._plan, reps, ctypes.byref(nl), ctypes.byref(grid),
+                                                    ctypes.byref(ms)), "geninv_batch_plan_autotune")
+        return nl.value, grid.value, ms.value
+
+    def config(self, nl: int | None = None, grid: int | None = None):
+        if nl is not None and grid is not None:
+            _check(self._lib.geninv_batch_plan_config(self._plan, int(nl), int(grid)), "geninv_batch_plan_config")
+        a, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.geninv_batch_plan_get_config(self._plan, ctypes.byref(a), ctypes.byref(b)),
+               "geninv_batch_plan_get_config")
+        return a.value, b.value
+
+    def W(self, b: int):
+        o = int(self.w_off[b])
+        n = int(self.n[b])
+        return self.Wbuf[o:o + n * self.k].view(self.k, n).t()
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            self._lib.geninv_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "common.h"
@@ -13,11 +14,11 @@ using namespace geninv;
 // Kernel classes for the optional event timers (geninv_prof_*).
 enum ProfClass {
     PC_GRAM, PC_TOL, PC_FILL, PC_PANEL_GEMM, PC_PANEL_FACTOR, PC_LTL, PC_INV_PANEL, PC_INV_UPDATE,
-    PC_MIRROR, PC_CHAIN_K, PC_CHAIN_P, PC_CHAIN_Y, PC_LSTSQ, PC_GEMM, PC_SLICE, PC_NS, PC_COUNT
+    PC_MIRROR, PC_CHAIN_K, PC_CHAIN_P, PC_CHAIN_Y, PC_LSTSQ, PC_GEMM, PC_SLICE, PC_NS, PC_BATCHED, PC_COUNT
 };
 static const char *const kProfNames[PC_COUNT] = {
     "gram", "tol", "fill", "panel_gemm", "panel_factor", "ltl", "inv_panel", "inv_update",
-    "mirror", "chain_k", "chain_p", "chain_y", "lstsq_apply", "gemm", "slice", "newton_schulz"};
+    "mirror", "chain_k", "chain_p", "chain_y", "lstsq_apply", "gemm", "slice", "newton_schulz", "batched"};
 
 struct ProfState {
     unsigned mask = 0;
@@ -28,6 +29,8 @@ struct ProfState {
     long cnt[PC_COUNT] = {};
     double fl[PC_COUNT] = {};
 };
+
+struct geninv_batch_plan;
 
 struct geninv_ctx {
     int device = 0;
@@ -803,6 +806,218 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
         HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
     }
     return finish_rank(c, rdev, rank);
+}
+
+}  // extern "C"
+
+// ---- batched least squares ----------------------------------------------
+
+struct geninv_batch_plan {
+    geninv_ctx *c = nullptr;
+    int batch = 0, k = 0, nmax = 0;
+    double tol = 0.0;
+    void *desc = nullptr;        // device BatchDesc[batch]
+    int *order = nullptr;        // device int[batch], largest problem first
+    int *queue = nullptr;        // device work counter
+    double *slabs = nullptr;     // device per-workgroup slabs
+    int max_grid = 0;
+    int *rank = nullptr;         // caller's device int[batch]
+    int nl = 0, grid = 0;        // LDS threshold and workgroups (autotuned)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+void plan_drop_graph(geninv_batch_plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->graph_stream = nullptr;
+}
+
+int plan_launch(geninv_batch_plan *p, hipStream_t s) {
+    HIPCHK(launch_batched(p->desc, p->order, p->batch, p->k, p->tol, p->nl, p->queue, p->slabs, p->grid, p->nmax,
+                          p->rank, p->c->status, s));
+    return GENINV_OK;
+}
+
+// LDS threshold -> workgroups per compute unit that fit 160 KB of LDS
+int wgs_per_cu(int nl, int nmax, int k) {
+    const size_t lds = batched_lds_bytes(nl, nmax, k);
+    int w = (int)(160 * 1024 / lds);
+    return std::max(1, std::min(w, 4));
+}
+
+}  // namespace
+
+extern "C" {
+
+int geninv_batch_plan_destroy(geninv_batch_plan *p);
+
+int geninv_batch_plan_create(geninv_ctx *c, geninv_batch_plan **plan, int batch, const int *m, const int *n, int k,
+                             const float *const *G, const int *ldg, const float *const *F, const int *ldf,
+                             double *const *W, const int *ldw, double tol, int *rank) {
+    if (!c || !plan || batch < 0 || k < 1 || k > BATCH_KMAX) return GENINV_EINVAL;
+    *plan = nullptr;
+    if (batch > 0 && (!m || !n || !G || !ldg || !F || !ldf || !W || !ldw || !rank)) return GENINV_EINVAL;
+    int nmax = 1;
+    for (int b = 0; b < batch; ++b) {
+        if (n[b] < 1 || n[b] > BATCH_NMAX || m[b] < n[b] || !G[b] || !F[b] || !W[b]) return GENINV_EINVAL;
+        if (ldg[b] < m[b] || ldf[b] < m[b] || ldw[b] < n[b]) return GENINV_EINVAL;
+        nmax = std::max(nmax, n[b]);
+    }
+    DeviceGuard g(c->device);
+    geninv_batch_plan *p = new geninv_batch_plan();
+    p->c = c;
+    p->batch = batch;
+    p->k = k;
+    p->nmax = nmax;
+    p->tol = tol;
+    p->rank = rank;
+    // largest-first order: estimated work m n^2 + n^3 (Gram, then factorization and inverse)
+    std::vector<int> order(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const double wa = (double)m[a] * n[a] * n[a] + (double)n[a] * n[a] * n[a];
+        const double wb = (double)m[b] * n[b] * n[b] + (double)n[b] * n[b] * n[b];
+        return wa > wb;
+    });
+    std::vector<char> desc(batched_desc_bytes() * std::max(batch, 1));
+    for (int b = 0; b < batch; ++b)
+        batched_fill_desc(desc.data() + b * batched_desc_bytes(), G[b], F[b], W[b], m[b], n[b], ldg[b], ldf[b], ldw[b]);
+    p->nl = std::min(128, nmax);
+    p->grid = 256 * wgs_per_cu(p->nl, nmax, k);
+    p->max_grid = 256 * 4;
+    const size_t slab_bytes = batched_slab_doubles(nmax, k) * sizeof(double) * p->max_grid;
+    bool ok = hipMalloc(&p->desc, desc.size()) == hipSuccess &&
+              hipMalloc((void **)&p->order, sizeof(int) * std::max(batch, 1)) == hipSuccess &&
+              hipMalloc((void **)&p->queue, 256) == hipSuccess &&
+              hipMalloc((void **)&p->slabs, slab_bytes) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        geninv_batch_plan_destroy(p);
+        return GENINV_ENOMEM;
+    }
+    if (hipMemcpy(p->desc, desc.data(), desc.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (batch > 0 && hipMemcpy(p->order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice) != hipSuccess)) {
+        geninv_batch_plan_destroy(p);
+        return GENINV_EHIP;
+    }
+    *plan = p;
+    return GENINV_OK;
+}
+
+int geninv_batch_plan_destroy(geninv_batch_plan *p) {
+    if (!p) return GENINV_OK;
+    DeviceGuard g(p->c->device);
+    (void)hipStreamSynchronize(p->c->stream);
+    plan_drop_graph(p);
+    if (p->desc) (void)hipFree(p->desc);
+    if (p->order) (void)hipFree(p->order);
+    if (p->queue) (void)hipFree(p->queue);
+    if (p->slabs) (void)hipFree(p->slabs);
+    delete p;
+    return GENINV_OK;
+}
+
+int geninv_batch_plan_config(geninv_batch_plan *p, int nl, int grid) {
+    if (!p || nl < 0 || grid < 1 || grid > p->max_grid) return GENINV_EINVAL;
+    if (batched_lds_bytes(nl, p->nmax, p->k) > 160 * 1024) return GENINV_EINVAL;
+    if (nl != p->nl || grid != p->grid) plan_drop_graph(p);
+    p->nl = nl;
+    p->grid = grid;
+    return GENINV_OK;
+}
+
+int geninv_batch_plan_get_config(geninv_batch_plan *p, int *nl, int *grid) {
+    if (!p) return GENINV_EINVAL;
+    if (nl) *nl = p->nl;
+    if (grid) *grid = p->grid;
+    return GENINV_OK;
+}
+
+int geninv_batch_plan_run(geninv_batch_plan *p, int use_graph) {
+    if (!p) return GENINV_EINVAL;
+    if (p->batch == 0) return GENINV_OK;
+    geninv_ctx *c = p->c;
+    DeviceGuard g(c->device);
+    ProfScope ps(c, PC_BATCHED, 0.0);
+    if (!use_graph || c->stream == nullptr) return plan_launch(p, c->stream);
+    if (p->exec && p->graph_stream != c->stream) plan_drop_graph(p);
+    if (!p->exec) {
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        const int st = plan_launch(p, c->stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (st != GENINV_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st != GENINV_OK ? st : GENINV_EHIP;
+        }
+        p->graph = graph;
+        if (hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            plan_drop_graph(p);
+            return GENINV_EHIP;
+        }
+        p->graph_stream = c->stream;
+    }
+    HIPCHK(hipGraphLaunch(p->exec, c->stream));
+    return GENINV_OK;
+}
+
+// Times every (LDS threshold, workgroups per CU) candidate `reps` times with
+// events on the context stream and keeps the fastest.
+int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, int *best_nl, int *best_grid, double *best_ms) {
+    if (!p || reps < 1) return GENINV_EINVAL;
+    geninv_ctx *c = p->c;
+    DeviceGuard g(c->device);
+    const int cand_nl[] = {128, 96, 64, 48, 32, 0};
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    double best = 1e300;
+    int bnl = p->nl, bgrid = p->grid;
+    for (int nl : cand_nl) {
+        if (nl > p->nmax && nl != 128) continue;
+        const int nlc = std::min(nl, p->nmax);
+        if (batched_lds_bytes(nlc, p->nmax, p->k) > 160 * 1024) continue;
+        const int w = wgs_per_cu(nlc, p->nmax, p->k);
+        for (int ww = 1; ww <= w; ww *= 2) {
+            const int grid = 256 * ww;
+            plan_drop_graph(p);
+            p->nl = nlc;
+            p->grid = grid;
+            CHK(plan_launch(p, c->stream));   // warm-up
+            std::vector<float> t;
+            for (int r = 0; r < reps; ++r) {
+                HIPCHK(hipEventRecord(a, c->stream));
+                CHK(plan_launch(p, c->stream));
+                HIPCHK(hipEventRecord(b, c->stream));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                t.push_back(ms);
+            }
+            std::sort(t.begin(), t.end());
+            const double med = t[t.size() / 2];
+            if (med < best) {
+                best = med;
+                bnl = nlc;
+                bgrid = grid;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    plan_drop_graph(p);
+    p->nl = bnl;
+    p->grid = bgrid;
+    if (best_nl) *best_nl = bnl;
+    if (best_grid) *best_grid = bgrid;
+    if (best_ms) *best_ms = best;
+    return GENINV_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,341 @@
+// Batched least squares W_b = G_b^+ F_b for thousands of small, unevenly sized
+// problems in one persistent launch (Section 1's least-squares use of the
+// method, Section 4's many small fits; the method itself is the Appendix's).
+//
+// Every workgroup (256 threads) takes problems from a device work queue (an
+// atomic counter over a host-computed order, largest first) until the queue
+// is empty; all workgroups reach that exit.  One problem runs entirely inside
+// one workgroup:
+//
+//   1. A = G'G and B = G'F, float32 inputs accumulated in float64 (register
+//      tiles of 4 x 4 outputs per thread, G staged through LDS 8 rows at a time)
+//   2. tol = 1e-9 min{A_kk > 0} (or the caller's), then the full-rank Cholesky
+//      of A in place, column by column with the paper's strict test
+//   3. C = L'L and T = L'B, as a second Gram product over the kept columns
+//   4. M = C^-1 in place by Gauss-Jordan elimination (C is SPD)
+//   5. W = L (M (M T))
+//
+// A (and later C) lives in LDS when its order is at most `nl` (a launch
+// parameter chosen by the autotuner), otherwise in a per-workgroup slab of
+// global memory; the same code runs on either through flat pointers.
+#include "common.h"
+
+namespace geninv {
+
+constexpr int BT_THREADS = 256;
+constexpr int BT_STAGE_ROWS = 8;
+
+__device__ __forceinline__ double ldv(const float *p) { return (double)*p; }
+__device__ __forceinline__ double ldv(const double *p) { return *p; }
+
+// Lower triangle of X(:, cols)' X(:, cols) into Aout (nc x nc, lda) and
+// X(:, cols)' F into Bout (nc x k, ldb).  cols[c] selects the source column of
+// output column c (identity when cols == nullptr); with `tri`, the source is
+// taken as zero above row cols[c] (a lower trapezoidal factor).
+template <typename T>
+__device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *cols, bool tri, const T *F, long ldf,
+                           int k, double *Aout, long lda, double *Bout, long ldb, double *stage) {
+    const int tid = threadIdx.x;
+    const int nt = (nc + 3) / 4, kt = (k + 3) / 4;
+    const int tri_tiles = nt * (nt + 1) / 2;
+    const int ntiles = tri_tiles + nt * kt;
+    const int sw = nc + k;                 // stage width (columns)
+    for (int base = 0; base < ntiles; base += BT_THREADS) {
+        const int t = base + tid;
+        int ti = 0, tj = 0;
+        bool fcol = false, active = t < ntiles;
+        if (active) {
+            if (t < tri_tiles) {
+                ti = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+                while (ti * (ti + 1) / 2 > t) --ti;
+                while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+                tj = t - ti * (ti + 1) / 2;
+            } else {
+                const int u = t - tri_tiles;
+                ti = u / kt;
+                tj = u % kt;
+                fcol = true;
+            }
+        }
+        double acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int k0 = 0; k0 < rows; k0 += BT_STAGE_ROWS) {
+            __syncthreads();
+            for (int e = tid; e < BT_STAGE_ROWS * sw; e += BT_THREADS) {
+                const int r = e % BT_STAGE_ROWS, c = e / BT_STAGE_ROWS;
+                const int row = k0 + r;
+                double v = 0.0;
+                if (row < rows) {
+                    if (c < nc) {
+                        const int src = cols ? cols[c] : c;
+                        if (!tri || row >= src) v = ldv(X + row + (long)src * ldx);
+                    } else {
+                        v = ldv(F + row + (long)(c - nc) * ldf);
+                    }
+                }
+                stage[r * sw + c] = v;
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int r = 0; r < BT_STAGE_ROWS; ++r) {
+                    double av[4], bv[4];
+                    const double *srow = stage + r * sw;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const int ci = ti * 4 + a;
+                        av[a] = ci < nc ? srow[ci] : 0.0;
+                    }
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int cj = fcol ? nc + tj * 4 + b : tj * 4 + b;
+                        bv[b] = (fcol ? (tj * 4 + b < k) : (cj < nc)) ? srow[cj] : 0.0;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+                }
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = ti * 4 + a, j = tj * 4 + b;
+                    if (i >= nc) continue;
+                    if (fcol) {
+                        if (j < k) Bout[i + (long)j * ldb] = acc[a][b];
+                    } else if (j <= i) {
+                        Aout[i + (long)j * lda] = acc[a][b];
+                    }
+                }
+        }
+    }
+    __syncthreads();
+}
+
+// tol (<= 0: paper default), returns the threshold; also flags non-finite diagonals
+__device__ double block_tol(const double *A, long lda, int n, double user_tol, double *red, int *bad) {
+    const int tid = threadIdx.x;
+    double mn = __builtin_huge_val();
+    int b = 0;
+    for (int i = tid; i < n; i += BT_THREADS) {
+        const double a = A[i + (long)i * lda];
+        if (!__builtin_isfinite(a)) b = 1;
+        else if (a > 0.0 && a < mn) mn = a;
+    }
+    red[tid] = mn;
+    __syncthreads();
+    if (b) *bad = 1;
+    for (int s = BT_THREADS / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmin(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const double m = red[0];
+    __syncthreads();
+    if (*bad) return __builtin_huge_val();
+    if (user_tol > 0.0) return user_tol;
+    return m == __builtin_huge_val() ? m : m * 1e-9;
+}
+
+// full-rank Cholesky in place on the lower triangle of A (n x n): column j
+// kept iff its updated pivot is > tol.  Kept columns hold L (rows >= j), the
+// others are zeroed.  cols[] receives the kept column indices; returns r.
+__device__ int block_frchol(double *A, long lda, int n, double tol, int *cols, int *cnt) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) *cnt = 0;
+    for (int j = 0; j < n; ++j) {
+        __syncthreads();
+        const double d = A[j + (long)j * lda];
+        const bool keep = d > tol;
+        double *colj = A + (long)j * lda;
+        __syncthreads();   // every thread has read the pivot before it is overwritten
+        if (keep) {
+            const double s = sqrt(d);
+            for (int i = j + 1 + tid; i < n; i += BT_THREADS) colj[i] = colj[i] / s;
+            if (tid == 0) {
+                colj[j] = s;
+                cols[*cnt] = j;
+                *cnt = *cnt + 1;
+            }
+            __syncthreads();
+            for (int l = j + 1 + wave; l < n; l += 4) {
+                const double f = colj[l];
+                double *coll = A + (long)l * lda;
+                for (int i = l + lane; i < n; i += 64) coll[i] -= colj[i] * f;
+            }
+        } else {
+            for (int i = j + tid; i < n; i += BT_THREADS) colj[i] = 0.0;
+        }
+    }
+    __syncthreads();
+    const int r = *cnt;
+    __syncthreads();
+    return r;
+}
+
+// in-place Gauss-Jordan inverse of the SPD matrix C (r x r, full storage);
+// returns false if a pivot is not positive
+__device__ bool block_gj(double *C, long ldc, int r, double *rowp, double *colp) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    bool ok = true;
+    for (int p = 0; p < r; ++p) {
+        __syncthreads();
+        const double pv = C[p + (long)p * ldc];
+        if (!(pv > 0.0)) ok = false;
+        const double dinv = 1.0 / pv;
+        for (int t = tid; t < r; t += BT_THREADS) {
+            rowp[t] = C[p + (long)t * ldc] * dinv;
+            colp[t] = C[t + (long)p * ldc];
+        }
+        __syncthreads();
+        for (int jc = wave; jc < r; jc += 4) {
+            const double rp = rowp[jc];
+            double *colc = C + (long)jc * ldc;
+            for (int i = lane; i < r; i += 64) {
+                double v = colc[i] - colp[i] * rp;
+                if (i == p) v = rp;
+                if (jc == p) v = (i == p) ? dinv : -colp[i] * dinv;
+                colc[i] = v;
+            }
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
+struct BatchDesc {
+    const float *G; const float *F; double *W;
+    int m, n, ldg, ldf, ldw;
+    int pad;
+};
+
+__global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
+                                                                   int k, double user_tol, int nl, int *queue,
+                                                                   double *slabs, long slab_stride, int nmax,
+                                                                   int *rank, int *status) {
+    extern __shared__ __attribute__((aligned(16))) double lds[];
+    // LDS carve-up: [nl*nl] big | [8*(nmax+k)] stage | [256] red | [nmax] rowp | [nmax] colp | ints
+    double *big = lds;
+    double *stage = big + (long)nl * nl;
+    double *red = stage + BT_STAGE_ROWS * (nmax + k);
+    double *rowp = red + BT_THREADS;
+    double *colp = rowp + nmax;
+    int *cols = reinterpret_cast<int *>(colp + nmax);
+    int *ints = cols + nmax;            // [0] queue slot, [1] counter, [2] bad flag
+
+    double *slab = slabs + (long)blockIdx.x * slab_stride;
+    double *Lg = slab;                                   // nmax x nmax
+    double *Cg = Lg + (long)nmax * nmax;                 // nmax x nmax
+    double *Bv = Cg + (long)nmax * nmax;                 // nmax x k: G'F
+    double *Tv = Bv + (long)nmax * k;                    // nmax x k: L'B, then M x
+    double *Xv = Tv + (long)nmax * k;                    // nmax x k
+
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) ints[0] = atomicAdd(queue, 1);
+        __syncthreads();
+        const int slot = ints[0];
+        __syncthreads();
+        if (slot >= batch) break;
+        const int b = order[slot];
+        const BatchDesc d = desc[b];
+        const int m = d.m, n = d.n;
+        if (tid == 0) ints[2] = 0;
+
+        // 1. A = G'G, B = G'F
+        double *A = (n <= nl) ? big : Lg;
+        const long lda = n;
+        block_gram<float>(d.G, d.ldg, m, n, nullptr, false, d.F, d.ldf, k, A, lda, Bv, n, stage);
+        // 2. tolerance and full-rank Cholesky in place
+        const double tol = block_tol(A, lda, n, user_tol, red, &ints[2]);
+        if (ints[2] && tid == 0) *status = ST_NONFINITE;
+        const int r = block_frchol(A, lda, n, tol, cols, &ints[1]);
+        if (tid == 0) rank[b] = r;
+        if (r == 0) {
+            for (int e = tid; e < n * k; e += BT_THREADS) d.W[(e % n) + (long)(e / n) * d.ldw] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        // L must stay readable while C occupies LDS: move it to the slab
+        if (A == big) {
+            for (long e = tid; e < (long)n * n; e += BT_THREADS) Lg[e] = big[e];
+            __syncthreads();
+        }
+        // 3. C = L'L (kept columns), T = L'B
+        double *C = (r <= nl) ? big : Cg;
+        const long ldc = r;
+        block_gram<double>(Lg, n, n, r, cols, true, Bv, n, k, C, ldc, Tv, r, stage);
+        // full symmetric C from its lower triangle
+        for (long e = tid; e < (long)r * r; e += BT_THREADS) {
+            const int i = (int)(e % r), j = (int)(e / r);
+            if (i < j) C[i + (long)j * ldc] = C[j + (long)i * ldc];
+        }
+        __syncthreads();
+        // 4. M = C^-1
+        if (!block_gj(C, ldc, r, rowp, colp) && tid == 0) *status = ST_NOTSPD;
+        // 5. X = M T, T = M X, W = L T
+        for (int e = tid; e < r * k; e += BT_THREADS) {
+            const int i = e % r, q = e / r;
+            double s = 0.0;
+            for (int j = 0; j < r; ++j) s = fma(C[i + (long)j * ldc], Tv[j + (long)q * r], s);
+            Xv[i + (long)q * r] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < r * k; e += BT_THREADS) {
+            const int i = e % r, q = e / r;
+            double s = 0.0;
+            for (int j = 0; j < r; ++j) s = fma(C[i + (long)j * ldc], Xv[j + (long)q * r], s);
+            Tv[i + (long)q * r] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * k; e += BT_THREADS) {
+            const int i = e % n, q = e / n;
+            double s = 0.0;
+            for (int c = 0; c < r && cols[c] <= i; ++c) s = fma(Lg[i + (long)cols[c] * n], Tv[c + (long)q * r], s);
+            d.W[i + (long)q * d.ldw] = s;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_queue_kernel(int *q) {
+    if (threadIdx.x == 0) *q = 0;
+}
+
+size_t batched_lds_bytes(int nl, int nmax, int k) {
+    return sizeof(double) * ((size_t)nl * nl + (size_t)BT_STAGE_ROWS * (nmax + k) + BT_THREADS + 2 * (size_t)nmax) +
+           sizeof(int) * ((size_t)nmax + 4);
+}
+
+size_t batched_slab_doubles(int nmax, int k) {
+    return 2 * (size_t)nmax * nmax + 3 * (size_t)nmax * k;
+}
+
+hipError_t launch_batched(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
+                          double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s) {
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = batched_lds_bytes(nl, nmax, k);
+    hipLaunchKernelGGL(batched_lstsq_kernel, dim3(grid), dim3(BT_THREADS), lds, s,
+                       static_cast<const BatchDesc *>(desc), order, batch, k, tol, nl, queue, slabs,
+                       (long)batched_slab_doubles(nmax, k), nmax, rank, status);
+    return hipGetLastError();
+}
+
+size_t batched_desc_bytes() { return sizeof(BatchDesc); }
+
+void batched_fill_desc(void *out, const float *G, const float *F, double *W, int m, int n, int ldg, int ldf, int ldw) {
+    BatchDesc *d = static_cast<BatchDesc *>(out);
+    d->G = G; d->F = F; d->W = W;
+    d->m = m; d->n = n; d->ldg = ldg; d->ldf = ldf; d->ldw = ldw;
+    d->pad = 0;
+}
+
+}  // namespace geninv

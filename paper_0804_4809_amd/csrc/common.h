@@ -87,4 +87,14 @@ hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, co
                                __bf16 *planes, long ldp, long sp, hipStream_t s);
 hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s);
 
+// batched least squares (batched.hip)
+constexpr int BATCH_NMAX = 256;
+constexpr int BATCH_KMAX = 16;
+hipError_t launch_batched(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
+                          double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s);
+size_t batched_lds_bytes(int nl, int nmax, int k);
+size_t batched_slab_doubles(int nmax, int k);
+size_t batched_desc_bytes();
+void batched_fill_desc(void *out, const float *G, const float *F, double *W, int m, int n, int ldg, int ldf, int ldw);
+
 }  // namespace geninv

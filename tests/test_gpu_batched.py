@@ -1,0 +1,122 @@
+"""GPU parity of the batched least-squares form against the oracle.
+
+The batch holds float32 G_b and F_b; the oracle runs on exactly those values
+upcast to float64, so input rounding is not counted as error.  Ranks must be
+identical (or an ambiguous decision replayed, as in the single-problem
+tests); W_b within 1e-10 relative Frobenius or 10x the oracle's own rounding
+sensitivity on that problem.
+"""
+import numpy as np
+import pytest
+
+from oracle import geninv_ref as o
+from paper_0804_4809_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0804_4809_amd import api  # noqa: E402
+
+FP64_TOL = 1e-10
+
+
+def _edge_problems():
+    rng = np.random.default_rng(5)
+    Gs, Fs = [], []
+    Gs.append(np.zeros((20, 5), np.float32)); Fs.append(rng.standard_normal((20, 4)).astype(np.float32))
+    Gs.append(np.ones((7, 1), np.float32)); Fs.append(rng.standard_normal((7, 4)).astype(np.float32))
+    A = rng.standard_normal((40, 40)).astype(np.float32)
+    Gs.append(A); Fs.append(rng.standard_normal((40, 4)).astype(np.float32))
+    B = rng.standard_normal((300, 10)).astype(np.float32)
+    Gs.append(np.concatenate([B, B[:, :3], B[:, 5:6]], axis=1)); Fs.append(rng.standard_normal((300, 4)).astype(np.float32))
+    C = rng.standard_normal((600, 200)).astype(np.float32) @ rng.standard_normal((200, 256)).astype(np.float32)
+    Gs.append(C); Fs.append(rng.standard_normal((600, 4)).astype(np.float32))
+    return Gs, Fs
+
+
+def _check(plan, Gs, Fs):
+    ranks = plan.rank.cpu().numpy()
+    worst = 0.0
+    for b in range(len(Gs)):
+        G = Gs[b].astype(np.float64)
+        F = Fs[b].astype(np.float64)
+        Wr, ref = o.lstsq(G, F)
+        Wg = plan.W(b).cpu().numpy()
+        assert ranks[b] == ref.rank, (b, ranks[b], ref.rank, G.shape)
+        if ref.rank == 0:
+            assert not Wg.any()
+            continue
+        err = o.rel_fro(Wg, Wr)
+        bound = max(FP64_TOL, 10 * o.self_spread(G, base=ref))
+        assert err <= bound, (b, err, bound, G.shape)
+        worst = max(worst, err)
+    return worst
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batched_edge_cases(use_graph):
+    print(f"[case] batched edge use_graph={use_graph}", flush=True)
+    Gs, Fs = _edge_problems()
+    plan = api.BatchPlan(Gs, Fs)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.run(use_graph=use_graph)
+    torch.cuda.synchronize()
+    _check(plan, Gs, Fs)
+    plan.close()
+
+
+def test_batched_random_uneven_sizes_all_lds_thresholds():
+    print("[case] batched 96 problems", flush=True)
+    B = w.batch_lowrank(96, seed=11, m_hi=600, n_hi=200)
+    plan = api.BatchPlan(B.G, B.F)
+    for nl, grid in [(0, 256), (64, 512), (128, 256)]:
+        plan.config(nl, grid)
+        plan.Wbuf.zero_()
+        plan.run(use_graph=False)
+        torch.cuda.synchronize()
+        worst = _check(plan, B.G, B.F)
+        print(f"  nl={nl} grid={grid} worst relF(W)={worst:.2e}", flush=True)
+    plan.close()
+
+
+def test_batched_graph_replays_match_direct_launch():
+    print("[case] batched graph replay", flush=True)
+    B = w.batch_lowrank(64, seed=12, m_hi=400, n_hi=128)
+    plan = api.BatchPlan(B.G, B.F)
+    plan.run(use_graph=False)
+    torch.cuda.synchronize()
+    W0 = plan.Wbuf.clone()
+    r0 = plan.rank.clone()
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        plan.Wbuf.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.run(use_graph=True)
+        stream.synchronize()
+        assert torch.equal(plan.Wbuf, W0), rep
+        assert torch.equal(plan.rank, r0), rep
+    # the graph follows new inputs written into the same buffers
+    B2 = w.batch_lowrank(64, seed=12, m_hi=400, n_hi=128)
+    plan.load([2.0 * g for g in B2.G], B2.F)
+    with torch.cuda.stream(stream):
+        plan.run(use_graph=True)
+    stream.synchronize()
+    assert torch.allclose(plan.Wbuf * 2.0, W0, rtol=1e-12, atol=0)
+    plan.close()
+
+
+def test_batched_autotune_picks_a_valid_config():
+    print("[case] batched autotune", flush=True)
+    B = w.batch_lowrank(128, seed=13, m_hi=500, n_hi=160)
+    plan = api.BatchPlan(B.G, B.F)
+    nl, grid, ms = plan.autotune(reps=2)
+    assert grid in (256, 512, 768, 1024) and 0 <= nl <= 128 and ms > 0
+    plan.run(use_graph=False)
+    torch.cuda.synchronize()
+    _check(plan, B.G, B.F)
+    plan.close()
