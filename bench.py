@@ -52,13 +52,151 @@ def algorithmic_flops(m: int, n: int, r_before, r: int, k: int = 0) -> float:
     return f
 
 
+def lstsq_flops(m: int, n: int, r: int, k: int) -> float:
+    """Least-squares variant of the model: the chain is replaced by
+    (2mn + 4nr + 4r^2) k for W = L (M (M (L' (G'F)))); the Cholesky term uses
+    r_k = min(k, r), exact for generic exact-rank inputs."""
+    f = m * n * (n + 1.0)
+    f += sum(2.0 * (n - kk) * min(kk, r) for kk in range(n))
+    f += n * r * (r + 1.0) + float(r) ** 3
+    f += (2.0 * m * n + 4.0 * n * r + 4.0 * r * r) * k
+    return f
+
+
+def _timed(fn, steps, sync):
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_mixed(lib, api, workloads, torch, np, steps, with_oracle):
+    """Mixed-precision form vs the float64 form on G = P diag(s) Q'
+    (32768 x 4096, rank 3072, s log-spaced in [1e-3, 1])."""
+    G, _, P, sv, Q = workloads.c3_problem()
+    m, n = G.shape
+    dev = torch.device("cuda", 0)
+    Gd = torch.from_numpy(G).to(dev)
+    Gc, ldg = api.colmajor(Gd)
+    del Gd
+    ctx = api._ctx(dev)
+    vp = ctypes.c_void_p
+    Y64 = api.empty_colmajor(n, m, dev)
+    Ymx = api.empty_colmajor(n, m, dev)
+    piv = torch.empty(n, dtype=torch.int32, device=dev)
+    out = {"workload": "G = P diag(s) Q', m=32768, n=4096, rank 3072, s log-spaced from 1 to 1e-3"}
+
+    def run64():
+        st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, vp(Y64.data_ptr()), n, None, None)
+        assert st == 0, st
+
+    def runmx(cs, ns):
+        def f():
+            st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n, None,
+                                  None)
+            assert st == 0, st
+        return f
+
+    r_c = ctypes.c_int(0)
+    lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, vp(Y64.data_ptr()), n, ctypes.byref(r_c),
+                       vp(piv.data_ptr()))
+    r = r_c.value
+    acc = np.zeros(n, bool)
+    acc[piv[:r].cpu().numpy()] = True
+    r_before = np.concatenate([[0], np.cumsum(acc)[:-1]])
+    flops = algorithmic_flops(m, n, r_before, r)
+    sync = torch.cuda.synchronize
+    run64()
+    t64 = _timed(run64, steps, sync)
+    out["fp64"] = {"ms": round(t64, 3), "tflops": round(flops / t64 / 1e9, 3), "rank": r}
+    Yor = None
+    Ytrue = None
+    if with_oracle:
+        from oracle import geninv_ref as o
+        c0 = time.perf_counter()
+        res = o.geninv(G)
+        out["oracle_seconds"] = round(time.perf_counter() - c0, 2)
+        out["oracle_rank"] = res.rank
+        Yor = res.Y
+        Ytrue = (Q / sv) @ P.T
+        Y64h = Y64.cpu().numpy()
+        out["fp64"]["relF_vs_oracle"] = float(np.linalg.norm(Y64h - Yor) / np.linalg.norm(Yor))
+        del Y64h
+    for cs, ns, key in [(4, 0, "mixed_s4_chain4"), (0, 0, "mixed_s4_chain_fp64"), (4, 1, "mixed_s4_chain4_ns1")]:
+        f = runmx(cs, ns)
+        r2 = ctypes.c_int(0)
+        st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n,
+                              ctypes.byref(r2), None)
+        assert st == 0, st
+        t = _timed(f, steps, sync)
+        d = {"ms": round(t, 3), "tflops_fp64_equivalent": round(flops / t / 1e9, 3), "rank": r2.value,
+             "speedup_vs_fp64": round(t64 / t, 3),
+             "relF_vs_fp64_gpu": float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64))}
+        if Yor is not None:
+            Ym = Ymx.cpu().numpy()
+            d["relF_vs_oracle"] = float(np.linalg.norm(Ym - Yor) / np.linalg.norm(Yor))
+            d["relF_vs_closed_form"] = float(np.linalg.norm(Ym - Ytrue) / np.linalg.norm(Ytrue))
+            del Ym
+        out[key] = d
+    del Gc, Y64, Ymx
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_batched(api, workloads, torch, np, steps, with_oracle):
+    """4096 uneven float32 least-squares problems in one persistent launch,
+    replayed from a HIP graph after autotuning."""
+    B = workloads.c4_problem()
+    plan = api.BatchPlan(B.G, B.F)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        nl, grid, tune_ms = plan.autotune(reps=2)
+        plan.run(use_graph=True)
+        stream.synchronize()
+        t = _timed(lambda: plan.run(use_graph=True), steps, stream.synchronize)
+    ranks = plan.rank.cpu().numpy()
+    flops = sum(lstsq_flops(int(B.m[b]), int(B.n[b]), int(ranks[b]), B.k) for b in range(len(B.G)))
+    out = {"workload": "4096 problems, m ~ U[64,1024], n ~ U[16, min(256, m/2)], rank ~ U[n/2, n], G = U V and "
+                       "F (m x 4) stored in float32, float64 accumulation and pivots",
+           "ms": round(t, 3), "solves_per_s": round(len(B.G) / (t * 1e-3), 1), "tflops": round(flops / t / 1e9, 3),
+           "autotuned": {"lds_threshold": nl, "workgroups": grid, "ms": round(tune_ms, 3)},
+           "rank_equals_construction": int((ranks == B.rank).sum())}
+    if with_oracle:
+        from oracle import geninv_ref as o
+        rng = np.random.default_rng(0)
+        worst = 0.0
+        for b in rng.choice(len(B.G), size=16, replace=False):
+            Wr, ref = o.lstsq(B.G[b].astype(np.float64), B.F[b].astype(np.float64))
+            Wg = plan.W(int(b)).cpu().numpy()
+            worst = max(worst, float(np.linalg.norm(Wg - Wr) / np.linalg.norm(Wr)))
+        out["sampled_16_max_relF_vs_oracle"] = worst
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-forms", action="store_true", help="only the float64 RBF workload")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle checks of the other forms")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
@@ -188,6 +326,12 @@ def main():
                          f"{med:.2f} s each; rank {res.rank}",
                "seconds": round(med, 3)}
 
+    forms = {}
+    if not args.skip_forms:
+        fsteps = max(2, min(args.steps, 5))
+        forms["mixed_vs_fp64"] = bench_mixed(lib, api, workloads, torch, np, fsteps, not args.no_oracle)
+        forms["batched"] = bench_batched(api, workloads, torch, np, max(3, min(args.steps, 10)), not args.no_oracle)
+
     out = {
         "metric": METRIC,
         "value": round(flops / (ms_per_step * 1e-3) / 1e12, 4),
@@ -209,6 +353,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernel_ms_one_step": breakdown,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
 
