@@ -17,6 +17,14 @@ struct Dim {
 };
 
 static inline Dim hdim(int v) { return Dim{v, nullptr}; }
+
+// p[i] if ok, else pad, with an unconditional load (the address falls back to
+// p[0], which must be readable): loads written this way carry no branch, so a
+// loop of them is issued back to back instead of one load and wait at a time.
+__device__ __forceinline__ double ld_or(const double *p, long i, bool ok, double pad) {
+    const double v = p[ok ? i : 0];
+    return ok ? v : pad;
+}
 static inline Dim ddim(int bound, const int *p) { return Dim{bound, p}; }
 
 // Output modes of the GEMM epilogue.

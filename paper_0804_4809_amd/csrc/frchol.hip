@@ -9,15 +9,16 @@
 //   1. panel update (an MFMA GEMM, split over K when the panel is tall and
 //      narrow, gemm.hip): A[k0:n, k0:k0+w] -= L[k0:n, :r0] L[k0:k0+w, :r0]'
 //      over the r0 columns accepted before the panel, written in place;
-//   2. panel factor (this file), one launch, every workgroup:
-//        - loads the updated diagonal block into LDS and factors it column by
-//          column with the paper's strict "pivot > tol" test, keeping
-//          accepted columns only (one wavefront, lane i owning row i);
+//   2. panel factor (this file), one launch of one-wavefront workgroups,
+//      each of which
+//        - factors the updated diagonal block column by column with the
+//          paper's strict "pivot > tol" test, keeping accepted columns only
+//          (lane i owning row i in registers);
 //        - for its own rows below the block, solves for the new L entries by
 //          forward substitution against the accepted columns, in the same
 //          column order as the paper;
-//      workgroup 0 also writes the diagonal block of L, the pivot indices and
-//      the new running rank rank_buf[p+1] = r0 + (accepted in this panel).
+//      workgroup 0 writes the diagonal block of L, the pivot indices and the
+//      new running rank rank_buf[p+1] = r0 + (accepted in this panel).
 //
 // Accepted columns are written compacted (column r0, r0+1, ...), so L comes
 // out n x r with zeros above each column's pivot row.  The running rank lives
@@ -25,9 +26,10 @@
 // so no kernel reads a value another workgroup of the same launch writes.
 #include "common.h"
 
+#include <utility>
+
 namespace geninv {
 
-constexpr int FR_ROWS = 256;   // rows per workgroup in the panel factor (one per thread)
 
 // value of v held by lane l of the wavefront (l a compile-time constant in
 // every use below)
@@ -84,134 +86,203 @@ hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double 
     return hipGetLastError();
 }
 
-// Panel factor.  P points at the updated panel (the rows k0..n-1 of the
-// panel's w columns, leading dimension ldp): A minus the contribution of the
-// columns accepted before the panel.
-__global__ __launch_bounds__(256) void frchol_panel_kernel(const double *__restrict__ P, long ldp,
-                                                           double *__restrict__ L, long ldl, int *rank_buf,
-                                                           int p, int k0, int w, int n, const double *tolp,
-                                                           int *piv, double *dvals) {
-    __shared__ double D[FR_NB][FR_NB + 1];   // D[j][i] = block entry (row i, column j)
-    __shared__ double dpiv[FR_NB];           // updated pivot value of each block column
-    __shared__ int outcol[FR_NB];            // L column of each accepted block column, -1 if dropped
-    __shared__ double rdiag[FR_NB];          // 1 / L(j, j) of each accepted block column
-    __shared__ int nacc;
+// ---- panel factor ---------------------------------------------------------
+//
+// Every workgroup is one wavefront.  Each one factors the diagonal block
+// itself (lane i owning row i in registers, the pivot and the scaled column
+// broadcast lane to lane with v_readlane), so that no workgroup waits for
+// another.  Workgroup 0 then writes the block of L, the pivots and the new
+// rank; every other workgroup solves FR_TRS rows below the block against the
+// accepted columns, four lanes per row.
+//
+// The substitution runs over the accepted columns only, renumbered 0..a-1 in
+// the paper's column order: for row x of the panel restricted to the accepted
+// columns and T the a x a lower triangle of the block at the pivot rows,
+//   x_c <- x_c / T_cc,  then  x_c' -= x_c T_c'c  for c' > c,
+// which is the paper's column-by-column update of these rows.  Lane q of a
+// row holds columns c = 4t + q (t = 0..15); the new x_c is passed within the
+// four lanes by a DPP quad broadcast, and T is read from LDS, laid out so that
+// lane q reads its own 16 entries of a column contiguously.
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+constexpr int FR_TRS = 16;             // rows per workgroup in the substitution
+constexpr int FR_TSEG = 18;            // T row: 4 segments of 18 doubles (16 used): 16-byte aligned, banks spread
+constexpr int FR_TLD = 4 * FR_TSEG;
+constexpr int FR_BC = 16;              // broadcasts in flight per group in the block factorization
+constexpr int FR_CH = 8;               // substitution columns per uniform chunk
+
+// lane (4 (lane / 4) + Q)'s value of v, within each group of four lanes
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, Q * 0x55, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), Q * 0x55, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+struct FrBlock {
+    double row[FR_NB];    // row `lane` of the block (lower triangle), then of L
+    int acc;              // accepted so far (uniform)
+    double mydiag;        // L(lane, lane) if column `lane` is accepted, else 1
+    double mypiv;         // updated pivot value of column `lane`
+    int myc;              // compact index of column `lane` if accepted, else -1
+};
+
+// Column J of the block: the paper's pivot test, then sqrt, scaling and the
+// rank-one update of the later columns (every index static after expansion).
+template <int J>
+__device__ __forceinline__ void fr_column(FrBlock &s, int lane, int w, double tol) {
+    if (J >= w) return;
+    const double d = lane_bcast(s.row[J], J);   // current pivot of column J
+    const bool keep = d > tol;                   // uniform
+    if (lane == J) {
+        s.mypiv = d;
+        s.myc = keep ? s.acc : -1;
+    }
+    if (!keep) return;
+    const double sq = sqrt(d);
+    const double lij = lane > J ? s.row[J] / sq : (lane == J ? sq : 0.0);
+    s.row[J] = lij;
+    if (lane == J) s.mydiag = sq;
+#pragma unroll
+    for (int g = (J + 1) / FR_BC; g < FR_NB / FR_BC; ++g) {
+        // FR_BC broadcasts into distinct scalar registers, then the FMAs
+        double bc[FR_BC];
+#pragma unroll
+        for (int e = 0; e < FR_BC; ++e)
+            if (g * FR_BC + e > J) bc[e] = lane_bcast(lij, g * FR_BC + e);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int e = 0; e < FR_BC; ++e)
+            if (g * FR_BC + e > J) s.row[g * FR_BC + e] -= lij * bc[e];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    ++s.acc;
+}
+
+template <int... J>
+__device__ __forceinline__ void fr_factor(std::integer_sequence<int, J...>, FrBlock &s, int lane, int w,
+                                          double tol) {
+    (fr_column<J>(s, lane, w, tol), ...);
+}
+
+// Compact column J of the substitution (branch-free; J >= a contributes 0).
+template <int J>
+__device__ __forceinline__ void trs_column(double (&x)[16], const double (&rd)[16], int q, int a, const double *tq) {
+    const double xj0 = quad_bcast<J & 3>(x[J >> 2] * rd[J >> 2]);
+    const double xj = J < a ? xj0 : 0.0;
+    const double upd = x[J >> 2] - xj * tq[J * FR_TLD + (J >> 2)];
+    x[J >> 2] = q == (J & 3) ? xj : upd;
+#pragma unroll
+    for (int t = (J >> 2) + 1; t < 16; ++t) x[t] -= xj * tq[J * FR_TLD + t];
+}
+
+template <int G, int... E>
+__device__ __forceinline__ void trs_chunk(std::integer_sequence<int, E...>, double (&x)[16], const double (&rd)[16],
+                                          int q, int a, const double *tq) {
+    if (G * FR_CH >= a) return;   // uniform
+    (trs_column<G * FR_CH + E>(x, rd, q, a, tq), ...);
+}
+
+template <int... G>
+__device__ __forceinline__ void trs_solve(std::integer_sequence<int, G...>, double (&x)[16], const double (&rd)[16],
+                                          int q, int a, const double *tq) {
+    (trs_chunk<G>(std::make_integer_sequence<int, FR_CH>{}, x, rd, q, a, tq), ...);
+}
+
+// P points at the updated panel: rows k0..n-1 of the panel's w columns
+// (leading dimension ldp), A minus the contribution of the columns accepted
+// before the panel.
+__global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restrict__ P, long ldp,
+                                                          double *__restrict__ L, long ldl, int *rank_buf, int p,
+                                                          int k0, int w, int n, const double *tolp, int *piv,
+                                                          double *dvals) {
+    __shared__ __align__(16) double T[FR_NB][FR_TLD];   // T[c][seg(c')] = L(pivot row of c', c), 0 unless c' > c
+    __shared__ double S[FR_TRS][FR_NB + 1];             // row staging for the renumbering of the columns
+    __shared__ double rdc[FR_NB];                       // 1 / L(pivot row of c, c)
+    __shared__ int pcol[FR_NB];                         // block column of compact column c
+
+    const int lane = threadIdx.x;
+    const int q = lane & 3;
     const int r0 = rank_buf[p];
     const double tol = *tolp;
+    const int irel = w + (int)(blockIdx.x - 1) * FR_TRS + (lane >> 2);
+    const bool trs = blockIdx.x > 0 && k0 + irel < n;
 
-    // diagonal block (lower triangle) into LDS
+    // this lane's entries of its row below the block (block column order),
+    // in flight during the factorization
+    double x[16];
 #pragma unroll
-    for (int q = 0; q < FR_NB / 4; ++q) {
-        const int j = wave + 4 * q;
-        if (lane < w && j < w && lane >= j) D[j][lane] = P[lane + (long)j * ldp];
+    for (int t = 0; t < 16; ++t) x[t] = ld_or(P, irel + (long)(4 * t + q) * ldp, trs && 4 * t + q < w, 0.0);
+
+    FrBlock s;
+#pragma unroll
+    for (int l = 0; l < FR_NB; ++l) s.row[l] = ld_or(P, lane + (long)l * ldp, lane < w && l <= lane, 0.0);
+    s.acc = 0;
+    s.mydiag = 1.0;
+    s.mypiv = 0.0;
+    s.myc = -1;
+    if (blockIdx.x > 0) {
+        // zero T, so that the columns of the last chunk past a read zeros
+        double *tf = &T[0][0];
+#pragma unroll
+        for (int e = 0; e < FR_NB * FR_TLD / 64; ++e) tf[e * 64 + lane] = 0.0;
     }
-    __syncthreads();
+    fr_factor(std::make_integer_sequence<int, FR_NB>{}, s, lane, w, tol);
+    const int a = s.acc;
 
-    // one wavefront factors the block column by column; lane i owns row i of
-    // the block in registers (fully unrolled, so every index is static).
-    // The pivot and the scaled column are broadcast lane to lane
-    // (v_readlane), without a round trip through memory.
-    if (wave == 0) {
-        double row[FR_NB];
-#pragma unroll
-        for (int l = 0; l < FR_NB; ++l) row[l] = (lane < w && l <= lane) ? D[l][lane] : 0.0;
-        int acc = 0;
-        double mydiag = 1.0;   // L(lane, lane) once column `lane` is accepted
-#pragma unroll
-        for (int j = 0; j < FR_NB; ++j) {
-            if (j < w) {
-                const double d = lane_bcast(row[j], j);   // current pivot of column j
-                const bool keep = d > tol;                 // the same in every lane: uniform
-                if (lane == 0) {
-                    dpiv[j] = d;
-                    outcol[j] = keep ? r0 + acc : -1;
-                }
-                if (keep) {
-                    const double sq = sqrt(d);
-                    const double lij = lane > j ? row[j] / sq : (lane == j ? sq : 0.0);
-                    row[j] = lij;
-                    if (lane == j) mydiag = sq;
-#pragma unroll
-                    for (int l0 = j + 1; l0 < FR_NB; l0 += 16) {
-#pragma unroll
-                        for (int l = l0; l < l0 + 16 && l < FR_NB; ++l) row[l] -= lij * lane_bcast(lij, l);
-                        __builtin_amdgcn_sched_barrier(0);   // bound the scalar registers in flight
-                    }
-                    ++acc;
-                }
-            }
-        }
-        // factored block back to LDS (lower triangle), reciprocal pivots
-#pragma unroll
-        for (int l = 0; l < FR_NB; ++l)
-            if (lane < w && l <= lane) D[l][lane] = row[l];
-        if (lane < w) rdiag[lane] = 1.0 / mydiag;
-        if (lane == 0) nacc = acc;
-    }
-    __syncthreads();
-
-    // workgroup 0: diagonal block of L, pivots, pivot values, running rank
     if (blockIdx.x == 0) {
+        // diagonal block of L, pivots, pivot values, running rank
+        if (lane < w) {
 #pragma unroll
-        for (int q = 0; q < FR_NB / 4; ++q) {
-            const int j = wave + 4 * q;
-            if (j < w && lane < w && lane >= j) {
-                const int c = outcol[j];
-                if (c >= 0) L[(k0 + lane) + (long)c * ldl] = D[j][lane];
+            for (int j = 0; j < FR_NB; ++j) {
+                const int cj = __builtin_amdgcn_readlane(s.myc, j);   // uniform
+                if (cj >= 0 && j <= lane) L[(k0 + lane) + (long)(r0 + cj) * ldl] = s.row[j];
             }
+            if (dvals) dvals[k0 + lane] = s.mypiv;
+            if (piv && s.myc >= 0) piv[r0 + s.myc] = k0 + lane;
         }
-        if (tid < w) {
-            if (dvals) dvals[k0 + tid] = dpiv[tid];
-            if (piv && outcol[tid] >= 0) piv[outcol[tid]] = k0 + tid;
-        }
-        if (tid == 0) rank_buf[p + 1] = r0 + nacc;
+        if (lane == 0) rank_buf[p + 1] = r0 + a;
+        return;
     }
 
-    // rows below the diagonal block: forward substitution, one row per thread,
-    // in the paper's column order (division by the pivot taken as a product
-    // with its reciprocal, computed once per column)
-    const int irel = blockIdx.x * FR_ROWS + tid;
-    if (irel < w || k0 + irel >= n) return;
-    // keep the row loads below this point: hoisted into the block
-    // factorization they would hold 64 more registers there and spill
-    __builtin_amdgcn_sched_barrier(0);
-    double x[FR_NB];
-    // column base addresses are uniform (scalar registers); only the row
-    // offset is per lane
+    // compact triangle T and the reciprocal pivots, from the registers
 #pragma unroll
     for (int j = 0; j < FR_NB; ++j) {
-        const double *colj = P + (long)j * ldp;
-        x[j] = j < w ? colj[irel] : 0.0;
+        const int cj = __builtin_amdgcn_readlane(s.myc, j);
+        if (cj >= 0 && s.myc >= 0) T[cj][FR_TSEG * (s.myc & 3) + (s.myc >> 2)] = lane > j ? s.row[j] : 0.0;
     }
-    double *lrow = L + (k0 + irel);
-#pragma unroll
-    for (int j = 0; j < FR_NB; ++j) {
-        if (j < w) {
-            const int c = outcol[j];
-            if (c >= 0) {
-                const double xj = x[j] * rdiag[j];
-                lrow[(long)c * ldl] = xj;
-                // groups of 16 broadcast reads, so that the compiler does not
-                // hoist all 63 of them at once and spill x
-#pragma unroll
-                for (int l0 = j + 1; l0 < FR_NB; l0 += 16) {
-#pragma unroll
-                    for (int l = l0; l < l0 + 16 && l < FR_NB; ++l) x[l] -= xj * D[j][l];
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        }
+    if (s.myc >= 0) {
+        rdc[s.myc] = 1.0 / s.mydiag;
+        pcol[s.myc] = lane;
     }
+    // renumber the row's entries to compact column order through LDS
+    const int rl = lane >> 2;
+    if (trs) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            if (4 * t + q < w) S[rl][4 * t + q] = x[t];
+    }
+    __syncthreads();
+    if (!trs) return;
+    double rd[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int c = 4 * t + q;
+        x[t] = c < a ? S[rl][pcol[c]] : 0.0;
+        rd[t] = c < a ? rdc[c] : 0.0;
+    }
+    trs_solve(std::make_integer_sequence<int, FR_NB / FR_CH>{}, x, rd, q, a, &T[0][FR_TSEG * q]);
+    double *lrow = L + (k0 + irel) + (long)r0 * ldl;
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+        if (4 * t + q < a) lrow[(long)(4 * t + q) * ldl] = x[t];
 }
 
 hipError_t launch_frchol_panel(const double *P, long ldp, double *L, long ldl, int *rank_buf, int p, int k0, int w,
                                int n, const double *tol, int *piv, double *dvals, hipStream_t s) {
-    const int rows = n - k0;
-    dim3 grid((rows + FR_ROWS - 1) / FR_ROWS);
-    hipLaunchKernelGGL(frchol_panel_kernel, grid, dim3(256), 0, s, P, ldp, L, ldl, rank_buf, p, k0, w, n, tol, piv,
+    const int below = n - k0 - w;   // rows under the block
+    dim3 grid(1 + (below + FR_TRS - 1) / FR_TRS);
+    hipLaunchKernelGGL(frchol_panel_kernel, grid, dim3(64), 0, s, P, ldp, L, ldl, rank_buf, p, k0, w, n, tol, piv,
                        dvals);
     return hipGetLastError();
 }

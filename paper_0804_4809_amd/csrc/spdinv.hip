@@ -19,6 +19,8 @@
 // read from device memory; steps and tiles past r exit at once.
 #include "common.h"
 
+#include <utility>
+
 namespace geninv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -53,44 +55,99 @@ __device__ __forceinline__ void tile64_mfma(const double (*Xs)[GJ_LD], const dou
     }
 }
 
-// In-LDS Gauss-Jordan inverse of the SPD block in X (column-major X[j][i]),
-// w x w in the top-left corner and identity elsewhere, so that every thread
-// updates a fixed set of elements without bounds tests.  Thread
-// (lane, wave) owns row `lane`, columns wave, wave + 4, ...  Each step is one
-// FMA per element (X -= column p * scaled row p), after which the owners of
-// row p and column p overwrite them.  Returns false (uniformly) if a pivot is
-// not positive.
-__device__ bool gj_invert_block(double (*X)[GJ_LD], int w, double *rowp, double *colp) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    bool ok = true;
-    for (int p = 0; p < w; ++p) {
-        __syncthreads();
-        const double pv = X[p][p];
-        if (!(pv > 0.0)) ok = false;
-        const double dinv = 1.0 / pv;
-        if (tid < GJ_NB) {
-            rowp[tid] = X[tid][p] * dinv;   // row p scaled by the inverse pivot
-            colp[tid] = X[p][tid];          // column p
-        }
-        __syncthreads();
-        const double cp = colp[lane];
-        double v[GJ_NB / 4], rp[GJ_NB / 4];
+// 1 / x for a positive normal x: the hardware estimate refined by two Newton
+// steps (within an ulp or so of the correctly rounded quotient, and a much
+// shorter dependency chain than the IEEE division sequence)
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
 #pragma unroll
-        for (int q = 0; q < GJ_NB / 4; ++q) {
-            v[q] = X[wave + 4 * q][lane];
-            rp[q] = rowp[wave + 4 * q];
-        }
+    for (int it = 0; it < 2; ++it) y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+    return y;
+}
+
+// Gauss-Jordan inverse of the SPD block held in X (column-major X[j][i]),
+// w x w in the top-left corner and identity elsewhere.  The 256 threads form
+// a 16 x 16 grid of 4 x 4 sub-blocks: thread t keeps rows 4 rb .. 4 rb + 3 and
+// columns 4 cb .. 4 cb + 3 (rb = t mod 16, cb = t / 16) in registers for the
+// whole elimination, so that a step needs only 4 entries of the pivot row
+// and 4 of the pivot column per thread (broadcast LDS reads cost the full
+// LDS return bandwidth, so the volume per step is what bounds it).  Those are
+// published through LDS, double buffered by the parity of p (a buffer is
+// rewritten two steps later, after every thread has passed the barrier of
+// the step in between), so one barrier per step suffices.  Step p with
+// d = 1 / X(p, p):
+//   X(i, j) -= X(i, p) d X(p, j)   (i, j != p),   X(p, j) *= d   (j != p),
+//   X(i, p) = -X(i, p) d           (i != p),      X(p, p) = d,
+// written per element as v alpha + X(p, j) beta with (alpha, beta) = (1,
+// -X(i, p) d) off row p and (d, 0) on it.  On return X holds the inverse.
+// Returns false (uniformly) if a pivot is not positive.
+struct GjRegs {
+    double v[4][4];   // v[i][j] = X(4 rb + i, 4 cb + j)
+    bool ok;
+};
+
+template <int P>
+__device__ __forceinline__ void gj_step(GjRegs &g, int w, int rb, int cb, double (*colb)[GJ_NB],
+                                        double (*rowb)[GJ_NB]) {
+    if (P >= w) return;   // identity padding: the remaining steps change nothing
+    constexpr int b = P & 1, pq = P >> 2, pr = P & 3;
+    if (cb == pq) {
 #pragma unroll
-        for (int q = 0; q < GJ_NB / 4; ++q) X[wave + 4 * q][lane] = v[q] - cp * rp[q];
-        if (lane == p) {
+        for (int i = 0; i < 4; ++i) colb[b][4 * rb + i] = g.v[i][pr];   // column p
+    }
+    if (rb == pq) {
 #pragma unroll
-            for (int q = 0; q < GJ_NB / 4; ++q) X[wave + 4 * q][p] = rp[q];
-        }
-        if (wave == (p & 3)) X[p][lane] = lane == p ? dinv : -cp * dinv;
+        for (int j = 0; j < 4; ++j) rowb[b][4 * cb + j] = g.v[pr][j];   // row p
     }
     __syncthreads();
-    return ok;
+    // every LDS read of the step is issued before the reciprocal
+    const double pv = colb[b][P];
+    double cp[4], rp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cp[i] = colb[b][4 * rb + i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rp[j] = rowb[b][4 * cb + j];
+    __builtin_amdgcn_sched_barrier(0);
+    if (!(pv > 0.0)) g.ok = false;
+    const double dinv = recip(pv);
+    const bool prow = rb == pq;   // this thread holds row p (as its row pr)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool onrow = i == pr && prow;
+        const double alpha = onrow ? dinv : 1.0;
+        const double beta = onrow ? 0.0 : -(cp[i] * dinv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g.v[i][j] = __builtin_fma(rp[j], beta, g.v[i][j] * alpha);
+        if (cb == pq) g.v[i][pr] = onrow ? dinv : beta;
+    }
+}
+
+template <int... P>
+__device__ __forceinline__ void gj_steps(std::integer_sequence<int, P...>, GjRegs &g, int w, int rb, int cb,
+                                         double (*colb)[GJ_NB], double (*rowb)[GJ_NB]) {
+    (gj_step<P>(g, w, rb, cb, colb, rowb), ...);
+}
+
+__device__ bool gj_invert_block(double (*X)[GJ_LD], int w) {
+    __shared__ __align__(16) double colb[2][GJ_NB];
+    __shared__ __align__(16) double rowb[2][GJ_NB];
+    const int tid = threadIdx.x;
+    const int rb = tid & 15, cb = tid >> 4;
+    __syncthreads();
+    GjRegs g;
+    g.ok = true;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) g.v[i][j] = X[4 * cb + j][4 * rb + i];
+    gj_steps(std::make_integer_sequence<int, GJ_NB>{}, g, w, rb, cb, colb, rowb);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) X[4 * cb + j][4 * rb + i] = g.v[i][j];
+    __syncthreads();
+    return g.ok;   // uniform: every thread read the same pivots
 }
 
 __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict__ B, long ldb, Dim rd, int b,
@@ -98,7 +155,6 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict_
                                                        double *__restrict__ Ccol, long ldc, int *status) {
     __shared__ double X[GJ_NB][GJ_LD];
     __shared__ double Bl[GJ_NB][GJ_LD];
-    __shared__ double rowp[GJ_NB], colp[GJ_NB];
     const int r = rd.get();
     const int nbk = (r + GJ_NB - 1) / GJ_NB;
     const int jb = blockIdx.x;
@@ -109,17 +165,25 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict_
     const int wj = min(GJ_NB, r - jb * GJ_NB);
     const long ob = (long)b * GJ_NB, oj = (long)jb * GJ_NB;
 
+    // all loads first (no branches), then the LDS and global writes
+    double xb[GJ_NB / 4], cb[GJ_NB / 4], bl[GJ_NB / 4];
 #pragma unroll
     for (int q = 0; q < GJ_NB / 4; ++q) {
         const int jc = wave + 4 * q;
-        const bool in_b = lane < wb && jc < wb;
-        X[jc][lane] = in_b ? B[(ob + lane) + (ob + jc) * ldb] : (lane == jc ? 1.0 : 0.0);
+        xb[q] = ld_or(B, (ob + lane) + (ob + jc) * ldb, lane < wb && jc < wb, lane == jc ? 1.0 : 0.0);
         // old block column (rows of block jb, columns of block b)
-        if (lane < wj && jc < wb) Ccol[(oj + lane) + (long)jc * ldc] = B[(oj + lane) + (ob + jc) * ldb];
+        cb[q] = ld_or(B, (oj + lane) + (ob + jc) * ldb, lane < wj && jc < wb, 0.0);
         // pivot block row restricted to the columns of block jb, zero padded
-        Bl[jc][lane] = (jb != b && lane < wb && jc < wj) ? B[(ob + lane) + (oj + jc) * ldb] : 0.0;
+        bl[q] = ld_or(B, (ob + lane) + (oj + jc) * ldb, jb != b && lane < wb && jc < wj, 0.0);
     }
-    const bool ok = gj_invert_block(X, wb, rowp, colp);
+#pragma unroll
+    for (int q = 0; q < GJ_NB / 4; ++q) {
+        const int jc = wave + 4 * q;
+        X[jc][lane] = xb[q];
+        if (lane < wj && jc < wb) Ccol[(oj + lane) + (long)jc * ldc] = cb[q];
+        Bl[jc][lane] = bl[q];
+    }
+    const bool ok = gj_invert_block(X, wb);
     if (jb == b) {
         if (!ok && tid == 0) *status = ST_NOTSPD;
 #pragma unroll
@@ -182,20 +246,27 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     }
     const bool newcol = jb == b;
     const int wr = newcol ? wb : wj;
+    // right factor: D (new block column) or R_jb
+    const double *Y = newcol ? Dbuf : Rrow + oj * GJ_NB;
+    double xv[GJ_NB / 4], yv[GJ_NB / 4];
 #pragma unroll
     for (int q = 0; q < GJ_NB / 4; ++q) {
         const int kc = wave + 4 * q;
         // left factor: old block column rows of block ib (wi x wb), zero padded
-        Xs[kc][lane] = (lane < wi && kc < wb) ? Ccol[(oi + lane) + (long)kc * ldc] : 0.0;
-        // right factor: D (new block column) or R_jb, zero padded
-        double y = 0.0;
-        if (lane < wb && kc < wr) y = newcol ? Dbuf[lane + (long)kc * GJ_NB] : Rrow[lane + (oj + kc) * GJ_NB];
-        Ys[kc][lane] = y;
+        xv[q] = ld_or(Ccol, (oi + lane) + (long)kc * ldc, lane < wi && kc < wb, 0.0);
+        yv[q] = ld_or(Y, lane + (long)kc * GJ_NB, lane < wb && kc < wr, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < GJ_NB / 4; ++q) {
+        const int kc = wave + 4 * q;
+        Xs[kc][lane] = xv[q];
+        Ys[kc][lane] = yv[q];
     }
     __syncthreads();
     d4 acc[2][2];
     tile64_mfma(Xs, Ys, acc);
     const int wm = wave & 1, wn = wave >> 1;
+    double old[2][2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -204,10 +275,17 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
             for (int v = 0; v < 4; ++v) {
                 const int row = wm * 32 + a * 16 + (lane & 15);
                 const int col = wn * 32 + bb * 16 + (lane >> 4) + 4 * v;
-                if (row < wi && col < wr) {
-                    double *dst = T + row + (long)col * ldb;
-                    *dst = newcol ? -acc[a][bb][v] : *dst - acc[a][bb][v];
-                }
+                old[a][bb][v] = ld_or(T, row + (long)col * ldb, !newcol && row < wi && col < wr, 0.0);
+            }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wm * 32 + a * 16 + (lane & 15);
+                const int col = wn * 32 + bb * 16 + (lane >> 4) + 4 * v;
+                if (row < wi && col < wr) T[row + (long)col * ldb] = old[a][bb][v] - acc[a][bb][v];
             }
 }
 
