@@ -20,7 +20,9 @@
  *   pointers owned by the caller; the library never frees them.
  * - Every call enqueues its kernels on the context's stream and returns
  *   without waiting, except where a HOST output pointer is passed (then the
- *   call waits for the stream before writing it).
+ *   call waits for the stream before writing it) and, by default, once in
+ *   the middle of the whole-method calls to learn the rank
+ *   (geninv_set_host_sync).
  * - The return value is a geninv_status code.  Nothing aborts or prints.
  *   Argument errors are detected on the host before anything is enqueued.
  *   Errors found on the device (non-finite data, a non-SPD L'L) are written
@@ -66,6 +68,17 @@ int geninv_destroy(geninv_ctx *ctx);
 
 /* Switch the stream later calls enqueue on (same device). */
 int geninv_set_stream(geninv_ctx *ctx, void *hip_stream);
+
+/* Whether a call reads the rank back to the host once its full-rank Cholesky
+ * factorization is done (enable != 0, the default) or not (enable == 0).
+ * On: one stream synchronization inside geninv_dgeninv, geninv_dlstsq and
+ * geninv_mixed, after which every later launch (the (L'L)^-1 steps, the
+ * chain products) is sized for the actual rank r.  Off: no host
+ * synchronization inside those calls (e.g. for stream capture or host-side
+ * overlap); the later kernels are then launched for the bound min(m, n) and
+ * read r from device memory, which costs idle launches when r is well below
+ * that bound.  Results are the same either way.  EINVAL for a null ctx. */
+int geninv_set_host_sync(geninv_ctx *ctx, int enable);
 
 /* Wait for the stream and return the device-side status of the calls made
  * since the last geninv_sync_status() (GENINV_OK, ENONFINITE or ENOTSPD);

@@ -36,6 +36,7 @@ _SIGS = [
     ("geninv_create", ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, _VP]),
     ("geninv_destroy", ctypes.c_int, [_VP]),
     ("geninv_set_stream", ctypes.c_int, [_VP, _VP]),
+    ("geninv_set_host_sync", ctypes.c_int, [_VP, ctypes.c_int]),
     ("geninv_sync_status", ctypes.c_int, [_VP]),
     ("geninv_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("geninv_version", ctypes.c_int, []),

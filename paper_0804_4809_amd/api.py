@@ -35,6 +35,13 @@ def _ctx(device: torch.device):
     return c
 
 
+def set_host_sync(enable: bool, device=None):
+    """geninv_set_host_sync on the context of `device` (default: current)."""
+    dev = torch.device("cuda", device if isinstance(device, int) else torch.cuda.current_device()) \
+        if not isinstance(device, torch.device) else device
+    _check(load().geninv_set_host_sync(_ctx(dev), 1 if enable else 0), "geninv_set_host_sync")
+
+
 def _check(st: int, where: str):
     if st != 0:
         raise GeninvError(st, where)

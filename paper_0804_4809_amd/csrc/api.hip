@@ -38,6 +38,8 @@ struct geninv_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int *status = nullptr;     // device status word (separate from the workspace: survives regrowth)
+    int host_sync = 1;         // read the rank back after the factorization (geninv_set_host_sync)
+    int *hpin = nullptr;       // pinned host word for that read-back
     ProfState prof;
 };
 
@@ -303,9 +305,8 @@ int run_spdinv(geninv_ctx *c, const Layout &lay, double *B, long ldb, Dim r) {
 }
 
 // B = L'L (r x r, full) into dst; then M = B^-1 in place.
-int run_factor_inverse(geninv_ctx *c, const Layout &lay, const double *L, long ldl, int nn, const int *rdev,
-                       double *dst, long ldd) {
-    const Dim r = ddim(nn, rdev);
+int run_factor_inverse(geninv_ctx *c, const Layout &lay, const double *L, long ldl, int nn, Dim r, double *dst,
+                       long ldd) {
     GemmArgs g = gemm(L, ldl, 1, L, ldl, 0, dst, ldd, r, r, hdim(nn), 1.0, 0.0, GEMM_LOWER);
     {
         ProfScope ps(c, PC_LTL, 0.0);
@@ -316,6 +317,25 @@ int run_factor_inverse(geninv_ctx *c, const Layout &lay, const double *L, long l
         HIPCHK(launch_mirror_lower(dst, ldd, r, c->stream));
     }
     return run_spdinv(c, lay, dst, ldd, r);
+}
+
+// The rank after the factorization as a launch dimension.  With host
+// synchronization on (the default) it is copied to the host, one stream
+// synchronization, and every later launch is sized for it exactly: no
+// Gauss-Jordan step, tile or GEMM block past r is launched.  With it off the
+// later kernels are launched for the bound nn and read r from device memory
+// (no host synchronization inside the call, e.g. for stream capture).
+int rank_dim(geninv_ctx *c, int nn, const int *rdev, Dim *out) {
+    if (!c->host_sync) {
+        *out = ddim(nn, rdev);
+        return GENINV_OK;
+    }
+    HIPCHK(hipMemcpyAsync(c->hpin, rdev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int r = *c->hpin;
+    if (r < 0 || r > nn) return GENINV_EHIP;
+    *out = hdim(r);
+    return GENINV_OK;
 }
 
 int finish_rank(geninv_ctx *c, const int *rdev, int *rank) {
@@ -451,6 +471,13 @@ int geninv_create(geninv_ctx **ctx, int device, void *hip_stream) {
         delete c;
         return GENINV_EHIP;
     }
+    void *h = nullptr;
+    if (hipHostMalloc(&h, 64, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(p);
+        delete c;
+        return GENINV_ENOMEM;
+    }
+    c->hpin = static_cast<int *>(h);
     *ctx = c;
     return GENINV_OK;
 }
@@ -463,7 +490,14 @@ int geninv_destroy(geninv_ctx *c) {
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     if (c->ws) (void)hipFree(c->ws);
     if (c->status) (void)hipFree(c->status);
+    if (c->hpin) (void)hipHostFree(c->hpin);
     delete c;
+    return GENINV_OK;
+}
+
+int geninv_set_host_sync(geninv_ctx *c, int enable) {
+    if (!c) return GENINV_EINVAL;
+    c->host_sync = enable ? 1 : 0;
     return GENINV_OK;
 }
 
@@ -608,9 +642,10 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     // 2-3. tolerance and full-rank Cholesky
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, pv, at<double>(c, lay.dvals)));
     const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
-    const Dim r = ddim(nn, rdev);
+    Dim r;
+    CHK(rank_dim(c, nn, rdev, &r));
     // 4. M = (L'L)^-1 into the Gram's slot
-    CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
+    CHK(run_factor_inverse(c, lay, L, ld, nn, r, A, ld));
     // 5. K = L M, P = K K' (= (G'G)^+), then Y = P G' or Y = G' P
     {
         ProfScope ps(c, PC_CHAIN_K, 0.0);
@@ -662,8 +697,9 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
     CHK(run_gram(c, lay, G, ldg, false, nn, m));
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, at<int>(c, lay.piv), at<double>(c, lay.dvals)));
     const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
-    const Dim r = ddim(nn, rdev);
-    CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
+    Dim r;
+    CHK(rank_dim(c, nn, rdev, &r));
+    CHK(run_factor_inverse(c, lay, L, ld, nn, r, A, ld));
     if (k > 0) {
         // W = L (M (M (L' (G' F))))
         ProfScope ps(c, PC_LSTSQ, 0.0);
@@ -761,8 +797,9 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
     // 2-4. tolerance, full-rank Cholesky, (L'L)^-1 in float64
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, pv, at<double>(c, lay.dvals)));
     const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
-    const Dim r = ddim(nn, rdev);
-    CHK(run_factor_inverse(c, lay, L, ld, nn, rdev, A, ld));
+    Dim r;
+    CHK(rank_dim(c, nn, rdev, &r));
+    CHK(run_factor_inverse(c, lay, L, ld, nn, r, A, ld));
     // 5. K = L M, P = K K' (float64)
     {
         ProfScope ps(c, PC_CHAIN_K, 0.0);

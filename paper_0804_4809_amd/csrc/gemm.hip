@@ -171,6 +171,20 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     const long ldc = p.ldc;
     const double alpha = p.alpha, beta = p.beta;
     const bool raw = p.splitk > 1;
+    const bool with_c = !raw && beta != 0.0;   // uniform
+    // the old values of C first, all in flight together, then the stores
+    d4 cold[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+        const int r = row0 + wm * TM + a * 16 + (lane & 15);
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = col0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
+                cold[a][b][v] = ld_or(C, r + (long)c * ldc, with_c && r < M && c < N && (!lower || r >= c), 0.0);
+            }
+    }
 #pragma unroll
     for (int a = 0; a < FM; ++a) {
         const int r = row0 + wm * TM + a * 16 + (lane & 15);
@@ -180,10 +194,8 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
             for (int v = 0; v < 4; ++v) {
                 const int c = col0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
                 if (r < M && c < N && (!lower || r >= c)) {
-                    double *dst = C + r + (long)c * ldc;
                     const double val = tot[a][b][v];
-                    if (raw) *dst = val;
-                    else *dst = (beta != 0.0) ? alpha * val + beta * (*dst) : alpha * val;
+                    C[r + (long)c * ldc] = raw ? val : (with_c ? alpha * val + beta * cold[a][b][v] : alpha * val);
                 }
             }
         }
@@ -303,10 +315,14 @@ __global__ void mirror_lower_kernel(double *X, long ldx, Dim nd) {
     const int bi = blockIdx.x, bj = blockIdx.y;    // source tile (bi, bj) with bi >= bj
     if (bi < bj) return;
     const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
-    for (int yy = ty; yy < 32; yy += 8) {
-        const int i = bi * 32 + tx, j = bj * 32 + yy;
-        t[yy][tx] = (i < n && j < n) ? X[i + (long)j * ldx] : 0.0;
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = bi * 32 + tx, j = bj * 32 + ty + 8 * q;
+        v[q] = ld_or(X, i + (long)j * ldx, i < n && j < n, 0.0);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) t[ty + 8 * q][tx] = v[q];
     __syncthreads();
     // destination (j, i) for source (i, j) with i > j
     for (int yy = ty; yy < 32; yy += 8) {

@@ -228,19 +228,21 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     const long oi = (long)ib * GJ_NB, oj = (long)jb * GJ_NB;
     double *T = B + oi + oj * ldb;
 
-    if (ib == b && jb == b) {
-#pragma unroll
-        for (int q = 0; q < GJ_NB / 4; ++q) {
-            const int jc = wave + 4 * q;
-            if (lane < wb && jc < wb) T[lane + (long)jc * ldb] = Dbuf[lane + (long)jc * GJ_NB];
-        }
-        return;
-    }
     if (ib == b) {
+        // row block b: D on the diagonal tile, R_jb elsewhere (loads first)
+        const bool diag = jb == b;
+        const double *src = diag ? Dbuf : Rrow + oj * GJ_NB;
+        const int wc = diag ? wb : wj;
+        double t[GJ_NB / 4];
 #pragma unroll
         for (int q = 0; q < GJ_NB / 4; ++q) {
             const int jc = wave + 4 * q;
-            if (lane < wb && jc < wj) T[lane + (long)jc * ldb] = Rrow[lane + (oj + jc) * GJ_NB];
+            t[q] = ld_or(src, lane + (long)jc * GJ_NB, lane < wb && jc < wc, 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) {
+            const int jc = wave + 4 * q;
+            if (lane < wb && jc < wc) T[lane + (long)jc * ldb] = t[q];
         }
         return;
     }
@@ -248,7 +250,10 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     const int wr = newcol ? wb : wj;
     // right factor: D (new block column) or R_jb
     const double *Y = newcol ? Dbuf : Rrow + oj * GJ_NB;
-    double xv[GJ_NB / 4], yv[GJ_NB / 4];
+    const int wm = wave & 1, wn = wave >> 1;
+    // every load first: both factors and the tile's old values (unless it is
+    // overwritten), so that they are all in flight together
+    double xv[GJ_NB / 4], yv[GJ_NB / 4], old[2][2][4];
 #pragma unroll
     for (int q = 0; q < GJ_NB / 4; ++q) {
         const int kc = wave + 4 * q;
@@ -256,17 +261,6 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
         xv[q] = ld_or(Ccol, (oi + lane) + (long)kc * ldc, lane < wi && kc < wb, 0.0);
         yv[q] = ld_or(Y, lane + (long)kc * GJ_NB, lane < wb && kc < wr, 0.0);
     }
-#pragma unroll
-    for (int q = 0; q < GJ_NB / 4; ++q) {
-        const int kc = wave + 4 * q;
-        Xs[kc][lane] = xv[q];
-        Ys[kc][lane] = yv[q];
-    }
-    __syncthreads();
-    d4 acc[2][2];
-    tile64_mfma(Xs, Ys, acc);
-    const int wm = wave & 1, wn = wave >> 1;
-    double old[2][2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -277,6 +271,15 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
                 const int col = wn * 32 + bb * 16 + (lane >> 4) + 4 * v;
                 old[a][bb][v] = ld_or(T, row + (long)col * ldb, !newcol && row < wi && col < wr, 0.0);
             }
+#pragma unroll
+    for (int q = 0; q < GJ_NB / 4; ++q) {
+        const int kc = wave + 4 * q;
+        Xs[kc][lane] = xv[q];
+        Ys[kc][lane] = yv[q];
+    }
+    __syncthreads();
+    d4 acc[2][2];
+    tile64_mfma(Xs, Ys, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll

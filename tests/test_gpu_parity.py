@@ -334,3 +334,37 @@ def test_geninv_c2_full_size():
     # the GPU's least-squares residual is no larger than the oracle's, up to
     # the method's own rounding sensitivity on this input
     assert rg <= rr * (1.0 + 10 * spread)
+
+
+@pytest.mark.parametrize("case", ["c1", "lowrank_1000x300_r200", "wide_300x700_r120", "zero", "lstsq_3000x257"])
+def test_host_sync_off_matches_on(case):
+    """Device-resident rank (every later launch sized for the bound) gives the
+    same results as the default host read-back (launches sized exactly)."""
+    _print_case("host sync off vs on", case=case)
+    if case == "c1":
+        G, F = w.c1_problem(0)
+    elif case == "lowrank_1000x300_r200":
+        G, F = w.lowrank_uv(1000, 300, 200, 1, k=3)
+    elif case == "wide_300x700_r120":
+        G, F = w.lowrank_uv(300, 700, 120, 6)
+    elif case == "zero":
+        G, F = np.zeros((90, 70)), np.ones((90, 2))
+    else:
+        G, F = w.lowrank_uv(3000, 257, 180, 3005, k=5)
+    out = {}
+    try:
+        for on in (True, False):
+            api.set_host_sync(on, DEV)
+            if case.startswith("lstsq"):
+                W, r = api.lstsq(up(G), up(F))
+                out[on] = (down(W), r)
+            else:
+                Y, r = api.geninv(up(G))
+                out[on] = (down(Y), r)
+    finally:
+        api.set_host_sync(True, DEV)
+    (Xa, ra), (Xb, rb) = out[True], out[False]
+    assert ra == rb
+    scale = max(np.abs(Xa).max(), 1e-300)
+    print(f"  rank {ra}; max |on - off| / max |on| = {np.abs(Xa - Xb).max() / scale:.3e}", flush=True)
+    assert np.abs(Xa - Xb).max() <= 1e-13 * scale
