@@ -11,7 +11,10 @@
 // (64 lanes each); each wavefront owns (BM/WM) x (BN/WN) and issues
 // v_mfma_f64_16x16x4_f64 on 16 x 16 blocks.  K is consumed in chunks of BK
 // staged through double-buffered LDS; the next chunk's global loads are in
-// flight while the current chunk feeds the matrix cores.
+// flight while the current chunk feeds the matrix cores.  Operands are read
+// as 16-byte pairs from per-thread 32-bit offsets computed once, against a
+// chunk origin that is the only thing that moves (few vector instructions per
+// load: the address arithmetic was what held the matrix cores back).
 //
 // Two-level summation: the matrix-core accumulators only ever hold the sum
 // over KFLUSH consecutive k; they are then added into a second set of
@@ -29,24 +32,51 @@
 // result element (i, j) in lane j + 16 (i % 4), accumulator slot i / 4.
 #include "common.h"
 
+#include <cstdint>
+#include <cstdlib>
+
 namespace geninv {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int KFLUSH = 256;
 
-template <int BM, int BN, int BK, int WM, int WN>
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Operand staging: the tile (TI rows of the output dimension, BK of k) is
+// read in pairs of consecutive doubles, along the output dimension for an
+// "MN-major" operand (A not transposed, B transposed) or along k for a
+// "K-major" one, and stored to LDS as [k][index].  An MN-major pair is one
+// 16-byte LDS write (row pitch TI + 4, 16-byte aligned); a K-major pair is
+// transposed on the way in with two 8-byte writes (odd pitch TI + 1, so that
+// the lanes of a wavefront hit different banks).
+template <bool KMAJ, int TI, int BK>
+struct Stage {
+    static constexpr int LD = KMAJ ? TI + 1 : TI + 4;
+    static constexpr int PAIRS = TI * BK / 2;
+    __device__ static __forceinline__ int idx(int c) { return KMAJ ? c / (BK / 2) : 2 * (c % (TI / 2)); }
+    __device__ static __forceinline__ int kk(int c) { return KMAJ ? 2 * (c % (BK / 2)) : c / (TI / 2); }
+    // memory offset (doubles) of element (index i, k) from the tile's origin
+    __device__ static __forceinline__ long off(int i, int k, long ld) { return KMAJ ? k + (long)i * ld : i + (long)k * ld; }
+    // the pair's second element
+    __device__ static __forceinline__ int i2(int i) { return KMAJ ? i : i + 1; }
+    __device__ static __forceinline__ int k2(int k) { return KMAJ ? k + 1 : k; }
+};
+
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     constexpr int NT = WM * WN * 64;
     constexpr int TM = BM / WM, TN = BN / WN;
     constexpr int FM = TM / 16, FN = TN / 16;
-    constexpr int LA = BM + 1, LB = BN + 1;   // one double of padding per LDS row
-    constexpr int EA = BM * BK / NT, EB = BN * BK / NT;
-    static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile/thread mismatch");
+    using SA = Stage<TA, BM, BK>;    // A stored K x M (k contiguous) when transposed
+    using SB = Stage<!TB, BN, BK>;   // B stored K x N (k contiguous) when not transposed
+    constexpr int LA = SA::LD, LB = SB::LD;
+    constexpr int PA = SA::PAIRS / NT, PB = SB::PAIRS / NT;   // pairs per thread per chunk
+    static_assert(PA * NT == SA::PAIRS && PB * NT == SB::PAIRS, "tile/thread mismatch");
     static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
 
-    __shared__ double As[2][BK][LA];
-    __shared__ double Bs[2][BK][LB];
+    __shared__ __align__(16) double As[2][BK][LA];
+    __shared__ __align__(16) double Bs[2][BK][LB];
 
     const int M = p.M.get(), N = p.N.get(), K = p.K.get();
     const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
@@ -68,50 +98,76 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     const double *__restrict__ A = p.A;
     const double *__restrict__ B = p.B;
     const long lda = p.lda, ldb = p.ldb;
-    const int tA = p.transA, tB = p.transB;
 
-    double ra[EA], rb[EB];
+    // Fast path (uniform): whole tile inside C, 16-byte aligned operands and
+    // 32-bit offsets within a chunk.  Each thread's pair offsets relative to
+    // the chunk origin are then computed once; a chunk only moves the
+    // (scalar) origin.
+    const bool aligned = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
+                         ((lda | ldb) & 1) == 0;
+    const bool small_off = (TA ? (long)BM * lda : (long)BK * lda) < (1L << 30) &&
+                           (TB ? (long)BK * ldb : (long)BN * ldb) < (1L << 30);
+    const bool interior = aligned && small_off && row0 + BM <= M && col0 + BN <= N;
+    int aoff[PA], boff[PB], alds[PA], blds[PB];
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+        const int c = tid + NT * q;
+        aoff[q] = (int)SA::off(SA::idx(c), SA::kk(c), lda);
+        alds[q] = SA::kk(c) * LA + SA::idx(c);
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+        const int c = tid + NT * q;
+        boff[q] = (int)SB::off(SB::idx(c), SB::kk(c), ldb);
+        blds[q] = SB::kk(c) * LB + SB::idx(c);
+    }
 
-    // element e of a chunk -> (row-or-col index, k index), chosen so that
-    // consecutive threads read consecutive addresses of global memory
-    auto a_idx = [&](int e, int &i, int &k) {
-        if (!tA) { i = e % BM; k = e / BM; } else { k = e % BK; i = e / BK; }
-    };
-    auto b_idx = [&](int e, int &j, int &k) {
-        if (tB) { j = e % BN; k = e / BN; } else { k = e % BK; j = e / BK; }
-    };
+    d2 ra[PA], rb[PB];
     auto gload = [&](int kc) {
+        if (interior && kc + BK <= kend) {
+            const double *a0 = A + SA::off(row0, kc, lda);
+            const double *b0 = B + SB::off(col0, kc, ldb);
 #pragma unroll
-        for (int q = 0; q < EA; ++q) {
-            int i, k;
-            a_idx(tid + NT * q, i, k);
-            const int gi = row0 + i, gk = kc + k;
-            double v = 0.0;
-            if (gi < M && gk < kend) v = tA ? A[gk + (long)gi * lda] : A[gi + (long)gk * lda];
-            ra[q] = v;
-        }
+            for (int q = 0; q < PA; ++q) ra[q] = *reinterpret_cast<const d2 *>(a0 + aoff[q]);
 #pragma unroll
-        for (int q = 0; q < EB; ++q) {
-            int j, k;
-            b_idx(tid + NT * q, j, k);
-            const int gj = col0 + j, gk = kc + k;
-            double v = 0.0;
-            if (gj < N && gk < kend) v = tB ? B[gj + (long)gk * ldb] : B[gk + (long)gj * ldb];
-            rb[q] = v;
+            for (int q = 0; q < PB; ++q) rb[q] = *reinterpret_cast<const d2 *>(b0 + boff[q]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < PA; ++q) {
+                const int c = tid + NT * q;
+                const int i = row0 + SA::idx(c), k = kc + SA::kk(c);
+                ra[q].x = ld_or(A, SA::off(i, k, lda), i < M && k < kend, 0.0);
+                ra[q].y = ld_or(A, SA::off(SA::i2(i), SA::k2(k), lda), SA::i2(i) < M && SA::k2(k) < kend, 0.0);
+            }
+#pragma unroll
+            for (int q = 0; q < PB; ++q) {
+                const int c = tid + NT * q;
+                const int j = col0 + SB::idx(c), k = kc + SB::kk(c);
+                rb[q].x = ld_or(B, SB::off(j, k, ldb), j < N && k < kend, 0.0);
+                rb[q].y = ld_or(B, SB::off(SB::i2(j), SB::k2(k), ldb), SB::i2(j) < N && SB::k2(k) < kend, 0.0);
+            }
         }
     };
     auto sstore = [&](int buf) {
+        double *as = &As[buf][0][0];
+        double *bs = &Bs[buf][0][0];
 #pragma unroll
-        for (int q = 0; q < EA; ++q) {
-            int i, k;
-            a_idx(tid + NT * q, i, k);
-            As[buf][k][i] = ra[q];
+        for (int q = 0; q < PA; ++q) {
+            if (TA) {
+                as[alds[q]] = ra[q].x;
+                as[alds[q] + LA] = ra[q].y;
+            } else {
+                *reinterpret_cast<d2 *>(as + alds[q]) = ra[q];
+            }
         }
 #pragma unroll
-        for (int q = 0; q < EB; ++q) {
-            int j, k;
-            b_idx(tid + NT * q, j, k);
-            Bs[buf][k][j] = rb[q];
+        for (int q = 0; q < PB; ++q) {
+            if (!TB) {
+                bs[blds[q]] = rb[q].x;
+                bs[blds[q] + LB] = rb[q].y;
+            } else {
+                *reinterpret_cast<d2 *>(bs + blds[q]) = rb[q];
+            }
         }
     };
 
@@ -202,13 +258,21 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     }
 }
 
-template <int BM, int BN, int BK, int WM, int WN>
-static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s) {
+template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+static hipError_t launch_cfg_t(const GemmArgs &a, hipStream_t s) {
     const int S = a.splitk > 1 ? a.splitk : 1;
     dim3 grid((a.M.host + BM - 1) / BM, (a.N.host + BN - 1) / BN, S);
     if (grid.x == 0 || grid.y == 0) return hipSuccess;
-    hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, WM, WN>), grid, dim3(WM * WN * 64), 0, s, a);
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, WM, WN, TA, TB>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
+}
+
+template <int BM, int BN, int BK, int WM, int WN>
+static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s) {
+    if (a.transA) return a.transB ? launch_cfg_t<BM, BN, BK, WM, WN, true, true>(a, s)
+                                  : launch_cfg_t<BM, BN, BK, WM, WN, true, false>(a, s);
+    return a.transB ? launch_cfg_t<BM, BN, BK, WM, WN, false, true>(a, s)
+                    : launch_cfg_t<BM, BN, BK, WM, WN, false, false>(a, s);
 }
 
 long gemm_tiles(const GemmArgs &a, int bm) {
@@ -222,7 +286,7 @@ hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s) {
     if (a.M.host <= 0 || a.N.host <= 0) return hipSuccess;
     // 128 x 128 tiles (8 wavefronts) when they alone fill the 256 compute
     // units; 64 x 64 tiles otherwise
-    if (gemm_tiles(a, 128) >= 256 && a.K.host >= 128) return launch_cfg<128, 128, 16, 4, 2>(a, s);
+    if (gemm_tiles(a, 128) >= 256 && a.K.host >= 128) return launch_cfg<128, 128, 32, 4, 2>(a, s);
     return launch_cfg<64, 64, 16, 2, 2>(a, s);
 }
 
