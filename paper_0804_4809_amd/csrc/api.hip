@@ -121,10 +121,19 @@ void prof_resolve(geninv_ctx *c) {
 // Workspace carve-up for a problem whose factored dimension is nn (the
 // smaller of m, n) with k right-hand sides.
 struct Layout {
-    size_t slotA, slotL, slotK, slotP, part, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, total;
+    size_t slotA, slotL, slotK, slotP, part, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, gpart, total;
+    int gram_splits;   // split-K factor of the float64 Gram matrix (partials in gpart)
 };
 
-Layout make_layout(int nn, int k) {
+constexpr size_t GPART_MAX_BYTES = size_t(2) << 30;   // bound on the Gram's split-K partials
+
+long lower_tiles128(int nn) {
+    const long t = (nn + 127) / 128;
+    return t * (t + 1) / 2;
+}
+
+// kdim: depth of the float64 Gram product (0 when the call forms none)
+Layout make_layout(int nn, int k, int kdim = 0) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -148,6 +157,14 @@ Layout make_layout(int nn, int k) {
     L.t0 = take((size_t)nn * std::max(k, 1) * sizeof(double));
     L.t1 = take((size_t)nn * std::max(k, 1) * sizeof(double));
     L.t2 = take((size_t)nn * std::max(k, 1) * sizeof(double));
+    L.gram_splits = 1;
+    L.gpart = 0;
+    if (kdim > 0 && nn > 0) {
+        const size_t n2 = (size_t)nn * nn * sizeof(double);
+        const int cap = (int)std::max<size_t>(1, std::min<size_t>(16, GPART_MAX_BYTES / n2));
+        L.gram_splits = choose_splits(lower_tiles128(nn), kdim, cap);
+        if (L.gram_splits > 1) L.gpart = take(L.gram_splits * n2);
+    }
     L.total = off;
     return L;
 }
@@ -214,24 +231,26 @@ int gemm_splitk(geninv_ctx *c, const Layout &lay, GemmArgs g, int min_tiles = 25
 }
 
 // Step 1: lower triangle of A = op(G)' op(G) (nn x nn, ld nn) into slotA.
-// When the 128 x 128 tiling would leave compute units idle, K is split in two
-// with the partial Grams in the (still unused) chain slots K and P, then summed.
+// The lower triangle has few 128 x 128 tiles for its depth (kdim = m), so K is
+// split (choose_splits: whole rounds of 256 workgroups) with the partial
+// Grams in gpart, then summed in a fixed order.
 int run_gram(geninv_ctx *c, const Layout &lay, const double *G, long ldg, bool tr, int nn, int kdim) {
     double *A = at<double>(c, lay.slotA);
     GemmArgs g = tr ? gemm(G, ldg, 0, G, ldg, 1, A, nn, hdim(nn), hdim(nn), hdim(kdim), 1.0, 0.0, GEMM_LOWER)
                     : gemm(G, ldg, 1, G, ldg, 0, A, nn, hdim(nn), hdim(nn), hdim(kdim), 1.0, 0.0, GEMM_LOWER);
     ProfScope ps(c, PC_GRAM, (double)kdim * nn * (nn + 1.0));
-    if (gemm_tiles(g, 128) >= 256 || kdim < 2048 || gemm_tiles(g, 128) * 2 < 128) {
+    const int S = lay.gram_splits;
+    if (S <= 1) {
         HIPCHK(launch_dgemm(g, c->stream));
         return GENINV_OK;
     }
-    const long stride = (long)((lay.slotP - lay.slotK) / sizeof(double));
-    g.C = at<double>(c, lay.slotK);
+    const long stride = (long)nn * nn;
+    g.C = at<double>(c, lay.gpart);
     g.ldc = nn;
-    g.splitk = 2;
+    g.splitk = S;
     g.strideC = stride;
     HIPCHK(launch_dgemm(g, c->stream));
-    HIPCHK(launch_splitk_reduce(g.C, nn, stride, 2, A, nn, hdim(nn), hdim(nn), 1.0, 0.0, GEMM_LOWER, c->stream));
+    HIPCHK(launch_splitk_reduce(g.C, nn, stride, S, A, nn, hdim(nn), hdim(nn), 1.0, 0.0, GEMM_LOWER, c->stream));
     return GENINV_OK;
 }
 
@@ -522,7 +541,7 @@ int geninv_sync_status(geninv_ctx *c) {
 
 size_t geninv_workspace_bytes(int m, int n, int k) {
     if (m <= 0 || n <= 0 || k < 0) return 0;
-    return make_layout(std::min(m, n), k).total;
+    return make_layout(std::min(m, n), k, std::max(m, n)).total;
 }
 
 int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, double alpha, const double *A,
@@ -628,7 +647,7 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     DeviceGuard g(c->device);
     const bool tr = m < n;              // Appendix: factor G G' when m < n
     const int nn = tr ? m : n;
-    const Layout lay = make_layout(nn, 0);
+    const Layout lay = make_layout(nn, 0, tr ? n : m);
     CHK(ensure_ws(c, lay.total));
     double *A = at<double>(c, lay.slotA);
     double *L = at<double>(c, lay.slotL);
@@ -685,7 +704,7 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
     if (k > 4096) return GENINV_ENOTSUP;
     DeviceGuard g(c->device);
     const int nn = n;
-    const Layout lay = make_layout(nn, k);
+    const Layout lay = make_layout(nn, k, m);
     CHK(ensure_ws(c, lay.total));
     double *A = at<double>(c, lay.slotA);
     double *L = at<double>(c, lay.slotL);

@@ -63,6 +63,47 @@ struct Stage {
     __device__ static __forceinline__ int k2(int k) { return KMAJ ? k + 1 : k; }
 };
 
+// Tiles of the launch: every tile of C for a full product, the tiles on or
+// below the diagonal for GEMM_LOWER; counted from the launch bounds M.host,
+// N.host.  The grid is one-dimensional over exactly these tiles (blockIdx.y =
+// split-K slice): the hardware deals workgroups to the 8 XCDs in turn, so a
+// grid with idle tiles interleaved (the upper triangle) leaves the XCDs with
+// unequal work, and in-order dispatch then stalls every XCD behind the
+// busiest one.
+template <int BM, int BN>
+__host__ __device__ inline long tiles_of(const GemmArgs &p) {
+    const long tm = (p.M.host + BM - 1) / BM, tn = (p.N.host + BN - 1) / BN;
+    if (p.uplo != GEMM_LOWER) return tm * tn;
+    // columns by = 0 .. tn-1 of the lower triangle hold tm - by tiles each (BM == BN)
+    const long t = tn < tm ? tn : tm;
+    return t * tm - t * (t - 1) / 2;
+}
+
+// Workgroup -> tile: the linear ids a single XCD receives (id mod 8) are
+// given one contiguous run of the tile order, which goes down the columns of
+// C (tile column by fixed, row bx running), so that the workgroups resident
+// on one XCD share operand panels in its L2.
+template <int BM, int BN>
+__device__ __forceinline__ void tile_of(const GemmArgs &p, int &bx, int &by) {
+    const long T = gridDim.x;
+    const long lin = blockIdx.x;
+    const long q = T / 8, rem = T % 8, x = lin % 8;
+    long t = x * q + (x < rem ? x : rem) + lin / 8;
+    const int tm = (p.M.host + BM - 1) / BM;
+    if (p.uplo != GEMM_LOWER) {
+        bx = (int)(t % tm);
+        by = (int)(t / tm);
+        return;
+    }
+    int c = 0;
+    while (t >= tm - c) {
+        t -= tm - c;
+        ++c;
+    }
+    by = c;
+    bx = c + (int)t;
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     constexpr int NT = WM * WN * 64;
@@ -79,17 +120,18 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     __shared__ __align__(16) double Bs[2][BK][LB];
 
     const int M = p.M.get(), N = p.N.get(), K = p.K.get();
-    const int row0 = blockIdx.x * BM, col0 = blockIdx.y * BN;
+    int bx, by;
+    tile_of<BM, BN>(p, bx, by);
+    const int row0 = bx * BM, col0 = by * BN;
     if (row0 >= M || col0 >= N) return;
-    if (p.uplo == GEMM_LOWER && col0 >= row0 + BM) return;
 
     int kbeg = 0, kend = K;
     double *C = p.C;
     if (p.splitk > 1) {
         const int chunk = (((K + p.splitk - 1) / p.splitk) + BK - 1) / BK * BK;
-        kbeg = blockIdx.z * chunk;
+        kbeg = blockIdx.y * chunk;
         kend = min(K, kbeg + chunk);
-        C += (long)blockIdx.z * p.strideC;
+        C += (long)blockIdx.y * p.strideC;
     }
 
     const int tid = threadIdx.x;
@@ -260,9 +302,11 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
 
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 static hipError_t launch_cfg_t(const GemmArgs &a, hipStream_t s) {
+    static_assert(BM == BN, "square tiles (the lower-triangle walk assumes them)");
     const int S = a.splitk > 1 ? a.splitk : 1;
-    dim3 grid((a.M.host + BM - 1) / BM, (a.N.host + BN - 1) / BN, S);
-    if (grid.x == 0 || grid.y == 0) return hipSuccess;
+    const long T = tiles_of<BM, BN>(a);
+    if (T <= 0) return hipSuccess;
+    dim3 grid((unsigned)T, S);
     hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, WM, WN, TA, TB>), grid, dim3(WM * WN * 64), 0, s, a);
     return hipGetLastError();
 }
@@ -275,10 +319,32 @@ static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s) {
                     : launch_cfg_t<BM, BN, BK, WM, WN, false, false>(a, s);
 }
 
+// Split-K factor for an output of `tiles` 128 x 128 tiles (one workgroup per
+// compute unit at a time, so launches run in rounds of 256 tiles) and depth
+// K: the time is about rounds(S) x K / S chunk-steps plus the reduction of the
+// S partial results.  Every split keeps at least 256 of K (a whole flush
+// period of the two-level summation).  A small launch pays for its last,
+// partly idle round; splitting K fills it.
+int choose_splits(long tiles, int K, int maxS) {
+    const double chunk_us = 4.5;      // one 128 x 128 x 32 chunk of one workgroup
+    const double reduce_us = 0.035;   // reading and adding one partial 128 x 128 tile
+    int best = 1;
+    double bestc = 1e300;
+    for (int S = 1; S <= maxS; ++S) {
+        const long kper = ((long)(K + S - 1) / S + 31) / 32 * 32;
+        if (S > 1 && kper < 256) break;
+        const long rounds = (tiles * S + 255) / 256;
+        const double c = rounds * (kper / 32) * chunk_us + (S > 1 ? (S + 1) * tiles * reduce_us : 0.0);
+        if (c < bestc * 0.98) {
+            bestc = c;
+            best = S;
+        }
+    }
+    return best;
+}
+
 long gemm_tiles(const GemmArgs &a, int bm) {
-    const long tm = (a.M.host + bm - 1) / bm, tn = (a.N.host + bm - 1) / bm;
-    long t = tm * tn;
-    if (a.uplo == GEMM_LOWER) t = (tm * (tm + 1)) / 2 + (tn > tm ? 0 : 0);
+    const long t = bm == 128 ? tiles_of<128, 128>(a) : tiles_of<64, 64>(a);
     return t * (a.splitk > 1 ? a.splitk : 1);
 }
 
