@@ -165,13 +165,16 @@ int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, d
  * cores as exact products of 8-bit operand slices (the error-free splitting of
  * Ozaki, Ogita, Oishi and Rump): every column of G (every row of P and G in the
  * chain) is scaled by a power of two and cut into `slices` signed 8-bit
- * integer slices; every pair of slices is multiplied exactly (float32
- * accumulation over chunks of 256, float64 totals).  The Gram matrix is thus
- * the exactly rounded Gram matrix of the 8*slices-bit representation of G.
+ * integer slices; every pair of slices is multiplied exactly (float32 sums
+ * of each weight class over 32 values of k, exact integers, moved into float64
+ * totals).  The Gram matrix is thus the exactly rounded Gram matrix of the
+ * 8*slices-bit representation of G (a truncated pair set would not be the
+ * Gram matrix of any matrix, and a rank-deficient G would turn its
+ * first-order error in the null space into a large error in G^+).
  * The tolerance, the pivot decisions, the Cholesky factor and (L'L)^-1 are
  * float64, as in geninv_dgeninv.
- *   slices        1..6, slices of G in the Gram matrix (4: 32-bit representation)
- *   chain_slices  0..6, slices of P and G in Y = P G'; 0 evaluates it in float64
+ *   slices        1..4, slices of G in the Gram matrix (4: 32-bit representation)
+ *   chain_slices  0..4, slices of P and G in Y = P G'; 0 evaluates it in float64
  *   ns_steps      >= 0 Newton-Schulz steps X <- X (2I - G X), taken in the
  *                 factored form P <- 2P - P A P (X = P G') in float64 with the
  *                 sliced Gram matrix A
@@ -188,8 +191,8 @@ int geninv_mixed(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double
 int geninv_bslice(geninv_ctx *ctx, int rows, int cols, const double *X, int ldx, int slices,
                   int transposed, void *planes, int ldp, int *e);
 
-/* Lower triangle of the sliced Gram matrix G_s'G_s (n x n, lda >= n), as used by
- * geninv_mixed, for parity testing. */
+/* Lower triangle of the sliced Gram matrix G_s'G_s (n x n, lda >= n) exactly
+ * as geninv_mixed forms it (slices 1..4), for parity testing. */
 int geninv_bgram(geninv_ctx *ctx, int m, int n, const double *G, int ldg, int slices, double *A, int lda);
 
 /* ---- batched least squares ---------------------------------------------- */

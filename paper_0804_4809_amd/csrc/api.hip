@@ -377,8 +377,13 @@ bool bad_ld(long ld, int rows) { return ld < std::max(1, rows); }
 inline long pad64(long x) { return (x + 63) / 64 * 64; }
 
 struct MixedLayout {
-    size_t gc, gt, pc, ecg, erg, ep, gram, total;
+    size_t gc, gt, pc, ecg, erg, ep, gram, gpart, total;
+    size_t gpart_elems;
 };
+
+SlicedGemmArgs sliced(const __bf16 *A, long lda, long sa, const __bf16 *B, long ldb, long sb, int S, const int *ea,
+                      const int *eb, double *C, long ldc, int M, int N, int Kpad, int lower);
+int sliced_splits(const SlicedGemmArgs &g, int maxS);
 
 // extra workspace of the mixed form, placed after the float64 layout
 MixedLayout make_mixed_layout(size_t base, int m, int n, int s, int sy, bool keep_gram) {
@@ -396,33 +401,64 @@ MixedLayout make_mixed_layout(size_t base, int m, int n, int s, int sy, bool kee
     L.erg = take((size_t)m * sizeof(int));
     L.ep = take((size_t)n * sizeof(int));
     L.gram = keep_gram ? take((size_t)n * n * sizeof(double)) : 0;
+    // split-K partials of the sliced Gram matrix
+    {
+        SlicedGemmArgs g = sliced(nullptr, 0, 0, nullptr, 0, 0, s, nullptr, nullptr, nullptr, 0, n, n,
+                                  (int)pad64(m), 1);
+        const size_t n2 = (size_t)n * n;
+        const int cap = (int)std::max<size_t>(1, std::min<size_t>(16, GPART_MAX_BYTES / (n2 * sizeof(double))));
+        const int S = sliced_splits(g, cap);
+        L.gpart_elems = S > 1 ? S * n2 : 0;
+        L.gpart = S > 1 ? take(L.gpart_elems * sizeof(double)) : 0;
+    }
     L.total = off;
     return L;
 }
 
-SlicedGemmArgs sliced(const __bf16 *A, long lda, long sa, int sA, const __bf16 *B, long ldb, long sb, int sB,
-                      const int *ea, const int *eb, double *C, long ldc, int M, int N, int Kpad, int lower) {
+SlicedGemmArgs sliced(const __bf16 *A, long lda, long sa, const __bf16 *B, long ldb, long sb, int S, const int *ea,
+                      const int *eb, double *C, long ldc, int M, int N, int Kpad, int lower) {
     SlicedGemmArgs g{};
     g.A = A; g.lda = lda; g.sa = sa;
     g.B = B; g.ldb = ldb; g.sb = sb;
     g.ea = ea; g.eb = eb;
     g.C = C; g.ldc = ldc;
     g.M = M; g.N = N; g.Kpad = Kpad;
+    g.S = S;
     g.lower = lower;
     g.beta = 0.0;
-    int np = 0;
-    // every slice pair, most significant first
-    for (int sum = 0; sum <= (sA - 1) + (sB - 1); ++sum)
-        for (int t = 0; t < sA; ++t) {
-            const int u = sum - t;
-            if (u < 0 || u >= sB) continue;
-            g.pt[np] = t;
-            g.pu[np] = u;
-            g.pw[np] = std::ldexp(1.0, -8 * (t + u + 2));
-            ++np;
-        }
-    g.npairs = np;
+    g.splitk = 1;
+    g.strideC = 0;
     return g;
+}
+
+// Split-K factor of a sliced product (one 128 x 64 workgroup per compute unit
+// at a time; 32-deep stages of about 0.6 us at 4 slices).
+int sliced_splits(const SlicedGemmArgs &g, int maxS) {
+    const long tiles = sliced_tiles(g.M, g.N, g.lower);
+    const int S = choose_splits(tiles, g.Kpad, maxS);   // rounds of 256 workgroups
+    return std::max(1, S);
+}
+
+// C = sliced product, split over K into `part` (S partial results of M x N,
+// scaled) and summed when that fills the compute units better.
+int run_sliced(geninv_ctx *c, SlicedGemmArgs g, double *part, size_t part_elems) {
+    const size_t mn = (size_t)g.M * g.N;
+    const int cap = (int)std::max<size_t>(1, std::min<size_t>(16, part ? part_elems / std::max<size_t>(mn, 1) : 1));
+    const int S = g.beta == 0.0 ? sliced_splits(g, cap) : 1;
+    if (S <= 1) {
+        HIPCHK(launch_sliced_gemm(g, c->stream));
+        return GENINV_OK;
+    }
+    double *C = g.C;
+    const long ldc = g.ldc;
+    g.C = part;
+    g.ldc = g.M;
+    g.splitk = S;
+    g.strideC = (long)mn;
+    HIPCHK(launch_sliced_gemm(g, c->stream));
+    HIPCHK(launch_splitk_reduce(part, g.M, (long)mn, S, C, ldc, hdim(g.M), hdim(g.N), 1.0, 0.0,
+                                g.lower ? GEMM_LOWER : GEMM_FULL, c->stream));
+    return GENINV_OK;
 }
 
 }  // namespace
@@ -750,7 +786,7 @@ int geninv_bslice(geninv_ctx *c, int rows, int cols, const double *X, int ldx, i
 }
 
 int geninv_bgram(geninv_ctx *c, int m, int n, const double *G, int ldg, int slices, double *A, int lda) {
-    if (!c || m < 0 || n < 0 || slices < 1 || slices > 6) return GENINV_EINVAL;
+    if (!c || m < 0 || n < 0 || slices < 1 || slices > SG_MAX_S) return GENINV_EINVAL;
     if (n == 0) return GENINV_OK;
     if (!A || bad_ld(lda, n) || (m > 0 && (!G || bad_ld(ldg, m)))) return GENINV_EINVAL;
     DeviceGuard g(c->device);
@@ -765,15 +801,15 @@ int geninv_bgram(geninv_ctx *c, int m, int n, const double *G, int ldg, int slic
     }
     HIPCHK(launch_col_exponents(G, ldg, m, n, ecg, c->stream));
     HIPCHK(launch_slice_cols(G, ldg, m, n, ecg, slices, Gc, mp, mp * n, c->stream));
-    ProfScope ps(c, PC_GRAM, (double)slices * slices * m * n * (n + 1.0));
-    HIPCHK(launch_sliced_gemm(sliced(Gc, mp, mp * n, slices, Gc, mp, mp * n, slices, ecg, ecg, A, lda, n, n, (int)mp, 1),
-                              c->stream));
-    return GENINV_OK;
+    ProfScope ps(c, PC_GRAM, 0.5 * slices * (slices + 1) * (double)m * n * (n + 1.0));
+    return run_sliced(c, sliced(Gc, mp, mp * n, Gc, mp, mp * n, slices, ecg, ecg, A, lda, n, n, (int)mp, 1),
+                      ml.gpart ? at<double>(c, ml.gpart) : nullptr, ml.gpart_elems);
 }
 
 int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double tol, int slices, int chain_slices,
                  int ns_steps, double *Y, int ldy, int *rank, int *piv) {
-    if (!c || m < 0 || n < 0 || slices < 1 || slices > 6 || chain_slices < 0 || chain_slices > 6 || ns_steps < 0)
+    if (!c || m < 0 || n < 0 || slices < 1 || slices > SG_MAX_S || chain_slices < 0 || chain_slices > SG_MAX_S ||
+        ns_steps < 0)
         return GENINV_EINVAL;
     if (m == 0 || n == 0) {
         if (rank) *rank = 0;
@@ -804,8 +840,8 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
     }
     {
         ProfScope ps(c, PC_GRAM, (double)m * nn * (nn + 1.0));
-        HIPCHK(launch_sliced_gemm(sliced(Gc, mp, mp * n, slices, Gc, mp, mp * n, slices, ecg, ecg, A, ld, n, n,
-                                         (int)mp, 1), c->stream));
+        CHK(run_sliced(c, sliced(Gc, mp, mp * n, Gc, mp, mp * n, slices, ecg, ecg, A, ld, n, n, (int)mp, 1),
+                       ml.gpart ? at<double>(c, ml.gpart) : nullptr, ml.gpart_elems));
     }
     double *Gram = nullptr;
     if (ns_steps > 0) {
@@ -855,8 +891,8 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
             HIPCHK(launch_slice_cols(P, ld, nn, nn, ep, chain_slices, Pc, np, np * nn, c->stream));
         }
         ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
-        HIPCHK(launch_sliced_gemm(sliced(Pc, np, np * nn, chain_slices, Gt, np, np * m, chain_slices, ep, erg, Y, ldy,
-                                         n, m, (int)np, 0), c->stream));
+        CHK(run_sliced(c, sliced(Pc, np, np * nn, Gt, np, np * m, chain_slices, ep, erg, Y, ldy, n, m, (int)np, 0),
+                       nullptr, 0));
     } else {
         ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
         HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));

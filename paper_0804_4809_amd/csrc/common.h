@@ -42,18 +42,18 @@ struct GemmArgs {
 };
 
 // Sliced (error-free split) GEMM on bfloat16 matrix cores, ozaki.hip.
-constexpr int SG_MAX_PAIRS = 36;
+constexpr int SG_MAX_S = 4;     // slices per operand (registers of the class loop)
 struct SlicedGemmArgs {
     const __bf16 *A; long lda; long sa;   // opA(i, k) = A[t sa + k + i lda]
     const __bf16 *B; long ldb; long sb;   // opB(k, j) = B[u sb + k + j ldb]
     const int *ea; const int *eb;         // row exponents of opA, column exponents of opB
     double *C; long ldc;
     int M, N, Kpad;                       // Kpad: multiple of 64, zero padded in the planes
-    int npairs;
-    int pt[SG_MAX_PAIRS], pu[SG_MAX_PAIRS];
-    double pw[SG_MAX_PAIRS];              // 2^(-8 (t + u + 2))
+    int S;                                // slices of both operands (every pair is formed)
     int lower;
     double beta;
+    int splitk;                           // > 1: raw scaled partial sums to C + z strideC
+    long strideC;
 };
 
 // Device status word values (match geninv_status).
@@ -95,6 +95,7 @@ hipError_t launch_slice_cols(const double *X, long ldx, int rows, int cols, cons
 hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, const int *e, int nslices,
                                __bf16 *planes, long ldp, long sp, hipStream_t s);
 hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s);
+long sliced_tiles(int M, int N, int lower);   // workgroups of one sliced-GEMM split
 
 // batched least squares (batched.hip)
 constexpr int BATCH_NMAX = 256;

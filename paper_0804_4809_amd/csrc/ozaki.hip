@@ -9,18 +9,26 @@
 // slice is an integer of magnitude <= 255, exact in bfloat16, and a product of
 // two slices is an integer <= 255^2, exact in float32.
 //
-// Sliced product: C_ij = 2^(ea_i + eb_j) sum over slice pairs (t, u) of
-// 2^(-8 (t+u+2)) (A_t B_u)_ij.  Each pair product runs on
-// v_mfma_f32_16x16x32_bf16 in float32; after at most 256 values of k the
-// partial sum (|.| <= 256 * 255^2 < 2^24) is still an exactly represented
-// integer, so it is moved into a float64 total (scaled by the exact power of
-// two of its pair) and the float32 accumulator restarts.  Every integer
-// product is therefore exact and only the float64 totals round.
+// Sliced product: C_ij = 2^(ea_i + eb_j) sum over every slice pair (t, u) of
+// 2^(-8 (t+u+2)) (A_t B_u)_ij.  Every pair is needed: with all pairs the
+// result is the exact product of the sliced operands, so a sliced Gram
+// matrix is still the Gram matrix of a matrix (the representation of G) and
+// keeps its (near) null space; a truncated pair set perturbs that null space
+// to first order, which a rank-deficient G turns into a large error in G^+.
+// The pairs of one weight class c = t + u share a float32 accumulator on
+// v_mfma_f32_16x16x32_bf16; a class of p pairs stays an exactly represented
+// integer (below 2^24) while p * 255^2 * k_span < 2^24; the kernel moves it
+// into a float64 total (scaled by its class's exact power of two) every 192
+// values of k for one pair, 96 for two and 64 for three or four.  Every
+// integer product and class sum is therefore exact and only the float64
+// totals round.
 //
 // Both operands are stored K-contiguous ("TN"): opA(i, k) = A_t[k + i lda],
 // opB(k, j) = B_u[k + j ldb], planes `sa` / `sb` elements apart, with the K
 // extent padded with zeros to a multiple of 64 by the slicing kernels.
 #include "common.h"
+
+#include <utility>
 
 namespace geninv {
 
@@ -125,119 +133,306 @@ __global__ __launch_bounds__(256) void slice_rows_t_kernel(const double *X, long
 
 // ---------------------------------------------------------------------------
 // sliced GEMM
+//
+// A workgroup (8 wavefronts, 4 x 2) owns a 128 x 64 tile of C; a wavefront
+// owns 32 x 32 (2 x 2 MFMA blocks).  K is taken 32 at a time: the 32-wide
+// slab of every slice of both operands (S x 192 rows of 64 bytes) goes
+// straight from global memory into LDS (global_load_lds_dwordx4, double
+// buffered: the next stage's loads are in flight while the current one
+// runs), and each wavefront then forms every slice pair from its registers.
+// Such a load writes 16 consecutive bytes per lane, a wavefront a 1 KiB
+// chunk of 16 rows; the four 16-byte granules of row r sit in the chunk
+// XOR-permuted by (r / 4) mod 4, so that the operand reads (16 rows, one
+// granule) meet distinct banks.  The grid is one-dimensional over the needed tiles
+// (lower triangle for the Gram matrix), with the tile order of the float64
+// GEMM (each XCD a contiguous run down the columns of C).
 // ---------------------------------------------------------------------------
-constexpr int SG_BM = 128, SG_BN = 128, SG_BK = 64;
-constexpr int SG_WM = 4, SG_WN = 2;              // 8 wavefronts, each 32 x 64
-constexpr int SG_LDK = SG_BK + 8;                // LDS row pitch (bf16), breaks bank conflicts
-constexpr int SG_FLUSH = 256;                    // k values per exact float32 chunk
+constexpr int SG_BM = 128, SG_BN = 64, SG_BK = 32;
+constexpr int SG_ROWS = SG_BM + SG_BN;    // LDS rows per slice per stage: A rows, then B rows
+constexpr int SG_CHUNKS = SG_ROWS / 16;  // 1 KiB LDS chunks (16 rows of 64 bytes) per slice per stage
+constexpr int SG_NT = 512;
+constexpr int SG_GM = 8;                  // tile rows per group of the tile order
 
-__global__ __launch_bounds__(512) void sliced_gemm_kernel(SlicedGemmArgs p) {
-    constexpr int NT = 512;
-    constexpr int TM = SG_BM / SG_WM, TN = SG_BN / SG_WN;   // 32 x 64
-    constexpr int FM = TM / 16, FN = TN / 16;               // 2 x 4 blocks
-    __shared__ __attribute__((aligned(16))) __bf16 As[2][SG_BM][SG_LDK];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][SG_BN][SG_LDK];
+// tiles of a launch: all of C, or those meeting the lower triangle (row tile
+// bx reaches column tiles by < 2 bx + 2, as BM = 2 BN)
+__host__ __device__ inline long sg_tiles(int M, int N, int lower) {
+    const long tm = (M + SG_BM - 1) / SG_BM, tn = (N + SG_BN - 1) / SG_BN;
+    if (!lower) return tm * tn;
+    long t = 0;
+    for (long r = 0; r < tm; ++r) t += 2 * r + 2 < tn ? 2 * r + 2 : tn;
+    return t;
+}
 
-    const int row0 = blockIdx.x * SG_BM, col0 = blockIdx.y * SG_BN;
-    if (p.lower && col0 >= row0 + SG_BM) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % SG_WM, wn = wave / SG_WM;
+// Weight class c = t + u of s-slice operands: its pair count, and the
+// number of 32-deep stages after which its float32 sum is moved to float64.
+// The sum stays an exact integer while pairs * 32 * stages * 255^2 < 2^24;
+// the kernel runs in cycles of 6 stages (its 3 LDS buffers twice over) and
+// flushes one pair every 6 stages, two pairs every 3 and three or four pairs
+// every 2.  Every class is also flushed at the end of a range.
+constexpr int SG_CYCLE = 6;
+__host__ __device__ constexpr int sg_pairs(int S, int c) {
+    return (c < S ? c + 1 : 2 * S - 1 - c);
+}
+__host__ __device__ constexpr int sg_period(int S, int c) {
+    return sg_pairs(S, c) == 1 ? 6 : (sg_pairs(S, c) == 2 ? 3 : 2);
+}
+static_assert(1 * 32 * 6 * 255 * 255 < (1 << 24) && 2 * 32 * 3 * 255 * 255 < (1 << 24) &&
+                  4 * 32 * 2 * 255 * 255 < (1 << 24),
+              "class periods must keep float32 class sums exact");
 
-    // global -> register staging: each thread moves two 16-byte chunks per operand
-    uint4 ra[2], rb[2];
-    auto gload = [&](const __bf16 *A, const __bf16 *B, int k0) {
+template <int S, int C>
+__device__ __forceinline__ void sg_flush_class(f4 (&acc)[2 * S - 1][2][2], double (&tot)[2][2][4]) {
+    const double w = __builtin_bit_cast(double, (unsigned long long)(1023 - 8 * (C + 2)) << 52);   // 2^(-8 (C+2))
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + NT * q;
-            const int r = c >> 3, kc = (c & 7) * 8;
-            const int gi = row0 + r, gj = col0 + r;
-            ra[q] = gi < p.M ? *reinterpret_cast<const uint4 *>(A + (long)gi * p.lda + k0 + kc) : uint4{0, 0, 0, 0};
-            rb[q] = gj < p.N ? *reinterpret_cast<const uint4 *>(B + (long)gj * p.ldb + k0 + kc) : uint4{0, 0, 0, 0};
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tot[a][b][v] = fma(w, (double)acc[C][a][b][v], tot[a][b][v]);
+            acc[C][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+}
+
+// after stage J of a run (or every class when `all`)
+template <int S, int J, int... C>
+__device__ __forceinline__ void sg_flush_due(std::integer_sequence<int, C...>, bool all, f4 (&acc)[2 * S - 1][2][2],
+                                             double (&tot)[2][2][4]) {
+    ((((J + 1) % sg_period(S, C) == 0 || all) ? sg_flush_class<S, C>(acc, tot) : void()), ...);
+}
+
+// one wavefront-wide direct load: 16 bytes per lane from g into LDS at
+// l + 16 * lane (l uniform across the wavefront)
+__device__ __forceinline__ void lds_load16(const void *g, void *l) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
+}
+
+// wait until at most N of this wavefront's vector memory loads are pending
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// workgroup barrier for the stage buffers: this wavefront's LDS reads have
+// returned, then s_barrier.  Unlike __syncthreads() it does not wait for
+// every outstanding vector load, so direct loads of later stages stay in
+// flight; each wavefront waits for the loads the next stage reads itself.
+__device__ __forceinline__ void stage_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int S>
+__global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
+    // three stage buffers (loads run two stages ahead), separate arrays so
+    // that reads of one need not wait for the direct loads into another
+    __shared__ __align__(1024) char Ls0[S * SG_ROWS * 64];
+    __shared__ __align__(1024) char Ls1[S * SG_ROWS * 64];
+    __shared__ __align__(1024) char Ls2[S * SG_ROWS * 64];
+
+    // workgroup -> tile: each XCD gets a contiguous run of the tile order, and
+    // the order walks groups of SG_GM tile rows, column by column inside a
+    // group, so that the ~32 tiles resident on one XCD form a block of about
+    // SG_GM x 4 tiles sharing their operand panels in its L2
+    const int tm = (p.M + SG_BM - 1) / SG_BM;
+    const int tn = (p.N + SG_BN - 1) / SG_BN;
+    int bx = 0, by = 0;
+    {
+        const long T = gridDim.x, lin = blockIdx.x;
+        const long q = T / 8, rem = T % 8, x = lin % 8;
+        long t = x * q + (x < rem ? x : rem) + lin / 8;
+        int g0 = 0;
+        for (;;) {   // the group holding tile t
+            const int g1 = min(g0 + SG_GM, tm);
+            long cnt = 0;
+            for (int r = g0; r < g1; ++r) cnt += p.lower ? min(2 * r + 2, tn) : tn;
+            if (t < cnt) break;
+            t -= cnt;
+            g0 = g1;
+        }
+        const int g1 = min(g0 + SG_GM, tm);
+        for (int c = 0;; ++c) {   // column c of the group: rows reaching it
+            const int lo = p.lower ? max(g0, c / 2) : g0;
+            const int rows = g1 - lo;
+            if (t < rows) {
+                bx = lo + (int)t;
+                by = c;
+                break;
+            }
+            t -= rows;
+        }
+    }
+    const int row0 = bx * SG_BM, col0 = by * SG_BN;
+
+    const int nst_all = p.Kpad / SG_BK;
+    int st0 = 0, st1 = nst_all;
+    double *C = p.C;
+    if (p.splitk > 1) {
+        const int per = (nst_all + p.splitk - 1) / p.splitk;
+        st0 = blockIdx.y * per;
+        st1 = min(nst_all, st0 + per);
+        C += (long)blockIdx.y * p.strideC;
+    }
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave & 3, wn = wave >> 2;
+
+    // Direct loads of a stage: chunk q (slice q / 12; A rows for the first 8
+    // chunks of a slice, B rows for the last 4) is loaded by wavefront q % 8.
+    // Lane l fills row l / 4 of its chunk, slot l % 4, with granule
+    // (l % 4) ^ (l / 16).  Rows past M (N) are read clamped: they only reach
+    // rows (columns) of C that are never stored.
+    constexpr int NCH = S * SG_CHUNKS;
+    constexpr int CPW = (NCH + 7) / 8;   // chunks per wavefront
+    // per chunk: a uniform base (operand and slice) and this lane's element
+    // offset inside the slice plane (below 2^32: planes hold < 2^32 elements)
+    unsigned srcoff[CPW];
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) {
+        const int q = wave + 8 * i < NCH ? wave + 8 * i : wave;
+        const int cq = q % SG_CHUNKS;
+        const int r = (cq % 8) * 16 + (lane >> 2);
+        const int g = (lane & 3) ^ (lane >> 4);
+        srcoff[i] = cq < 8 ? (unsigned)((long)min(row0 + r, p.M - 1) * p.lda + 8 * g)
+                           : (unsigned)((long)min(col0 + r, p.N - 1) * p.ldb + 8 * g);
+    }
+    auto chunk_base = [&](int i) {
+        const int q = wave + 8 * i < NCH ? wave + 8 * i : wave;
+        const int t = q / SG_CHUNKS, cq = q % SG_CHUNKS;
+        return cq < 8 ? p.A + (long)t * p.sa : p.B + (long)t * p.sb;
+    };
+    auto dma = [&](int st, char *buf) {
+        const long k0 = (long)st * SG_BK;
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) {
+            // a wavefront without an i-th chunk reloads its first one (same
+            // bytes to the same place), so every wavefront issues CPW loads
+            const int q = NCH % 8 == 0 || wave + 8 * i < NCH ? wave + 8 * i : wave;
+            lds_load16(chunk_base(i) + k0 + srcoff[i], buf + q * 1024);
         }
     };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + NT * q;
-            const int r = c >> 3, kc = (c & 7) * 8;
-            *reinterpret_cast<uint4 *>(&As[buf][r][kc]) = ra[q];
-            *reinterpret_cast<uint4 *>(&Bs[buf][r][kc]) = rb[q];
-        }
-    };
 
-    double tot[FM][FN][4];
+    f4 acc[2 * S - 1][2][2];
+    double tot[2][2][4];
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b)
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int c = 0; c < 2 * S - 1; ++c) acc[c][a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) tot[a][b][v] = 0.0;
-
-    const int nst = p.Kpad / SG_BK;
-    constexpr int FLUSH_ST = SG_FLUSH / SG_BK;
-    for (int pr = 0; pr < p.npairs; ++pr) {
-        const __bf16 *A = p.A + (long)p.pt[pr] * p.sa;
-        const __bf16 *B = p.B + (long)p.pu[pr] * p.sb;
-        const double w = p.pw[pr];
-        f4 acc[FM][FN];
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-#pragma unroll
-            for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-        gload(A, B, 0);
-        sstore(0);
-        __syncthreads();
-        for (int st = 0; st < nst; ++st) {
-            const int buf = st & 1;
-            const bool more = st + 1 < nst;
-            if (more) gload(A, B, (st + 1) * SG_BK);
-#pragma unroll
-            for (int kk = 0; kk < SG_BK; kk += 32) {
-                const int ko = kk + 8 * (lane >> 4);
-                bf8 af[FM], bfr[FN];
-#pragma unroll
-                for (int a = 0; a < FM; ++a)
-                    af[a] = *reinterpret_cast<const bf8 *>(&As[buf][wm * TM + a * 16 + (lane & 15)][ko]);
-#pragma unroll
-                for (int b = 0; b < FN; ++b)
-                    bfr[b] = *reinterpret_cast<const bf8 *>(&Bs[buf][wn * TN + b * 16 + (lane & 15)][ko]);
-#pragma unroll
-                for (int a = 0; a < FM; ++a)
-#pragma unroll
-                    for (int b = 0; b < FN; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[b], af[a], acc[a][b], 0, 0, 0);
-            }
-            if ((st + 1) % FLUSH_ST == 0 || !more) {
-#pragma unroll
-                for (int a = 0; a < FM; ++a)
-#pragma unroll
-                    for (int b = 0; b < FN; ++b) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) tot[a][b][v] = fma(w, (double)acc[a][b][v], tot[a][b][v]);
-                        acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-                    }
-            }
-            if (more) sstore(buf ^ 1);
-            __syncthreads();
         }
+
+    // stage st from LDS buffer B: every slice pair, A slices one at a time
+    // (all B slices held), into the pair's weight class
+    // Per-lane LDS read offsets of the wavefront's A and B blocks (lane l:
+    // row l % 16 of a 16-row block, granule l / 16), computed once and kept
+    // opaque, so that every fragment address is one array plus this offset
+    // plus a constant: the compiler then still sees which stage buffer a read
+    // touches, and does not make it wait for loads into the other buffers.
+    int rda = (wm * 32 + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ ((lane >> 2) & 3));
+    int rdb = rda + (SG_BM + wn * 32 - wm * 32) * 64;
+    asm volatile("" : "+v"(rda), "+v"(rdb));
+    auto compute = [&](const char *buf) {
+        bf8 bfr[S][2];
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                bfr[u][b] = *reinterpret_cast<const bf8 *>(buf + rdb + (u * SG_ROWS + b * 16) * 64);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            bf8 af[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                af[a] = *reinterpret_cast<const bf8 *>(buf + rda + (t * SG_ROWS + a * 16) * 64);
+#pragma unroll
+            for (int u = 0; u < S; ++u)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[t + u][a][b] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[u][b], af[a], acc[t + u][a][b], 0, 0, 0);
+        }
+    };
+    // Stage st: start the loads of stage st + 2 (clamped to the last stage of
+    // the range: the extra loads land in a buffer no later stage reads),
+    // compute stage st, flush the classes whose period ends, wait until this
+    // wavefront's loads of stage st + 1 have landed (those of st + 2 may stay
+    // in flight), barrier.  Full cycles of 6 stages run with their buffers and
+    // flushes fixed at compile time; the last nst % 6 stages flush every class.
+    auto buf_of = [&](auto bc) -> char * {
+        constexpr int b = decltype(bc)::value;
+        if constexpr (b == 0) return Ls0;
+        else if constexpr (b == 1) return Ls1;
+        else return Ls2;
+    };
+    // wait until only the latest stage's loads of this wavefront are pending
+    auto wait_prev = [&]() { wait_vm<CPW>(); };
+    const auto all_classes = std::make_integer_sequence<int, 2 * S - 1>{};
+    auto stage = [&](int st, auto jc) {
+        constexpr int J = decltype(jc)::value;
+        dma(min(st + 2, st1 - 1), buf_of(std::integral_constant<int, (J + 2) % 3>{}));
+        compute(buf_of(std::integral_constant<int, J % 3>{}));
+        sg_flush_due<S, J>(all_classes, false, acc, tot);
+        wait_prev();
+        stage_barrier();
+    };
+    if (st1 > st0) {
+        dma(st0, Ls0);
+        dma(min(st0 + 1, st1 - 1), Ls1);
+        wait_prev();   // stage st0 landed
+        stage_barrier();
+        const int ncyc = (st1 - st0) / SG_CYCLE;
+        int st = st0;
+        for (int c = 0; c < ncyc; ++c, st += SG_CYCLE) {
+            stage(st, std::integral_constant<int, 0>{});
+            stage(st + 1, std::integral_constant<int, 1>{});
+            stage(st + 2, std::integral_constant<int, 2>{});
+            stage(st + 3, std::integral_constant<int, 3>{});
+            stage(st + 4, std::integral_constant<int, 4>{});
+            stage(st + 5, std::integral_constant<int, 5>{});
+        }
+        for (int i = 0; st < st1; ++i, ++st) {   // buffer of stage st: i mod 3
+            const int bi = i % 3, bn = (i + 2) % 3;
+            dma(min(st + 2, st1 - 1), bn == 0 ? Ls0 : (bn == 1 ? Ls1 : Ls2));
+            compute(bi == 0 ? Ls0 : (bi == 1 ? Ls1 : Ls2));
+            sg_flush_due<S, 0>(all_classes, true, acc, tot);
+            wait_prev();
+            stage_barrier();
+        }
+        wait_vm<0>();
     }
 
     // result element (row, col): MFMA row index = column of C (4 (lane/16) + v),
     // MFMA column index = row of C (lane & 15)
+    const bool raw = p.splitk > 1;
 #pragma unroll
-    for (int a = 0; a < FM; ++a) {
-        const int r = row0 + wm * TM + a * 16 + (lane & 15);
+    for (int a = 0; a < 2; ++a) {
+        const int r = row0 + wm * 32 + a * 16 + (lane & 15);
         if (r >= p.M) continue;
         const int er = p.ea[r];
+        double old[2][4];
 #pragma unroll
-        for (int b = 0; b < FN; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int c = col0 + wn * TN + b * 16 + 4 * (lane >> 4) + v;
+                const int c = col0 + wn * 32 + b * 16 + 4 * (lane >> 4) + v;
+                old[b][v] = ld_or(C, r + (long)c * p.ldc,
+                                  !raw && p.beta != 0.0 && c < p.N && !(p.lower && r < c), 0.0);
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = col0 + wn * 32 + b * 16 + 4 * (lane >> 4) + v;
                 if (c >= p.N || (p.lower && r < c)) continue;
-                double *dst = p.C + r + (long)c * p.ldc;
                 const double val = ldexp(tot[a][b][v], er + p.eb[c]);
-                *dst = (p.beta != 0.0) ? val + p.beta * (*dst) : val;
+                C[r + (long)c * p.ldc] = raw ? val : ((p.beta != 0.0) ? val + p.beta * old[b][v] : val);
             }
     }
 }
@@ -298,11 +493,29 @@ hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, co
     }
 }
 
-hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s) {
-    if (a.M <= 0 || a.N <= 0) return hipSuccess;
-    dim3 grid((a.M + SG_BM - 1) / SG_BM, (a.N + SG_BN - 1) / SG_BN);
-    hipLaunchKernelGGL(sliced_gemm_kernel, grid, dim3(512), 0, s, a);
+template <int S>
+static hipError_t launch_sliced_s(const SlicedGemmArgs &a, hipStream_t s) {
+    const long T = sg_tiles(a.M, a.N, a.lower);
+    const int Z = a.splitk > 1 ? a.splitk : 1;
+    hipLaunchKernelGGL((sliced_gemm_kernel<S>), dim3((unsigned)T, Z), dim3(SG_NT), 0, s, a);
     return hipGetLastError();
 }
+
+hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s) {
+    if (a.M <= 0 || a.N <= 0) return hipSuccess;
+    if (a.Kpad % 64 != 0) return hipErrorInvalidValue;
+    // lane offsets into a slice plane are 32-bit element counts
+    if ((double)(a.M - 1) * a.lda + a.Kpad >= 4294967296.0 || (double)(a.N - 1) * a.ldb + a.Kpad >= 4294967296.0)
+        return hipErrorInvalidValue;
+    switch (a.S) {
+        case 1: return launch_sliced_s<1>(a, s);
+        case 2: return launch_sliced_s<2>(a, s);
+        case 3: return launch_sliced_s<3>(a, s);
+        case 4: return launch_sliced_s<4>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+long sliced_tiles(int M, int N, int lower) { return sg_tiles(M, N, lower); }
 
 }  // namespace geninv

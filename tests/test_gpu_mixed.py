@@ -77,18 +77,29 @@ def test_sliced_gram_integer_input_bit_exact():
     assert np.array_equal(np.tril(A), np.tril(ref))
 
 
-@pytest.mark.parametrize("m,n,s", [(300, 40, 4), (513, 129, 3), (2000, 200, 4)])
+@pytest.mark.parametrize("m,n,s", [(300, 40, 4), (513, 129, 3), (2000, 200, 4), (12000, 150, 4), (64, 200, 2),
+                                   (100, 7, 1)])
 def test_sliced_gram_matches_exact_representation_gram(m, n, s):
+    """The GPU sliced Gram is the exact Gram matrix of the sliced representation
+    up to the float64 rounding of its class totals (12000 x 150 goes through
+    the split-K path)."""
     _case("bgram", m=m, n=n, s=s)
     G, _ = w.lowrank_uv(m, n, max(1, n // 2), seed=m)
     S, e = z.slice_columns(G, s)
     Gs = z.reconstruct(S, e)
     A = np.tril(down(api.bgram(up(G), s)))
-    ref = np.tril(z.sliced_gram(G, s)) if m * n * n <= 3e6 else np.tril(Gs.T @ Gs)
-    # float64 totals of s^2 pairs over ceil(m/256) exact chunks, plus one final scaling
-    nterms = s * s * ((m + 255) // 256) + 2
+    ref = np.tril(z.sliced_gram(G, s))
+    # float64 totals: 2s - 1 weight classes per 32-deep stage, plus the
+    # split-K sum and one final scaling
+    nterms = (2 * s - 1) * ((m + 31) // 32) + 18
     bound = nterms * 2.0 ** -53 * np.tril(np.abs(Gs).T @ np.abs(Gs))
     assert np.all(np.abs(A - ref) <= bound + 1e-300)
+
+
+def test_sliced_gram_rejects_five_slices():
+    with pytest.raises(api.GeninvError) as e:
+        api.bgram(up(np.ones((10, 3))), 5)
+    assert e.value.status == -1
 
 
 def test_mixed_c1_matches_oracle():

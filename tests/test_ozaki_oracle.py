@@ -83,3 +83,19 @@ def test_chunk_of_256_pair_products_is_exact_in_float32():
     for x, y in zip(a, b):
         acc = np.float32(acc + np.float32(x) * np.float32(y))
     assert int(acc) == int(np.dot(a, b))
+
+
+@pytest.mark.parametrize("pairs,stages,exact", [(1, 6, True), (2, 3, True), (3, 2, True), (4, 2, True),
+                                                 (4, 3, False), (2, 5, False), (1, 9, False)])
+def test_class_period_bound_of_the_gpu_kernel(pairs, stages, exact):
+    # the GPU kernel sums the slice products of one weight class (1 to 4
+    # pairs) over `stages` 32-deep K stages in float32 before moving the sum
+    # to float64: 6 stages for one pair, 3 for two, 2 for three or four.  The
+    # sum stays an exact integer iff pairs * 32 * stages * 255^2 <= 2^24.
+    n = pairs * 32 * stages
+    assert (n * 255 * 255 <= 2 ** 24) == exact
+    if exact:   # worst case: every product +255^2, summed in float32 order
+        acc = np.float32(0.0)
+        for _ in range(n):
+            acc = np.float32(acc + np.float32(255.0 * 255.0))
+        assert int(acc) == n * 255 * 255
