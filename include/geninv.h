@@ -162,15 +162,17 @@ int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, d
 /* ---- mixed precision: error-free split products on bfloat16 matrix cores - */
 
 /* Y = G^+ (Theorem 1) with the two dense products on the bfloat16 matrix
- * cores as exact products of 8-bit operand slices (the error-free splitting of
- * Ozaki, Ogita, Oishi and Rump): every column of G (every row of P and G in the
- * chain) is scaled by a power of two and cut into `slices` signed 8-bit
- * integer slices; every pair of slices is multiplied exactly (float32 sums
- * of each weight class over 32 values of k, exact integers, moved into float64
- * totals).  The Gram matrix is thus the exactly rounded Gram matrix of the
- * 8*slices-bit representation of G (a truncated pair set would not be the
- * Gram matrix of any matrix, and a rank-deficient G would turn its
- * first-order error in the null space into a large error in G^+).
+ * cores as sums of exact products of 8-bit operand slices (the error-free
+ * splitting of Ozaki, Ogita, Oishi and Rump): every column of G (every row of
+ * P and G in the chain) is scaled by a power of two and cut into `slices`
+ * signed 8-bit integer slices; slice pairs are multiplied exactly (float32
+ * sums of each weight class, exact integers, moved into float64 totals).
+ * The Gram matrix takes every pair, so it is the exactly rounded Gram matrix
+ * of the 8*slices-bit representation of G (a truncated pair set would not be
+ * the Gram matrix of any matrix, and a rank-deficient G would turn its
+ * first-order error in the null space into a large error in G^+).  The chain
+ * product takes the pairs t + u <= s of weight >= 2^(-8 (s+2)) (13 of 16 at
+ * s = 4); the pairs left out weigh less than the s-slice truncation itself.
  * The tolerance, the pivot decisions, the Cholesky factor and (L'L)^-1 are
  * float64, as in geninv_dgeninv.
  *   slices        1..4, slices of G in the Gram matrix (4: 32-bit representation)
@@ -186,14 +188,22 @@ int geninv_mixed(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double
  * exponents e[cols] and planes[t][i + j*ldp] = slice t of X(i, j) (ldp >= rows,
  * rows rows..ldp-1 zero).  transposed != 0: row exponents e[rows] and
  * planes[t][k + i*ldp] = slice t of X(i, k) (ldp >= cols, columns cols..ldp-1
- * zero).  planes: DEVICE bfloat16 array of slices*ldp*(cols or rows) elements;
- * e: DEVICE int array. */
+ * zero).  planes: DEVICE bfloat16 array of slices*ldp*(cols or rows) elements,
+ * 16-byte aligned, with ldp a multiple of 8 (EINVAL otherwise); e: DEVICE int
+ * array. */
 int geninv_bslice(geninv_ctx *ctx, int rows, int cols, const double *X, int ldx, int slices,
                   int transposed, void *planes, int ldp, int *e);
 
 /* Lower triangle of the sliced Gram matrix G_s'G_s (n x n, lda >= n) exactly
  * as geninv_mixed forms it (slices 1..4), for parity testing. */
 int geninv_bgram(geninv_ctx *ctx, int m, int n, const double *G, int ldg, int slices, double *A, int lda);
+
+/* Y = P G' (n x m, ldy >= n) for P n x k (ldp >= n) and G m x k (ldg >= m),
+ * exactly as geninv_mixed forms its chain product: rows of P and of G sliced
+ * (slices 1..4), the pairs t + u <= slices multiplied, float64 totals.  For
+ * parity testing.  k = 0 gives Y = 0. */
+int geninv_bchain(geninv_ctx *ctx, int n, int m, int k, const double *P, int ldp, const double *G, int ldg,
+                  int slices, double *Y, int ldy);
 
 /* ---- batched least squares ---------------------------------------------- */
 

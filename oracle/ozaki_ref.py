@@ -64,9 +64,11 @@ def reconstruct(S: np.ndarray, e: np.ndarray, bits: int = SLICE_BITS) -> np.ndar
 
 
 def sliced_product_exact(SA: np.ndarray, ea: np.ndarray, SB: np.ndarray, eb: np.ndarray,
-                         bits: int = SLICE_BITS) -> np.ndarray:
-    """C = A_s' B_s for column-sliced A (k x M) and B (k x N), every slice pair
-    included: C_ij = 2^(ea_i + eb_j) sum_{t,u} 2^(-bits (t+u+2)) (S^A_t' S^B_u)_ij.
+                         bits: int = SLICE_BITS, max_class: int | None = None) -> np.ndarray:
+    """C = A_s' B_s for column-sliced A (k x M) and B (k x N):
+    C_ij = 2^(ea_i + eb_j) sum_{t,u} 2^(-bits (t+u+2)) (S^A_t' S^B_u)_ij over
+    every slice pair, or, with ``max_class``, over the pairs with
+    t + u <= max_class only (the truncated pair set of the Ozaki scheme).
 
     The integer products are exact in int64 (|entries| <= 255^2 k); the pair
     sums are formed exactly with Python integers and rounded to float64 once.
@@ -77,6 +79,8 @@ def sliced_product_exact(SA: np.ndarray, ea: np.ndarray, SB: np.ndarray, eb: np.
     tot = np.zeros((M, N), dtype=object)
     for t in range(s_a):
         for u in range(s_b):
+            if max_class is not None and t + u > max_class:
+                continue
             prod = SA[t].T.astype(np.int64) @ SB[u].astype(np.int64)
             shift = bits * ((s_a - 1 - t) + (s_b - 1 - u))
             tot = tot + prod.astype(object) * (1 << shift)

@@ -136,6 +136,22 @@ def bgram(G: torch.Tensor, slices: int = 4):
     return A
 
 
+def bchain(P: torch.Tensor, G: torch.Tensor, slices: int = 4):
+    """Y = P G' as the mixed form's chain product (rows of P and G sliced)."""
+    _dev(P, "P")
+    _dev(G, "G")
+    n, k = P.shape
+    m = G.shape[0]
+    if G.shape[1] != k:
+        raise ValueError("P and G must have the same number of columns")
+    Pc, ldp = colmajor(P)
+    Gc, ldg = colmajor(G)
+    Y = empty_colmajor(n, m, P.device)
+    _check(load().geninv_bchain(_ctx(P.device), n, m, k, _p(Pc), ldp, _p(Gc), ldg, int(slices), _p(Y), max(1, n)),
+           "geninv_bchain")
+    return Y
+
+
 def lstsq(G: torch.Tensor, F: torch.Tensor, tol: float | None = None):
     """W = G^+ F (n x k), minimum-norm least squares (Section 1); m >= n."""
     _dev(G, "G")

@@ -424,6 +424,7 @@ SlicedGemmArgs sliced(const __bf16 *A, long lda, long sa, const __bf16 *B, long 
     g.C = C; g.ldc = ldc;
     g.M = M; g.N = N; g.Kpad = Kpad;
     g.S = S;
+    g.nclass = 2 * S - 1;
     g.lower = lower;
     g.beta = 0.0;
     g.splitk = 1;
@@ -772,7 +773,8 @@ int geninv_bslice(geninv_ctx *c, int rows, int cols, const double *X, int ldx, i
     if (!c || rows < 0 || cols < 0 || slices < 1 || slices > 6) return GENINV_EINVAL;
     if (rows == 0 || cols == 0) return GENINV_OK;
     if (!X || !planes || !e || bad_ld(ldx, rows)) return GENINV_EINVAL;
-    if (bad_ld(ldp, transposed ? cols : rows)) return GENINV_EINVAL;
+    if (bad_ld(ldp, transposed ? cols : rows) || ldp % 8 != 0 || (reinterpret_cast<uintptr_t>(planes) & 15))
+        return GENINV_EINVAL;
     DeviceGuard g(c->device);
     __bf16 *P = static_cast<__bf16 *>(planes);
     if (!transposed) {
@@ -804,6 +806,39 @@ int geninv_bgram(geninv_ctx *c, int m, int n, const double *G, int ldg, int slic
     ProfScope ps(c, PC_GRAM, 0.5 * slices * (slices + 1) * (double)m * n * (n + 1.0));
     return run_sliced(c, sliced(Gc, mp, mp * n, Gc, mp, mp * n, slices, ecg, ecg, A, lda, n, n, (int)mp, 1),
                       ml.gpart ? at<double>(c, ml.gpart) : nullptr, ml.gpart_elems);
+}
+
+int geninv_bchain(geninv_ctx *c, int n, int m, int k, const double *P, int ldp, const double *G, int ldg, int slices,
+                  double *Y, int ldy) {
+    if (!c || n < 0 || m < 0 || k < 0 || slices < 1 || slices > SG_MAX_S) return GENINV_EINVAL;
+    if (n == 0 || m == 0) return GENINV_OK;
+    if (!Y || bad_ld(ldy, n) || (k > 0 && (!P || !G || bad_ld(ldp, n) || bad_ld(ldg, m)))) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    if (k == 0) {
+        HIPCHK(launch_fill(Y, ldy, n, m, 0.0, c->stream));
+        return GENINV_OK;
+    }
+    const long kp = pad64(k);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t opa = take((size_t)slices * kp * n * sizeof(__bf16));
+    const size_t opb = take((size_t)slices * kp * m * sizeof(__bf16));
+    const size_t oea = take((size_t)n * sizeof(int));
+    const size_t oeb = take((size_t)m * sizeof(int));
+    CHK(ensure_ws(c, off));
+    __bf16 *Pa = at<__bf16>(c, opa), *Gb = at<__bf16>(c, opb);
+    int *ea = at<int>(c, oea), *eb = at<int>(c, oeb);
+    HIPCHK(launch_row_exponents(P, ldp, n, k, ea, c->stream));
+    HIPCHK(launch_slice_rows_t(P, ldp, n, k, ea, slices, Pa, kp, kp * n, c->stream));
+    HIPCHK(launch_row_exponents(G, ldg, m, k, eb, c->stream));
+    HIPCHK(launch_slice_rows_t(G, ldg, m, k, eb, slices, Gb, kp, kp * m, c->stream));
+    SlicedGemmArgs sg = sliced(Pa, kp, kp * n, Gb, kp, kp * m, slices, ea, eb, Y, ldy, n, m, (int)kp, 0);
+    sg.nclass = sliced_chain_classes(slices);
+    return run_sliced(c, sg, nullptr, 0);
 }
 
 int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double tol, int slices, int chain_slices,
@@ -891,8 +926,9 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
             HIPCHK(launch_slice_cols(P, ld, nn, nn, ep, chain_slices, Pc, np, np * nn, c->stream));
         }
         ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
-        CHK(run_sliced(c, sliced(Pc, np, np * nn, Gt, np, np * m, chain_slices, ep, erg, Y, ldy, n, m, (int)np, 0),
-                       nullptr, 0));
+        SlicedGemmArgs sg = sliced(Pc, np, np * nn, Gt, np, np * m, chain_slices, ep, erg, Y, ldy, n, m, (int)np, 0);
+        sg.nclass = sliced_chain_classes(chain_slices);
+        CHK(run_sliced(c, sg, nullptr, 0));
     } else {
         ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
         HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));

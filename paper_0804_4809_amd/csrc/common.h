@@ -49,7 +49,8 @@ struct SlicedGemmArgs {
     const int *ea; const int *eb;         // row exponents of opA, column exponents of opB
     double *C; long ldc;
     int M, N, Kpad;                       // Kpad: multiple of 64, zero padded in the planes
-    int S;                                // slices of both operands (every pair is formed)
+    int S;                                // slices of both operands
+    int nclass;                           // pairs formed: weight classes t + u < nclass (2 S - 1: every pair)
     int lower;
     double beta;
     int splitk;                           // > 1: raw scaled partial sums to C + z strideC
@@ -96,6 +97,8 @@ hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, co
                                __bf16 *planes, long ldp, long sp, hipStream_t s);
 hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s);
 long sliced_tiles(int M, int N, int lower);   // workgroups of one sliced-GEMM split
+// weight classes of the chain's truncated pair set (t + u <= S)
+constexpr int sliced_chain_classes(int S) { return S + 1 < 2 * S - 1 ? S + 1 : 2 * S - 1; }
 
 // batched least squares (batched.hip)
 constexpr int BATCH_NMAX = 256;

@@ -61,12 +61,26 @@ __global__ __launch_bounds__(256) void col_exponent_kernel(const double *X, long
     if (threadIdx.x == 0) e[j] = bound_exponent(red[0]);
 }
 
+// 64 rows per workgroup, four column groups of 64 threads: each wavefront
+// reads 64 consecutive rows of every fourth column (512-byte segments)
 __global__ __launch_bounds__(256) void row_exponent_kernel(const double *X, long ldx, int rows, int cols, int *e) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= rows) return;
+    __shared__ double red[4][64];
+    const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + r;
     double mx = 0.0;
-    for (int j = 0; j < cols; ++j) mx = fmax(mx, fabs(X[i + (long)j * ldx]));
-    e[i] = bound_exponent(mx);
+    if (i < rows) {
+        const double *row = X + i;
+        int j = g;
+        for (; j + 12 < cols; j += 16) {
+            const double a0 = row[(long)j * ldx], a1 = row[(long)(j + 4) * ldx];
+            const double a2 = row[(long)(j + 8) * ldx], a3 = row[(long)(j + 12) * ldx];
+            mx = fmax(mx, fmax(fmax(fabs(a0), fabs(a1)), fmax(fabs(a2), fabs(a3))));
+        }
+        for (; j < cols; j += 4) mx = fmax(mx, fabs(row[(long)j * ldx]));
+    }
+    red[g][r] = mx;
+    __syncthreads();
+    if (g == 0 && i < rows) e[i] = bound_exponent(fmax(fmax(red[0][r], red[1][r]), fmax(red[2][r], red[3][r])));
 }
 
 // the s slices of x / 2^e, most significant first
@@ -82,53 +96,78 @@ __device__ __forceinline__ void slice_value(double x, int e, __bf16 *out) {
     }
 }
 
+// eight consecutive slices t of one operand, packed for a 16-byte store
+template <int S>
+struct Slices8 {
+    uint4 v[S];
+};
+
+template <int S>
+__device__ __forceinline__ void slice8(const double (&x)[8], int e, Slices8<S> &out) {
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+        __bf16 a[S], b[S];
+        slice_value<S>(x[q], e, a);
+        slice_value<S>(x[q + 1], e, b);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const unsigned lo = __builtin_bit_cast(unsigned short, a[t]);
+            const unsigned hi = __builtin_bit_cast(unsigned short, b[t]);
+            reinterpret_cast<unsigned *>(&out.v[t])[q / 2] = lo | (hi << 16);
+        }
+    }
+}
+
 // planes[t][i + j ldp] = slice t of X(i, j) with the column exponent e[j];
-// rows rows..ldp-1 are written as zeros
+// rows rows..ldp-1 are written as zeros.  A thread takes 8 consecutive rows
+// (one 16-byte store per slice); ldp is a multiple of 8.
 template <int S>
 __global__ __launch_bounds__(256) void slice_cols_kernel(const double *X, long ldx, int rows, int cols,
                                                          const int *e, __bf16 *planes, long ldp, long sp) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const long i0 = ((long)blockIdx.x * 256 + threadIdx.x) * 8;
     const int j = blockIdx.y;
-    if (i >= ldp || j >= cols) return;
-    __bf16 v[S];
-    if (i < rows) {
-        slice_value<S>(X[i + (long)j * ldx], e[j], v);
-    } else {
+    if (i0 >= ldp || j >= cols) return;
+    const double *col = X + (long)j * ldx;
+    double x[8];
 #pragma unroll
-        for (int t = 0; t < S; ++t) v[t] = (__bf16)0.0f;
-    }
+    for (int q = 0; q < 8; ++q) x[q] = ld_or(col, i0 + q, i0 + q < rows, 0.0);
+    Slices8<S> o;
+    slice8<S>(x, e[j], o);
 #pragma unroll
-    for (int t = 0; t < S; ++t) planes[t * sp + i + (long)j * ldp] = v[t];
+    for (int t = 0; t < S; ++t) *reinterpret_cast<uint4 *>(planes + t * sp + i0 + (long)j * ldp) = o.v[t];
 }
 
 // transposed row slicing: planes[t][k + i ldp] = slice t of X(i, k) with the
-// row exponent e[i]; k = cols..ldp-1 written as zeros.  32 x 32 tiles staged
-// through LDS so that both the read (down columns of X) and the write (along
-// rows of X) are contiguous.
+// row exponent e[i]; k = cols..ldp-1 written as zeros (ldp a multiple of 8).
+// A 32 x 64 (rows x k) tile is staged through LDS: read down the columns of
+// X (32 rows = 256 contiguous bytes), written along its rows, each thread 8
+// consecutive k of one row (one 16-byte store per slice).
 template <int S>
 __global__ __launch_bounds__(256) void slice_rows_t_kernel(const double *X, long ldx, int rows, int cols,
                                                            const int *e, __bf16 *planes, long ldp, long sp) {
-    __shared__ double tile[32][33];
-    const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
+    __shared__ double tile[64][33];
+    const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    for (int yy = ty; yy < 32; yy += 8) {
-        const int i = i0 + tx, k = k0 + yy;
-        tile[yy][tx] = (i < rows && k < cols) ? X[i + (long)k * ldx] : 0.0;
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = i0 + tx, k = k0 + ty + 8 * q;
+        v[q] = ld_or(X, i + (long)k * ldx, i < rows && k < cols, 0.0);
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) tile[ty + 8 * q][tx] = v[q];
     __syncthreads();
-    for (int yy = ty; yy < 32; yy += 8) {
-        const int i = i0 + yy, k = k0 + tx;
-        if (i >= rows || k >= ldp) continue;
-        __bf16 v[S];
-        if (k < cols) {
-            slice_value<S>(tile[tx][yy], e[i], v);
-        } else {
+    const int r = threadIdx.x >> 3, kc = (threadIdx.x & 7) * 8;   // row r of the tile, k0 + kc .. + 7
+    const int i = i0 + r;
+    const long k = k0 + kc;
+    if (i >= rows || k >= ldp) return;
+    double x[8];
 #pragma unroll
-            for (int t = 0; t < S; ++t) v[t] = (__bf16)0.0f;
-        }
+    for (int q = 0; q < 8; ++q) x[q] = tile[kc + q][r];
+    Slices8<S> o;
+    slice8<S>(x, e[i], o);
 #pragma unroll
-        for (int t = 0; t < S; ++t) planes[t * sp + k + (long)i * ldp] = v[t];
-    }
+    for (int t = 0; t < S; ++t) *reinterpret_cast<uint4 *>(planes + t * sp + k + (long)i * ldp) = o.v[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -180,8 +219,8 @@ static_assert(1 * 32 * 6 * 255 * 255 < (1 << 24) && 2 * 32 * 3 * 255 * 255 < (1 
                   4 * 32 * 2 * 255 * 255 < (1 << 24),
               "class periods must keep float32 class sums exact");
 
-template <int S, int C>
-__device__ __forceinline__ void sg_flush_class(f4 (&acc)[2 * S - 1][2][2], double (&tot)[2][2][4]) {
+template <int S, int NC, int C>
+__device__ __forceinline__ void sg_flush_class(f4 (&acc)[NC][2][2], double (&tot)[2][2][4]) {
     const double w = __builtin_bit_cast(double, (unsigned long long)(1023 - 8 * (C + 2)) << 52);   // 2^(-8 (C+2))
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -194,10 +233,10 @@ __device__ __forceinline__ void sg_flush_class(f4 (&acc)[2 * S - 1][2][2], doubl
 }
 
 // after stage J of a run (or every class when `all`)
-template <int S, int J, int... C>
-__device__ __forceinline__ void sg_flush_due(std::integer_sequence<int, C...>, bool all, f4 (&acc)[2 * S - 1][2][2],
+template <int S, int NC, int J, int... C>
+__device__ __forceinline__ void sg_flush_due(std::integer_sequence<int, C...>, bool all, f4 (&acc)[NC][2][2],
                                              double (&tot)[2][2][4]) {
-    ((((J + 1) % sg_period(S, C) == 0 || all) ? sg_flush_class<S, C>(acc, tot) : void()), ...);
+    ((((J + 1) % sg_period(S, C) == 0 || all) ? sg_flush_class<S, NC, C>(acc, tot) : void()), ...);
 }
 
 // one wavefront-wide direct load: 16 bytes per lane from g into LDS at
@@ -224,8 +263,10 @@ __device__ __forceinline__ void stage_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int S>
+// S slices per operand; the pairs of the NC weight classes t + u < NC
+template <int S, int NC>
 __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
+    static_assert(NC >= 1 && NC <= 2 * S - 1, "class count");
     // three stage buffers (loads run two stages ahead), separate arrays so
     // that reads of one need not wait for the direct loads into another
     __shared__ __align__(1024) char Ls0[S * SG_ROWS * 64];
@@ -314,14 +355,14 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
         }
     };
 
-    f4 acc[2 * S - 1][2][2];
+    f4 acc[NC][2][2];
     double tot[2][2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
 #pragma unroll
-            for (int c = 0; c < 2 * S - 1; ++c) acc[c][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < NC; ++c) acc[c][a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) tot[a][b][v] = 0.0;
         }
@@ -350,13 +391,15 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
             for (int a = 0; a < 2; ++a)
                 af[a] = *reinterpret_cast<const bf8 *>(buf + rda + (t * SG_ROWS + a * 16) * 64);
 #pragma unroll
-            for (int u = 0; u < S; ++u)
+            for (int u = 0; u < S; ++u) {
+                if (t + u >= NC) continue;
+                const int c = t + u < NC ? t + u : 0;
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < 2; ++b)
-                        acc[t + u][a][b] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[u][b], af[a], acc[t + u][a][b], 0, 0, 0);
+                        acc[c][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[u][b], af[a], acc[c][a][b], 0, 0, 0);
+            }
         }
     };
     // Stage st: start the loads of stage st + 2 (clamped to the last stage of
@@ -373,12 +416,12 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
     };
     // wait until only the latest stage's loads of this wavefront are pending
     auto wait_prev = [&]() { wait_vm<CPW>(); };
-    const auto all_classes = std::make_integer_sequence<int, 2 * S - 1>{};
+    const auto all_classes = std::make_integer_sequence<int, NC>{};
     auto stage = [&](int st, auto jc) {
         constexpr int J = decltype(jc)::value;
         dma(min(st + 2, st1 - 1), buf_of(std::integral_constant<int, (J + 2) % 3>{}));
         compute(buf_of(std::integral_constant<int, J % 3>{}));
-        sg_flush_due<S, J>(all_classes, false, acc, tot);
+        sg_flush_due<S, NC, J>(all_classes, false, acc, tot);
         wait_prev();
         stage_barrier();
     };
@@ -401,7 +444,7 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
             const int bi = i % 3, bn = (i + 2) % 3;
             dma(min(st + 2, st1 - 1), bn == 0 ? Ls0 : (bn == 1 ? Ls1 : Ls2));
             compute(bi == 0 ? Ls0 : (bi == 1 ? Ls1 : Ls2));
-            sg_flush_due<S, 0>(all_classes, true, acc, tot);
+            sg_flush_due<S, NC, 0>(all_classes, true, acc, tot);
             wait_prev();
             stage_barrier();
         }
@@ -445,14 +488,14 @@ hipError_t launch_col_exponents(const double *X, long ldx, int rows, int cols, i
 
 hipError_t launch_row_exponents(const double *X, long ldx, int rows, int cols, int *e, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(row_exponent_kernel, dim3((rows + 255) / 256), dim3(256), 0, s, X, ldx, rows, cols, e);
+    hipLaunchKernelGGL(row_exponent_kernel, dim3((rows + 63) / 64), dim3(256), 0, s, X, ldx, rows, cols, e);
     return hipGetLastError();
 }
 
 template <int S>
 static hipError_t slice_cols_s(const double *X, long ldx, int rows, int cols, const int *e, __bf16 *planes, long ldp,
                                long sp, hipStream_t s) {
-    dim3 grid((ldp + 255) / 256, cols);
+    dim3 grid((ldp / 8 + 255) / 256, cols);
     hipLaunchKernelGGL((slice_cols_kernel<S>), grid, dim3(256), 0, s, X, ldx, rows, cols, e, planes, ldp, sp);
     return hipGetLastError();
 }
@@ -460,7 +503,7 @@ static hipError_t slice_cols_s(const double *X, long ldx, int rows, int cols, co
 template <int S>
 static hipError_t slice_rows_t_s(const double *X, long ldx, int rows, int cols, const int *e, __bf16 *planes,
                                  long ldp, long sp, hipStream_t s) {
-    dim3 grid((rows + 31) / 32, (ldp + 31) / 32);
+    dim3 grid((rows + 31) / 32, (ldp + 63) / 64);
     hipLaunchKernelGGL((slice_rows_t_kernel<S>), grid, dim3(256), 0, s, X, ldx, rows, cols, e, planes, ldp, sp);
     return hipGetLastError();
 }
@@ -468,6 +511,7 @@ static hipError_t slice_rows_t_s(const double *X, long ldx, int rows, int cols, 
 hipError_t launch_slice_cols(const double *X, long ldx, int rows, int cols, const int *e, int nslices,
                              __bf16 *planes, long ldp, long sp, hipStream_t s) {
     if (rows < 0 || cols <= 0) return hipSuccess;
+    if (ldp % 8 != 0 || sp % 8 != 0 || (reinterpret_cast<uintptr_t>(planes) & 15)) return hipErrorInvalidValue;
     switch (nslices) {
         case 1: return slice_cols_s<1>(X, ldx, rows, cols, e, planes, ldp, sp, s);
         case 2: return slice_cols_s<2>(X, ldx, rows, cols, e, planes, ldp, sp, s);
@@ -482,6 +526,7 @@ hipError_t launch_slice_cols(const double *X, long ldx, int rows, int cols, cons
 hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, const int *e, int nslices,
                                __bf16 *planes, long ldp, long sp, hipStream_t s) {
     if (rows <= 0 || cols < 0) return hipSuccess;
+    if (ldp % 8 != 0 || sp % 8 != 0 || (reinterpret_cast<uintptr_t>(planes) & 15)) return hipErrorInvalidValue;
     switch (nslices) {
         case 1: return slice_rows_t_s<1>(X, ldx, rows, cols, e, planes, ldp, sp, s);
         case 2: return slice_rows_t_s<2>(X, ldx, rows, cols, e, planes, ldp, sp, s);
@@ -493,11 +538,11 @@ hipError_t launch_slice_rows_t(const double *X, long ldx, int rows, int cols, co
     }
 }
 
-template <int S>
+template <int S, int NC>
 static hipError_t launch_sliced_s(const SlicedGemmArgs &a, hipStream_t s) {
     const long T = sg_tiles(a.M, a.N, a.lower);
     const int Z = a.splitk > 1 ? a.splitk : 1;
-    hipLaunchKernelGGL((sliced_gemm_kernel<S>), dim3((unsigned)T, Z), dim3(SG_NT), 0, s, a);
+    hipLaunchKernelGGL((sliced_gemm_kernel<S, NC>), dim3((unsigned)T, Z), dim3(SG_NT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -507,11 +552,14 @@ hipError_t launch_sliced_gemm(const SlicedGemmArgs &a, hipStream_t s) {
     // lane offsets into a slice plane are 32-bit element counts
     if ((double)(a.M - 1) * a.lda + a.Kpad >= 4294967296.0 || (double)(a.N - 1) * a.ldb + a.Kpad >= 4294967296.0)
         return hipErrorInvalidValue;
+    // every pair, or the pairs of weight at least 2^(-8 (S + 2)) (t + u <= S)
+    const bool all = a.nclass == 2 * a.S - 1;
+    if (!all && a.nclass != sliced_chain_classes(a.S)) return hipErrorInvalidValue;
     switch (a.S) {
-        case 1: return launch_sliced_s<1>(a, s);
-        case 2: return launch_sliced_s<2>(a, s);
-        case 3: return launch_sliced_s<3>(a, s);
-        case 4: return launch_sliced_s<4>(a, s);
+        case 1: return launch_sliced_s<1, 1>(a, s);
+        case 2: return launch_sliced_s<2, 3>(a, s);
+        case 3: return all ? launch_sliced_s<3, 5>(a, s) : launch_sliced_s<3, 4>(a, s);
+        case 4: return all ? launch_sliced_s<4, 7>(a, s) : launch_sliced_s<4, 5>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -96,6 +96,30 @@ def test_sliced_gram_matches_exact_representation_gram(m, n, s):
     assert np.all(np.abs(A - ref) <= bound + 1e-300)
 
 
+@pytest.mark.parametrize("n,m,k,s", [(40, 300, 100, 4), (129, 513, 257, 3), (150, 2000, 600, 4), (7, 100, 33, 1),
+                                     (64, 70, 200, 2), (33, 65, 1, 4)])
+def test_sliced_chain_matches_exact_truncated_product(n, m, k, s):
+    """The GPU chain product Y = P G' is the exact sum of the slice pairs
+    t + u <= s of the row-sliced operands, up to the float64 rounding of its
+    class totals."""
+    _case("bchain", n=n, m=m, k=k, s=s)
+    rng = np.random.default_rng(n * 1000 + k)
+    P = rng.standard_normal((n, k)) * np.exp(rng.uniform(-3, 3, (n, 1)))
+    G = rng.standard_normal((m, k))
+    Y = down(api.bchain(up(P), up(G), s))
+    SA, ea = z.slice_columns(P.T.copy(), s)
+    SB, eb = z.slice_columns(G.T.copy(), s)
+    ref = z.sliced_product_exact(SA, ea, SB, eb, max_class=min(s, 2 * s - 2))
+    nterms = (s + 1) * ((k + 31) // 32) + 18
+    bound = nterms * 2.0 ** -53 * (np.abs(z.reconstruct(SA, ea)).T @ np.abs(z.reconstruct(SB, eb)))
+    assert np.all(np.abs(Y - ref) <= bound + 1e-300)
+
+
+def test_sliced_chain_empty_inner_dimension_is_zero():
+    Y = down(api.bchain(up(np.zeros((5, 0))), up(np.zeros((9, 0))), 4))
+    assert Y.shape == (5, 9) and not Y.any()
+
+
 def test_sliced_gram_rejects_five_slices():
     with pytest.raises(api.GeninvError) as e:
         api.bgram(up(np.ones((10, 3))), 5)

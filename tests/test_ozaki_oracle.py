@@ -99,3 +99,31 @@ def test_class_period_bound_of_the_gpu_kernel(pairs, stages, exact):
         for _ in range(n):
             acc = np.float32(acc + np.float32(255.0 * 255.0))
         assert int(acc) == n * 255 * 255
+
+
+@pytest.mark.parametrize("s,c", [(4, 0), (4, 3), (4, 4), (3, 2), (2, 1)])
+def test_truncated_pair_set_is_the_sum_of_its_pairs(s, c):
+    # brute force: each slice pair's product formed separately from the
+    # exact per-slice reconstructions (small k: every float64 sum is exact)
+    rng = np.random.default_rng(10 * s + c)
+    A = rng.standard_normal((5, 3))
+    B = rng.standard_normal((5, 4))
+    SA, ea = z.slice_columns(A, s)
+    SB, eb = z.slice_columns(B, s)
+    got = z.sliced_product_exact(SA, ea, SB, eb, max_class=c)
+    want = np.zeros((3, 4))
+    for t in range(s):
+        for u in range(s):
+            if t + u <= c:
+                At = np.ldexp(SA[t].astype(np.float64), -8 * (t + 1)) * np.ldexp(1.0, ea)[None, :]
+                Bu = np.ldexp(SB[u].astype(np.float64), -8 * (u + 1)) * np.ldexp(1.0, eb)[None, :]
+                want += At.T @ Bu
+    assert np.array_equal(got, want)
+
+
+def test_full_class_range_is_every_pair():
+    rng = np.random.default_rng(3)
+    SA, ea = z.slice_columns(rng.standard_normal((6, 2)), 3)
+    SB, eb = z.slice_columns(rng.standard_normal((6, 5)), 3)
+    assert np.array_equal(z.sliced_product_exact(SA, ea, SB, eb, max_class=4),
+                          z.sliced_product_exact(SA, ea, SB, eb))
