@@ -63,6 +63,30 @@ def lstsq_flops(m: int, n: int, r: int, k: int) -> float:
     return f
 
 
+def _counter_traffic(kernel_class: str):
+    """HBM bytes per launch of `kernel_class` (FETCH_SIZE + WRITE_SIZE, scaled
+    by a plain copy) from the committed counter summary, or None when the
+    summary has no such line or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fp64_rbf_8192x2048_hbm_bytes.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        if not line.startswith(f"traffic {kernel_class} "):
+            continue
+        fields = dict(f.split("=", 1) for f in line.split()[2:] if "=" in f and not f.startswith('kernel'))
+        h = hashlib.sha256()
+        for src in fields["sources"].split(","):
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != fields["sha256_16"]:
+            return None
+        return int(fields["read_bytes"]) + int(fields["write_bytes"])
+    return None
+
+
 def _timed(fn, steps, sync):
     sync()
     t0 = time.perf_counter()
@@ -298,7 +322,8 @@ def main():
         "peak": FP64_MFMA_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": _counter_traffic(dom),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_launch_ms": round(avg_ms, 4),
         "launches_per_step": dcnt.value / args.steps,
     }
