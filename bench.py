@@ -96,9 +96,10 @@ def _timed(fn, steps, sync):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
-def bench_mixed(lib, api, workloads, torch, np, steps, with_oracle):
+def bench_mixed(lib, api, workloads, torch, np, steps, keep_host):
     """Mixed-precision form vs the float64 form on G = P diag(s) Q'
-    (32768 x 4096, rank 3072, s log-spaced in [1e-3, 1])."""
+    (32768 x 4096, rank 3072, s log-spaced in [1e-3, 1]).  Returns the
+    report and, with ``keep_host``, host copies of every Y for the oracle leg."""
     G, _, P, sv, Q = workloads.c3_problem()
     m, n = G.shape
     dev = torch.device("cuda", 0)
@@ -111,6 +112,7 @@ def bench_mixed(lib, api, workloads, torch, np, steps, with_oracle):
     Ymx = api.empty_colmajor(n, m, dev)
     piv = torch.empty(n, dtype=torch.int32, device=dev)
     out = {"workload": "G = P diag(s) Q', m=32768, n=4096, rank 3072, s log-spaced from 1 to 1e-3"}
+    host = {"G": G, "P": P, "sv": sv, "Q": Q, "Y": {}} if keep_host else None
 
     def run64():
         st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, vp(Y64.data_ptr()), n, None, None)
@@ -135,29 +137,8 @@ def bench_mixed(lib, api, workloads, torch, np, steps, with_oracle):
     run64()
     t64 = _timed(run64, steps, sync)
     out["fp64"] = {"ms": round(t64, 3), "tflops": round(flops / t64 / 1e9, 3), "rank": r}
-    Yor = None
-    Ytrue = None
-    if with_oracle:
-        from oracle import geninv_ref as o
-        c0 = time.perf_counter()
-        res = o.geninv(G)
-        out["oracle_seconds"] = round(time.perf_counter() - c0, 2)
-        out["oracle_rank"] = res.rank
-        Yor = res.Y
-        Ytrue = (Q / sv) @ P.T
-        # the oracle on the 32-bit column-sliced representation G_s that the
-        # mixed Gram matrix is exact for: separates representation error
-        # from arithmetic error
-        from oracle import ozaki_ref as z
-        Ssl, esl = z.slice_columns(G, 4)
-        Gs = z.reconstruct(Ssl, esl)
-        del Ssl
-        Yor_s = o.geninv(Gs).Y
-        out["oracle_on_sliced_G_relF_vs_oracle"] = float(np.linalg.norm(Yor_s - Yor) / np.linalg.norm(Yor))
-        del Gs
-        Y64h = Y64.cpu().numpy()
-        out["fp64"]["relF_vs_oracle"] = float(np.linalg.norm(Y64h - Yor) / np.linalg.norm(Yor))
-        del Y64h
+    if host is not None:
+        host["Y"]["fp64"] = Y64.cpu().numpy()
     for cs, ns, key in [(4, 0, "mixed_s4_chain4"), (0, 0, "mixed_s4_chain_fp64"), (4, 1, "mixed_s4_chain4_ns1")]:
         f = runmx(cs, ns)
         r2 = ctypes.c_int(0)
@@ -165,17 +146,69 @@ def bench_mixed(lib, api, workloads, torch, np, steps, with_oracle):
                               ctypes.byref(r2), None)
         assert st == 0, st
         t = _timed(f, steps, sync)
-        d = {"ms": round(t, 3), "tflops_fp64_equivalent": round(flops / t / 1e9, 3), "rank": r2.value,
-             "speedup_vs_fp64": round(t64 / t, 3),
-             "relF_vs_fp64_gpu": float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64))}
-        if Yor is not None:
-            Ym = Ymx.cpu().numpy()
-            d["relF_vs_oracle"] = float(np.linalg.norm(Ym - Yor) / np.linalg.norm(Yor))
-            d["relF_vs_closed_form"] = float(np.linalg.norm(Ym - Ytrue) / np.linalg.norm(Ytrue))
-            d["relF_vs_oracle_on_sliced_G"] = float(np.linalg.norm(Ym - Yor_s) / np.linalg.norm(Yor_s))
-            del Ym
-        out[key] = d
+        out[key] = {"ms": round(t, 3), "tflops_fp64_equivalent": round(flops / t / 1e9, 3), "rank": r2.value,
+                    "speedup_vs_fp64": round(t64 / t, 3),
+                    "relF_vs_fp64_gpu": float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64))}
+        if host is not None:
+            host["Y"][key] = Ymx.cpu().numpy()
     del Gc, Y64, Ymx
+    torch.cuda.empty_cache()
+    return out, host
+
+
+def bench_large_rbf(lib, api, workloads, torch, np, steps):
+    """Mixed vs float64 on the large RBF design (131072 inputs in [0,1]^8,
+    8192 centers with sigma 0.5, 1192 of them exact duplicates, F 131072 x 16).
+    The float64 CPU oracle is out of reach at this size (minutes); the mixed
+    result is compared with the float64 GPU form, which is parity-tested
+    against the oracle at the sizes the oracle finishes."""
+    c0 = time.perf_counter()
+    G, F, _ = workloads.c5_problem()
+    gen_s = time.perf_counter() - c0
+    m, n = G.shape
+    dev = torch.device("cuda", 0)
+    Gc = torch.from_numpy(G).to(dev).t().contiguous().t()
+    Fd = torch.from_numpy(F).to(dev)
+    del G, F
+    ctx = api._ctx(dev)
+    vp = ctypes.c_void_p
+    Y64 = api.empty_colmajor(n, m, dev)
+    Ymx = api.empty_colmajor(n, m, dev)
+    sync = torch.cuda.synchronize
+    out = {"workload": "RBF design: m=131072 inputs uniform in [0,1]^8, n=8192 centers (7000 uniform + 1192 exact "
+                       "duplicates), sigma=0.5, F 131072x16", "generate_s": round(gen_s, 1)}
+
+    def run64():
+        st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, vp(Y64.data_ptr()), n, None, None)
+        assert st == 0, st
+
+    r64 = ctypes.c_int(0)
+    st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, vp(Y64.data_ptr()), n, ctypes.byref(r64), None)
+    assert st == 0, st
+    t64 = _timed(run64, steps, sync)
+    W64 = Y64 @ Fd
+    fn = torch.linalg.norm(Fd)
+    # least-squares residual |G W - F| / |F|: a backward-stable figure of
+    # merit on this ill-conditioned design (cond(L'L) ~ 4e13), where no two
+    # float64 evaluations of Y agree closely
+    out["fp64"] = {"ms": round(t64, 2), "rank": r64.value,
+                   "ls_residual": float(torch.linalg.norm(Gc @ W64 - Fd) / fn)}
+    for cs, ns, key in [(4, 0, "mixed_s4_chain4"), (4, 1, "mixed_s4_chain4_ns1")]:
+        def f():
+            st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n, None, None)
+            assert st == 0, st
+        rm = ctypes.c_int(0)
+        st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n,
+                              ctypes.byref(rm), None)
+        assert st == 0, st
+        t = _timed(f, steps, sync)
+        Wmx = Ymx @ Fd
+        out[key] = {"ms": round(t, 2), "rank": rm.value, "speedup_vs_fp64": round(t64 / t, 3),
+                    "relF_Y_vs_fp64_gpu": float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64)),
+                    "relF_W_vs_fp64_gpu": float(torch.linalg.norm(Wmx - W64) / torch.linalg.norm(W64)),
+                    "ls_residual": float(torch.linalg.norm(Gc @ Wmx - Fd) / fn)}
+        del Wmx
+    del Gc, Fd, Y64, Ymx, W64
     torch.cuda.empty_cache()
     return out
 
@@ -222,7 +255,7 @@ def bench_table1(lib, api, workloads, torch, np, steps):
             "rows": rows}
 
 
-def bench_batched(api, workloads, torch, np, steps, with_oracle):
+def bench_batched(api, workloads, torch, np, steps, keep_host):
     """4096 uneven float32 least-squares problems in one persistent launch,
     replayed from a HIP graph after autotuning."""
     B = workloads.c4_problem()
@@ -278,22 +311,86 @@ def bench_batched(api, workloads, torch, np, steps, with_oracle):
     out["rank_equals_fp64_form"] = int(same.sum())
     out["relF_vs_fp64_form_same_rank"] = {"median": float(np.median(rel[same])), "max": float(rel[same].max()),
                                           "above_1e-6": int((rel[same] > 1e-6).sum())}
-    if (~same).any():
-        out["rank_differs_from_fp64_form"] = [
-            {"problem": int(b), "m": int(B.m[b]), "n": int(B.n[b]), "rank_batched": int(ranks[b]),
-             "rank_fp64": int(r64[b]), "rank_constructed": int(B.rank[b])} for b in np.nonzero(~same)[0][:8]]
+
     del Gs, Fs, Ws
-    if with_oracle:
-        from oracle import geninv_ref as o
+    host = None
+    if keep_host:
         rng = np.random.default_rng(0)
-        worst = 0.0
-        for b in rng.choice(len(B.G), size=16, replace=False):
-            Wr, ref = o.lstsq(B.G[b].astype(np.float64), B.F[b].astype(np.float64))
-            Wg = plan.W(int(b)).cpu().numpy()
-            worst = max(worst, float(np.linalg.norm(Wg - Wr) / np.linalg.norm(Wr)))
-        out["sampled_16_max_relF_vs_oracle"] = worst
+        sample = [int(b) for b in rng.choice(len(B.G), size=16, replace=False)]
+        host = {"B": B, "sample": {b: plan.W(b).cpu().numpy() for b in sample},
+                "rank_batched": ranks.copy(), "rank_fp64": r64, "differs": [int(b) for b in np.nonzero(~same)[0]]}
     plan.close()
-    return out
+    return out, host
+
+
+def cpu_oracle_leg(workloads, np, G, F, flops, mixed_host, batched_host, forms):
+    """Everything that runs the CPU oracle: its timing on the headline
+    workload (cpu_baseline) and the reference results that the other forms'
+    accuracy figures are stated against."""
+    from oracle import geninv_ref as o
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        threads = int(os.environ.get("OPENBLAS_NUM_THREADS", "1"))
+    times = []
+    budget = 25.0
+    while not times or (sum(times) + times[-1] < budget and len(times) < 3):
+        c0 = time.perf_counter()
+        res = o.geninv(G)
+        _ = res.Y @ F
+        times.append(time.perf_counter() - c0)
+    med = sorted(times)[len(times) // 2]
+    cpu = {"value": round(flops / med / 1e12, 5), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"whole float64 oracle (Gram, tol, column-by-column full-rank Cholesky, (L'L)^-1, "
+                     f"chain, W = Y F) on the full workload, median of {len(times)} run(s), "
+                     f"{med:.2f} s each; rank {res.rank}",
+           "seconds": round(med, 3)}
+
+    def relf(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    if mixed_host is not None:
+        mo = forms["mixed_vs_fp64"]
+        Gm = mixed_host["G"]
+        c0 = time.perf_counter()
+        ref = o.geninv(Gm)
+        mo["oracle_seconds"] = round(time.perf_counter() - c0, 2)
+        mo["oracle_rank"] = ref.rank
+        Ytrue = (mixed_host["Q"] / mixed_host["sv"]) @ mixed_host["P"].T
+        # the oracle on the 32-bit column-sliced representation G_s that the
+        # mixed Gram matrix is exact for: separates representation error
+        # from arithmetic error
+        from oracle import ozaki_ref as z
+        Ssl, esl = z.slice_columns(Gm, 4)
+        Gs = z.reconstruct(Ssl, esl)
+        del Ssl
+        ref_s = o.geninv(Gs).Y
+        del Gs
+        mo["oracle_on_sliced_G_relF_vs_oracle"] = relf(ref_s, ref.Y)
+        for key, Y in mixed_host["Y"].items():
+            mo[key]["relF_vs_oracle"] = relf(Y, ref.Y)
+            mo[key]["relF_vs_closed_form"] = relf(Y, Ytrue)
+            if key != "fp64":
+                mo[key]["relF_vs_oracle_on_sliced_G"] = relf(Y, ref_s)
+    if batched_host is not None:
+        bo = forms["batched"]
+        B = batched_host["B"]
+        worst = 0.0
+        for b, Wg in batched_host["sample"].items():
+            Wr, _ = o.lstsq(B.G[b].astype(np.float64), B.F[b].astype(np.float64))
+            worst = max(worst, relf(Wg, Wr))
+        bo["sampled_16_max_relF_vs_oracle"] = worst
+        # problems whose rank differs from the float64 form: the oracle's
+        # rank from its own Gram and from an extended-precision Gram
+        diffs = []
+        for b in batched_host["differs"][:16]:
+            Gb = B.G[b].astype(np.float64)
+            diffs.append({"problem": b, "rank_batched": int(batched_host["rank_batched"][b]),
+                          "rank_fp64": int(batched_host["rank_fp64"][b]), "rank_oracle": o.geninv(Gb).rank,
+                          "rank_oracle_extended_gram": o.geninv(Gb, A=o.gram_extended(Gb)).rank})
+        bo["rank_differs_from_fp64_form"] = diffs
+    return cpu
 
 
 def main():
@@ -304,6 +401,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-forms", action="store_true", help="only the float64 RBF workload")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle checks of the other forms")
+    ap.add_argument("--large-rbf", action="store_true",
+                    help="also run mixed vs float64 on the 131072 x 8192 RBF design (about a minute more)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for hardware byte counters) and exit")
     args = ap.parse_args()
@@ -425,34 +524,23 @@ def main():
     }
     breakdown = {name: round(v[0], 4) for name, v in per_class.items() if v[1] > 0}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import geninv_ref as o
-        try:
-            from threadpoolctl import threadpool_info
-            threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
-        except Exception:  # pragma: no cover
-            threads = int(os.environ.get("OPENBLAS_NUM_THREADS", "1"))
-        times = []
-        budget = 25.0
-        while not times or (sum(times) + times[-1] < budget and len(times) < 3):
-            c0 = time.perf_counter()
-            res = o.geninv(G)
-            _ = res.Y @ F
-            times.append(time.perf_counter() - c0)
-        med = sorted(times)[len(times) // 2]
-        cpu = {"value": round(flops / med / 1e12, 5), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-               "sample": f"whole float64 oracle (Gram, tol, column-by-column full-rank Cholesky, (L'L)^-1, "
-                         f"chain, W = Y F) on the full workload, median of {len(times)} run(s), "
-                         f"{med:.2f} s each; rank {res.rank}",
-               "seconds": round(med, 3)}
-
+    oracle_on = not args.no_cpu_baseline and not args.no_oracle
     forms = {}
+    mixed_host = batched_host = None
     if not args.skip_forms:
         fsteps = max(2, min(args.steps, 5))
-        forms["mixed_vs_fp64"] = bench_mixed(lib, api, workloads, torch, np, fsteps, not args.no_oracle)
-        forms["batched"] = bench_batched(api, workloads, torch, np, max(3, min(args.steps, 10)), not args.no_oracle)
+        forms["mixed_vs_fp64"], mixed_host = bench_mixed(lib, api, workloads, torch, np, fsteps, oracle_on)
+        forms["batched"], batched_host = bench_batched(api, workloads, torch, np, max(3, min(args.steps, 10)),
+                                                       oracle_on)
         forms["table1_sweep"] = bench_table1(lib, api, workloads, torch, np, 5)
+    if args.large_rbf:
+        forms["large_rbf_mixed_vs_fp64"] = bench_large_rbf(lib, api, workloads, torch, np, 2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_oracle_leg(workloads, np, G, F, flops, mixed_host if oracle_on else None,
+                             batched_host if oracle_on else None, forms)
+    del mixed_host, batched_host
 
     out = {
         "metric": METRIC,
