@@ -300,6 +300,276 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// 128 x 128 tiles with direct global -> LDS operand loads
+//
+// Same tiling, tile order, two-level summation and epilogue as dgemm_kernel
+// <128, 128, 32, 4, 2>, but the interior K chunks of interior tiles go from
+// global memory straight into LDS (global_load_lds_dwordx4: no staging
+// registers, no LDS store instructions, the next chunk in flight during the
+// current one).  A wavefront's direct load fills 1 KiB of LDS, 16 bytes per
+// lane in lane order, so the LDS layouts are:
+//   MN-major operand (index contiguous in memory): [k][DM_LD] with a padded
+//     row pitch; one k row (128 doubles) is one wavefront load.
+//   K-major operand (k contiguous): [index][32], the 16 two-double granules
+//     of row i XOR-permuted by i mod 16, so that the matrix-core reads (16
+//     consecutive rows at one k) meet distinct banks; four rows per load.
+// Edge tiles and the last partial K chunk are staged through registers into
+// the same layouts.  The two stage buffers of each operand are separate LDS
+// arrays and every read address is array + opaque per-lane offset +
+// constant, so the compiler keeps reads of one buffer independent of the
+// direct loads into the other.
+// ---------------------------------------------------------------------------
+constexpr int DM_T = 128, DM_BK = 32, DM_NT = 512;
+constexpr int DM_LD = DM_T + 4;   // MN-major LDS row pitch (doubles)
+
+template <bool KMAJ>
+struct DmOp {
+    static constexpr int BYTES = KMAJ ? DM_T * DM_BK * 8 : DM_BK * DM_LD * 8;
+    // LDS double index of element (index i, k)
+    __device__ static __forceinline__ int lds_index(int i, int k) {
+        return KMAJ ? i * DM_BK + (((k >> 1) ^ (i & 15)) << 1) + (k & 1) : k * DM_LD + i;
+    }
+};
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
+    constexpr bool AK = TA, BK_ = !TB;   // K-major operands
+    using OA = DmOp<AK>;
+    using OB = DmOp<BK_>;
+    constexpr int TM = 32, TN = 64, FM = 2, FN = 4;
+    __shared__ __align__(1024) char As0[OA::BYTES];
+    __shared__ __align__(1024) char As1[OA::BYTES];
+    __shared__ __align__(1024) char Bs0[OB::BYTES];
+    __shared__ __align__(1024) char Bs1[OB::BYTES];
+
+    const int M = p.M.get(), N = p.N.get(), K = p.K.get();
+    int bx, by;
+    tile_of<DM_T, DM_T>(p, bx, by);
+    const int row0 = bx * DM_T, col0 = by * DM_T;
+    if (row0 >= M || col0 >= N) return;
+
+    int kbeg = 0, kend = K;
+    double *C = p.C;
+    if (p.splitk > 1) {
+        const int chunk = (((K + p.splitk - 1) / p.splitk) + DM_BK - 1) / DM_BK * DM_BK;
+        kbeg = blockIdx.y * chunk;
+        kend = min(K, kbeg + chunk);
+        C += (long)blockIdx.y * p.strideC;
+    }
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave & 3, wn = wave >> 2;
+    const double *__restrict__ A = p.A;
+    const double *__restrict__ B = p.B;
+    const long lda = p.lda, ldb = p.ldb;
+
+    // interior tiles with 16-byte aligned operands take direct loads for
+    // every whole chunk
+    const bool aligned = ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0 &&
+                         ((lda | ldb) & 1) == 0;
+    const bool small_off = 4L * (lda + ldb) + 64L * (lda + ldb) < (1L << 30);
+    const bool interior = aligned && small_off && row0 + DM_T <= M && col0 + DM_T <= N;
+
+    // ---- direct loads: per-lane element offsets (the same for the four
+    // loads of each operand a wavefront issues per chunk)
+    //   MN-major: load q of wavefront w is k row w + 8q, lane l its granule l
+    //   K-major: load q is rows 4 (w + 8q) .. +3, lane l row + l / 16, slot
+    //            l % 16 holding granule (l % 16) ^ (row % 16)
+    auto dma_lane_off = [&](bool kmaj, long ld) -> int {
+        if (!kmaj) return 2 * lane;
+        const int r = lane >> 4;
+        const int g = (lane & 15) ^ ((4 * (wave & 3) + r) & 15);
+        return 2 * g + (int)(r * ld);
+    };
+    const int adl = dma_lane_off(AK, lda), bdl = dma_lane_off(BK_, ldb);
+    // load q (0..3) of each operand for the chunk at kc
+    auto dma_piece = [&](int q, int kc, char *as, char *bs) {
+        const int u = wave + 8 * q;   // k row (MN-major) or row group (K-major)
+        const double *ga = AK ? A + kc + (long)(row0 + 4 * u) * lda : A + row0 + (long)(kc + u) * lda;
+        const double *gb = BK_ ? B + kc + (long)(col0 + 4 * u) * ldb : B + col0 + (long)(kc + u) * ldb;
+        lds_load16(ga + adl, as + (AK ? u * 1024 : u * DM_LD * 8));
+        lds_load16(gb + bdl, bs + (BK_ ? u * 1024 : u * DM_LD * 8));
+    };
+    auto dma = [&](int kc, char *as, char *bs) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dma_piece(q, kc, as, bs);
+    };
+
+    // ---- staged fill (edge tiles, partial chunks), after the current chunk's
+    // products so that it holds no registers across them: 4 pairs per operand
+    // per thread, zero outside the operand, written to the same layouts
+    auto pair_of = [&](bool kmaj, int q, int &i, int &k) {
+        const int c = tid + DM_NT * q;
+        if (kmaj) { i = c / (DM_BK / 2); k = 2 * (c % (DM_BK / 2)); }
+        else      { i = 2 * (c % (DM_T / 2)); k = c / (DM_T / 2); }
+    };
+    auto staged_fill = [&](int kc, char *as, char *bs) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i, k;
+            d2 v;
+            pair_of(AK, q, i, k);
+            const int gi = row0 + i, gk = kc + k;
+            if (AK) {
+                v.x = ld_or(A, gk + (long)gi * lda, gi < M && gk < kend, 0.0);
+                v.y = ld_or(A, gk + 1 + (long)gi * lda, gi < M && gk + 1 < kend, 0.0);
+            } else {
+                v.x = ld_or(A, gi + (long)gk * lda, gi < M && gk < kend, 0.0);
+                v.y = ld_or(A, gi + 1 + (long)gk * lda, gi + 1 < M && gk < kend, 0.0);
+            }
+            *reinterpret_cast<d2 *>(as + 8 * OA::lds_index(i, k)) = v;
+            pair_of(BK_, q, i, k);
+            const int gj = col0 + i, gk2 = kc + k;
+            if (BK_) {
+                v.x = ld_or(B, gk2 + (long)gj * ldb, gj < N && gk2 < kend, 0.0);
+                v.y = ld_or(B, gk2 + 1 + (long)gj * ldb, gj < N && gk2 + 1 < kend, 0.0);
+            } else {
+                v.x = ld_or(B, gj + (long)gk2 * ldb, gj < N && gk2 < kend, 0.0);
+                v.y = ld_or(B, gj + 1 + (long)gk2 * ldb, gj + 1 < N && gk2 < kend, 0.0);
+            }
+            *reinterpret_cast<d2 *>(bs + 8 * OB::lds_index(i, k)) = v;
+        }
+    };
+
+    // ---- matrix-core reads: fragment a of the wavefront's rows wm*32 + 16a
+    // + (lane % 16) at k = kk + lane / 16.  MN-major: one per-lane offset;
+    // K-major: one per-lane offset for each of the 8 k steps of a chunk.
+    int aro[DM_BK / 4], bro[DM_BK / 4];
+#pragma unroll
+    for (int s = 0; s < DM_BK / 4; ++s) {
+        const int k = 4 * s + (lane >> 4);
+        aro[s] = 8 * OA::lds_index(lane & 15, k);
+        bro[s] = 8 * OB::lds_index(lane & 15, k);
+        if (!AK && s > 0) aro[s] = aro[0];
+        if (!BK_ && s > 0) bro[s] = bro[0];
+    }
+#pragma unroll
+    for (int s = 0; s < DM_BK / 4; ++s) {
+        if (AK || s == 0) asm volatile("" : "+v"(aro[s]));
+        if (BK_ || s == 0) asm volatile("" : "+v"(bro[s]));
+    }
+    // byte offset of row block r (a multiple of 16) at k step s, beyond the lane offset
+    auto rconst = [&](bool kmaj, int r, int s) { return kmaj ? 8 * r * DM_BK : 8 * (4 * s * DM_LD + r); };
+
+    constexpr int FLUSH_CHUNKS = KFLUSH / DM_BK;
+    d4 acc[FM][FN], tot[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            tot[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+    // the products of one chunk; with `pf`, the direct loads of the next
+    // chunk (at kn, into na / nb) are spread over its first k steps
+    auto compute = [&](const char *as, const char *bs, bool pf, int kn, char *na, char *nb) {
+#pragma unroll
+        for (int s = 0; s < DM_BK / 4; ++s) {
+            if (s < 4 && pf) dma_piece(s, kn, na, nb);
+            double af[FM], bf[FN];
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+                af[a] = *reinterpret_cast<const double *>(as + (AK ? aro[s] : aro[0]) +
+                                                          rconst(AK, wm * TM + a * 16, s));
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+                bf[b] = *reinterpret_cast<const double *>(bs + (BK_ ? bro[s] : bro[0]) +
+                                                          rconst(BK_, wn * TN + b * 16, s));
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+        }
+    };
+
+    const int nchunks = kend > kbeg ? (kend - kbeg + DM_BK - 1) / DM_BK : 0;
+    auto direct = [&](int c) { return interior && kbeg + (c + 1) * DM_BK <= kend; };   // uniform
+    // chunk c from buffer X while chunk c + 1 goes into buffer Y
+    auto step = [&](int c, char *xa, char *xb, char *ya, char *yb) {
+        const bool more = c + 1 < nchunks;
+        const bool dnext = more && direct(c + 1);
+        compute(xa, xb, dnext, kbeg + (c + 1) * DM_BK, ya, yb);
+        if ((c + 1) % FLUSH_CHUNKS == 0) {
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                    tot[a][b] += acc[a][b];
+                    acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                }
+        }
+        if (more && !dnext) staged_fill(kbeg + (c + 1) * DM_BK, ya, yb);
+        wait_vm<0>();
+        stage_barrier();
+    };
+    if (nchunks > 0) {
+        if (direct(0)) dma(kbeg, As0, Bs0);
+        else staged_fill(kbeg, As0, Bs0);
+        wait_vm<0>();
+        stage_barrier();
+        int c = 0;
+        for (; c + 1 < nchunks; c += 2) {
+            step(c, As0, Bs0, As1, Bs1);
+            step(c + 1, As1, Bs1, As0, Bs0);
+        }
+        if (c < nchunks) step(c, As0, Bs0, As1, Bs1);
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) tot[a][b] += acc[a][b];
+
+    const bool lower = p.uplo == GEMM_LOWER;
+    const long ldc = p.ldc;
+    const double alpha = p.alpha, beta = p.beta;
+    const bool raw = p.splitk > 1;
+    const bool with_c = !raw && beta != 0.0;   // uniform
+    d4 cold[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+        const int r = row0 + wm * TM + a * 16 + (lane & 15);
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = col0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
+                cold[a][b][v] = ld_or(C, r + (long)c * ldc, with_c && r < M && c < N && (!lower || r >= c), 0.0);
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < FM; ++a) {
+        const int r = row0 + wm * TM + a * 16 + (lane & 15);
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = col0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
+                if (r < M && c < N && (!lower || r >= c)) {
+                    const double val = tot[a][b][v];
+                    C[r + (long)c * ldc] = raw ? val : (with_c ? alpha * val + beta * cold[a][b][v] : alpha * val);
+                }
+            }
+        }
+    }
+}
+
+template <bool TA, bool TB>
+static hipError_t launch_dma_t(const GemmArgs &a, hipStream_t s) {
+    const int S = a.splitk > 1 ? a.splitk : 1;
+    const long T = tiles_of<DM_T, DM_T>(a);
+    if (T <= 0) return hipSuccess;
+    hipLaunchKernelGGL((dgemm_dma_kernel<TA, TB>), dim3((unsigned)T, S), dim3(DM_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+static hipError_t launch_dma(const GemmArgs &a, hipStream_t s) {
+    if (a.transA) return a.transB ? launch_dma_t<true, true>(a, s) : launch_dma_t<true, false>(a, s);
+    return a.transB ? launch_dma_t<false, true>(a, s) : launch_dma_t<false, false>(a, s);
+}
+
 template <int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 static hipError_t launch_cfg_t(const GemmArgs &a, hipStream_t s) {
     static_assert(BM == BN, "square tiles (the lower-triangle walk assumes them)");
@@ -352,7 +622,7 @@ hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s) {
     if (a.M.host <= 0 || a.N.host <= 0) return hipSuccess;
     // 128 x 128 tiles (8 wavefronts) when they alone fill the 256 compute
     // units; 64 x 64 tiles otherwise
-    if (gemm_tiles(a, 128) >= 256 && a.K.host >= 128) return launch_cfg<128, 128, 32, 4, 2>(a, s);
+    if (gemm_tiles(a, 128) >= 256 && a.K.host >= 128) return launch_dma(a, s);
     return launch_cfg<64, 64, 16, 2, 2>(a, s);
 }
 

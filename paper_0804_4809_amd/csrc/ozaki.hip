@@ -239,30 +239,6 @@ __device__ __forceinline__ void sg_flush_due(std::integer_sequence<int, C...>, b
     ((((J + 1) % sg_period(S, C) == 0 || all) ? sg_flush_class<S, NC, C>(acc, tot) : void()), ...);
 }
 
-// one wavefront-wide direct load: 16 bytes per lane from g into LDS at
-// l + 16 * lane (l uniform across the wavefront)
-__device__ __forceinline__ void lds_load16(const void *g, void *l) {
-    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 16, 0, 0);
-}
-
-// wait until at most N of this wavefront's vector memory loads are pending
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
-// workgroup barrier for the stage buffers: this wavefront's LDS reads have
-// returned, then s_barrier.  Unlike __syncthreads() it does not wait for
-// every outstanding vector load, so direct loads of later stages stay in
-// flight; each wavefront waits for the loads the next stage reads itself.
-__device__ __forceinline__ void stage_barrier() {
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
 // S slices per operand; the pairs of the NC weight classes t + u < NC
 template <int S, int NC>
 __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {

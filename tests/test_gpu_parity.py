@@ -54,6 +54,10 @@ def _print_case(label, **kw):
 @pytest.mark.parametrize("M,N,K,tA,tB", [
     (64, 64, 64, 0, 0), (200, 130, 77, 0, 0), (130, 200, 77, 1, 0), (77, 61, 300, 0, 1),
     (300, 50, 1000, 1, 1), (1, 1, 1, 0, 0), (5, 7, 0, 0, 0), (3000, 2900, 300, 0, 1),
+    # 128-tile launches (direct LDS loads): ragged edges and K tails, every
+    # transposition, an odd leading dimension (staged loads only), all-interior
+    (2100, 2060, 333, 0, 0), (2100, 2060, 333, 1, 0), (2100, 2060, 333, 0, 1), (2100, 2060, 333, 1, 1),
+    (2101, 2049, 257, 1, 0), (2048, 2048, 4096, 1, 0),
 ])
 def test_dgemm_parity(M, N, K, tA, tB):
     _print_case("dgemm", M=M, N=N, K=K, tA=tA, tB=tB)
