@@ -213,6 +213,67 @@ def bench_large_rbf(lib, api, workloads, torch, np, steps):
     return out
 
 
+def _incremental_run(api, torch, Gd, Fd, first, batch, steps):
+    m, n = Gd.shape
+    k = Fd.shape[1]
+    sync = torch.cuda.synchronize
+    # warm both paths (workspace growth) at the full size
+    inc = api.IncrementalLstsq(n, k)
+    inc.append(Gd, Fd)
+    inc.solve()
+    api.lstsq(Gd, Fd)
+    inc = api.IncrementalLstsq(n, k)
+    rows = []
+    n_t = 0
+    for n_new in [first] + list(range(first + batch, n + 1, batch)):
+        Gv = Gd[:, :n_new]
+        sync()
+        t0 = time.perf_counter()
+        inc.append(Gv, Fd)
+        W_inc, r_inc = inc.solve()
+        sync()
+        t_inc = (time.perf_counter() - t0) * 1e3
+        one = []
+        for _ in range(max(1, steps)):
+            sync()
+            t0 = time.perf_counter()
+            W_one, r_one = api.lstsq(Gv, Fd)
+            sync()
+            one.append((time.perf_counter() - t0) * 1e3)
+        rows.append({"columns": n_new, "appended": n_new - n_t, "incremental_ms": round(t_inc, 3),
+                     "one_shot_ms": round(sorted(one)[len(one) // 2], 3), "rank_incremental": r_inc,
+                     "rank_one_shot": r_one,
+                     "relF_W_vs_one_shot": float(torch.linalg.norm(W_inc - W_one) / torch.linalg.norm(W_one))})
+        n_t = n_new
+    return rows
+
+
+def bench_incremental(lib, api, workloads, torch, np, steps):
+    """Incremental least squares (appended Gram and G'F rows, then the method
+    from the Gram matrix) against geninv_dlstsq on the whole matrix so far,
+    on the RBF design and on a tall low-rank matrix where the Gram matrix
+    dominates the cost.  Times include each solve's rank read-back."""
+    dev = torch.device("cuda", 0)
+    out = {}
+    G, F, _ = workloads.c2_problem()
+    Gd = torch.from_numpy(G).to(dev).t().contiguous().t()
+    Fd = torch.from_numpy(F).to(dev).t().contiguous().t()
+    out["rbf_8192x2048"] = {"workload": "RBF design 8192 x 2048 (sigma 0.3, 256 duplicate centers), F 8192 x 8: "
+                                        "1536 centers, then 4 x 128 appended",
+                            "steps": _incremental_run(api, torch, Gd, Fd, 1536, 128, steps)}
+    del Gd, Fd
+    G, F = workloads.lowrank_uv(131072, 1024, 896, seed=5, k=8)
+    Gd = torch.from_numpy(G).to(dev).t().contiguous().t()
+    Fd = torch.from_numpy(F).to(dev).t().contiguous().t()
+    del G, F
+    out["tall_131072x1024"] = {"workload": "G = U V, 131072 x 1024 of rank 896 (N(0,1) factors), F 131072 x 8: "
+                                           "768 columns, then 2 x 128 appended",
+                               "steps": _incremental_run(api, torch, Gd, Fd, 768, 128, steps)}
+    del Gd, Fd
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_table1(lib, api, workloads, torch, np, steps):
     """The paper's timing family (Section 3, Table 1): m = 2n, rank 7n/8,
     entries in [-1, 1], float64 geninv on the GPU, with the four Penrose
@@ -533,6 +594,7 @@ def main():
         forms["batched"], batched_host = bench_batched(api, workloads, torch, np, max(3, min(args.steps, 10)),
                                                        oracle_on)
         forms["table1_sweep"] = bench_table1(lib, api, workloads, torch, np, 5)
+        forms["incremental_lstsq"] = bench_incremental(lib, api, workloads, torch, np, 3)
     if args.large_rbf:
         forms["large_rbf_mixed_vs_fp64"] = bench_large_rbf(lib, api, workloads, torch, np, 2)
 

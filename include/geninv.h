@@ -159,6 +159,30 @@ int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, d
                  const double *A, int lda, const double *B, int ldb, double beta, double *C,
                  int ldc);
 
+/* ---- incremental least squares ---------------------------------------------- */
+
+/* Incremental learning (Section 4): when basis functions (columns of G) are
+ * added to a network, the Gram matrix A = G'G and G'F grow by rows instead of
+ * being formed again.  This call appends the rows of p new columns:
+ *   A[n_old + i, j] = G(:, n_old + i)' G(:, j)    for every j < n_old + p
+ *   B[n_old + i, q] = G(:, n_old + i)' F(:, q)    for q < k
+ * (the new diagonal block is written in full, i.e. with its symmetric upper
+ * part).  G is m x (n_old + p) with the old columns first (ldg >= m), F is
+ * m x k (ldf >= m); A (lda >= n_old + p) and B (ldb >= n_old + p) keep the
+ * rows of earlier calls, which are not read.  n_old = 0 forms both from
+ * scratch.  Cost O(m (n_old + p) p) instead of O(m (n_old + p)^2).  All
+ * pointers DEVICE memory; p = 0 returns at once. */
+int geninv_inc_gram(geninv_ctx *ctx, int m, int n_old, int p, int k, const double *G, int ldg,
+                    const double *F, int ldf, double *A, int lda, double *B, int ldb);
+
+/* W = G^+ F (n x k, ldw >= n) from the lower triangle of the Gram matrix A
+ * (n x n, lda >= n) and B = G'F (n x k, ldb >= n), e.g. as geninv_inc_gram
+ * leaves them: the method from the tolerance on (Section 2, Eq. (1) - (4);
+ * the Appendix after its Gram product), G itself is not needed.  A and B
+ * are read only.  tol and rank as in geninv_dgeninv. */
+int geninv_dlstsq_gram(geninv_ctx *ctx, int n, int k, const double *A, int lda, const double *B, int ldb,
+                       double tol, double *W, int ldw, int *rank);
+
 /* ---- mixed precision: error-free split products on bfloat16 matrix cores - */
 
 /* Y = G^+ (Theorem 1) with the two dense products on the bfloat16 matrix

@@ -60,6 +60,10 @@ _SIGS = [
                                     ctypes.c_int]),
     ("geninv_bchain", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
                                      ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int]),
+    ("geninv_inc_gram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
+                                       ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
+    ("geninv_dlstsq_gram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int,
+                                          ctypes.c_double, _VP, ctypes.c_int, _c_int_p]),
     ("geninv_batch_plan_create", ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int, _c_int_p, _c_int_p,
                                                 ctypes.c_int, ctypes.POINTER(_VP), _c_int_p, ctypes.POINTER(_VP),
                                                 _c_int_p, ctypes.POINTER(_VP), _c_int_p, ctypes.c_double, _VP]),

@@ -136,6 +136,42 @@ def bgram(G: torch.Tensor, slices: int = 4):
     return A
 
 
+class IncrementalLstsq:
+    """Least squares W = G^+ F while columns are appended to G (Section 4's
+    incremental learning): the Gram matrix G'G and G'F grow by the rows of
+    the new columns (geninv_inc_gram), and each solve runs the method from
+    them (geninv_dlstsq_gram).  Column-major device buffers sized for
+    ``nmax`` columns are held here."""
+
+    def __init__(self, nmax: int, k: int, device=None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
+        self.nmax, self.k, self.n = int(nmax), int(k), 0
+        self.A = torch.zeros((self.nmax, self.nmax), dtype=torch.float64, device=self.device).t()
+        self.B = torch.zeros((max(1, self.k), self.nmax), dtype=torch.float64, device=self.device).t()
+
+    def append(self, G: torch.Tensor, F: torch.Tensor):
+        """G: m x n_total, the columns seen so far followed by the new ones; F: m x k."""
+        _dev(G, "G")
+        _dev(F, "F")
+        m, n_total = G.shape
+        if n_total > self.nmax or n_total < self.n or F.shape != (m, self.k):
+            raise ValueError("G must hold the earlier columns first, at most nmax in all; F must be m x k")
+        Gc, ldg = colmajor(G)
+        Fc, ldf = colmajor(F)
+        _check(load().geninv_inc_gram(_ctx(self.device), m, self.n, n_total - self.n, self.k, _p(Gc), ldg, _p(Fc),
+                                      ldf, _p(self.A), self.nmax, _p(self.B), self.nmax), "geninv_inc_gram")
+        self.n = n_total
+
+    def solve(self, tol: float | None = None):
+        """(W, rank) for the columns appended so far."""
+        W = empty_colmajor(self.n, self.k, self.device)
+        r = ctypes.c_int(0)
+        _check(load().geninv_dlstsq_gram(_ctx(self.device), self.n, self.k, _p(self.A), self.nmax, _p(self.B),
+                                         self.nmax, float(tol or 0.0), _p(W), max(1, self.n), ctypes.byref(r)),
+               "geninv_dlstsq_gram")
+        return W, r.value
+
+
 def bchain(P: torch.Tensor, G: torch.Tensor, slices: int = 4):
     """Y = P G' as the mixed form's chain product (rows of P and G sliced)."""
     _dev(P, "P")

@@ -768,6 +768,93 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
     return finish_rank(c, rdev, rank);
 }
 
+// C (M x N, ldc) = op(A) op(B) split over K into `part` when the output is
+// too small to fill the compute units (S partial results, then a reduction)
+static int rows_gemm(geninv_ctx *c, GemmArgs g, double *part, size_t part_elems) {
+    const long tiles = (long)((g.M.host + 63) / 64) * ((g.N.host + 63) / 64);
+    const size_t mn = (size_t)g.M.host * g.N.host;
+    int S = (int)std::min<long>({16L, (256 + tiles - 1) / tiles, (long)g.K.host / 256});
+    while (S > 1 && (size_t)S * mn > part_elems) --S;
+    if (S <= 1) {
+        HIPCHK(launch_dgemm(g, c->stream));
+        return GENINV_OK;
+    }
+    double *C = g.C;
+    const long ldc = g.ldc;
+    g.C = part;
+    g.ldc = g.M.host;
+    g.splitk = S;
+    g.strideC = (long)mn;
+    HIPCHK(launch_dgemm(g, c->stream));
+    HIPCHK(launch_splitk_reduce(part, g.M.host, (long)mn, S, C, ldc, g.M, g.N, 1.0, 0.0, GEMM_FULL, c->stream));
+    return GENINV_OK;
+}
+
+int geninv_inc_gram(geninv_ctx *c, int m, int n_old, int p, int k, const double *G, int ldg, const double *F,
+                    int ldf, double *A, int lda, double *B, int ldb) {
+    if (!c || m < 0 || n_old < 0 || p < 0 || k < 0) return GENINV_EINVAL;
+    const int n_new = n_old + p;
+    if (p == 0) return GENINV_OK;
+    if (!A || bad_ld(lda, n_new) || (k > 0 && (!B || bad_ld(ldb, n_new)))) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    if (m == 0) {
+        HIPCHK(launch_fill(A + n_old, lda, p, n_new, 0.0, c->stream));
+        if (k > 0) HIPCHK(launch_fill(B + n_old, ldb, p, k, 0.0, c->stream));
+        return GENINV_OK;
+    }
+    if (!G || bad_ld(ldg, m) || (k > 0 && (!F || bad_ld(ldf, m)))) return GENINV_EINVAL;
+    // split-K partials: up to 16 copies of the larger of the two row blocks
+    const size_t part_elems = (size_t)16 * p * std::max(n_new, k);
+    CHK(ensure_ws(c, part_elems * sizeof(double)));
+    double *part = at<double>(c, 0);
+    const double *Gn = G + (long)n_old * ldg;   // the p new columns
+    ProfScope ps(c, PC_GRAM, 2.0 * m * (double)p * n_new);
+    // A[n_old + i, j] = G(:, n_old + i)' G(:, j), all j < n_new (the part above
+    // the diagonal of the new block is its symmetric copy)
+    CHK(rows_gemm(c, gemm(Gn, ldg, 1, G, ldg, 0, A + n_old, lda, hdim(p), hdim(n_new), hdim(m), 1.0, 0.0), part,
+                  part_elems));
+    if (k > 0)
+        CHK(rows_gemm(c, gemm(Gn, ldg, 1, F, ldf, 0, B + n_old, ldb, hdim(p), hdim(k), hdim(m), 1.0, 0.0), part,
+                      part_elems));
+    return GENINV_OK;
+}
+
+int geninv_dlstsq_gram(geninv_ctx *c, int n, int k, const double *A, int lda, const double *B, int ldb, double tol,
+                       double *W, int ldw, int *rank) {
+    if (!c || n < 0 || k < 0) return GENINV_EINVAL;
+    if (n == 0) {
+        if (rank) *rank = 0;
+        return GENINV_OK;
+    }
+    if (!A || bad_ld(lda, n) || (k > 0 && (!B || !W || bad_ld(ldb, n) || bad_ld(ldw, n)))) return GENINV_EINVAL;
+    if (k > 4096) return GENINV_ENOTSUP;
+    DeviceGuard g(c->device);
+    const int nn = n;
+    const Layout lay = make_layout(nn, k, 0);
+    CHK(ensure_ws(c, lay.total));
+    double *Aw = at<double>(c, lay.slotA);
+    double *L = at<double>(c, lay.slotL);
+    double *T1 = at<double>(c, lay.t1);
+    double *T2 = at<double>(c, lay.t2);
+    const long ld = nn;
+    // the factorization overwrites its Gram matrix: work on a copy
+    HIPCHK(launch_copy(A, lda, Aw, ld, hdim(nn), hdim(nn), c->stream));
+    CHK(run_frchol(c, lay, Aw, ld, nn, tol, L, ld, at<int>(c, lay.piv), at<double>(c, lay.dvals)));
+    const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
+    Dim r;
+    CHK(rank_dim(c, nn, rdev, &r));
+    CHK(run_factor_inverse(c, lay, L, ld, nn, r, Aw, ld));
+    if (k > 0) {
+        // W = L (M (M (L' B)))
+        ProfScope ps(c, PC_LSTSQ, 0.0);
+        HIPCHK(launch_dgemm(gemm(L, ld, 1, B, ldb, 0, T1, ld, r, hdim(k), hdim(nn), 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(Aw, ld, 0, T1, ld, 0, T2, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(Aw, ld, 0, T2, ld, 0, T1, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(L, ld, 0, T1, ld, 0, W, ldw, hdim(nn), hdim(k), r, 1.0, 0.0), c->stream));
+    }
+    return finish_rank(c, rdev, rank);
+}
+
 int geninv_bslice(geninv_ctx *c, int rows, int cols, const double *X, int ldx, int slices, int transposed,
                   void *planes, int ldp, int *e) {
     if (!c || rows < 0 || cols < 0 || slices < 1 || slices > 6) return GENINV_EINVAL;
