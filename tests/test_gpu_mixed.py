@@ -153,6 +153,34 @@ def test_mixed_svd_family(chain_slices, ns):
     assert err <= MIXED_TOL
 
 
+@pytest.mark.parametrize("kind,m,n,r,slices,chain_slices,ns", [
+    ("uv", 3001, 517, 300, 4, 4, 0),     # ragged against the 128 x 64 tiles and the 64-deep K padding
+    ("uv", 2000, 2000, 1500, 4, 4, 0),   # square
+    ("svd", 5000, 300, 300, 4, 3, 0),    # full column rank, cond 2, 3-slice chain (pairs t + u <= 3)
+    ("uv", 4000, 256, 200, 4, 4, 2),     # two Newton-Schulz steps
+])
+def test_mixed_more_shapes(kind, m, n, r, slices, chain_slices, ns):
+    """G = U V (N(0,1) factors) of exact rank r, or P diag(s) Q' with s in
+    [0.5, 1]: the mixed form's decisions equal the oracle's and Y is within
+    the mixed tolerance."""
+    _case("mixed", kind=kind, m=m, n=n, r=r, slices=slices, chain_slices=chain_slices, ns=ns)
+    if kind == "uv":
+        G, _ = w.lowrank_uv(m, n, r, seed=m + n)
+    else:
+        G = w.svd_family(m, n, r, 0.5, seed=m + n)[0]
+    ref = o.geninv(G)
+    Y, rg, piv = api.mixed(up(G), slices=slices, chain_slices=chain_slices, ns_steps=ns, return_piv=True)
+    err = o.rel_fro(down(Y), ref.Y)
+    # 4 chain slices: the 1e-6 target.  3 chain slices represent P and G with
+    # 24 bits: an entry of Y = P G' (n terms of random sign) then carries
+    # about sqrt(n) 2^-23 relative error, which the target does not cover
+    tol = MIXED_TOL if chain_slices == 4 else 4 * np.sqrt(n) * 2.0 ** -23
+    print(f"  rank gpu {rg} oracle {ref.rank}; relF(Y) {err:.3e} (bound {tol:.1e})", flush=True)
+    assert rg == ref.rank == r
+    assert np.array_equal(down(piv).astype(np.int64), ref.piv)
+    assert err <= tol
+
+
 def test_mixed_rejects_wide_input():
     G = up(np.ones((3, 5)))
     with pytest.raises(api.GeninvError) as e:
