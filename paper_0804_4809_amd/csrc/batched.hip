@@ -209,6 +209,117 @@ __device__ bool block_gj(double *C, long ldc, int r, double *rowp, double *colp)
     return ok;
 }
 
+// Blocked Gauss-Jordan for C in global memory (the per-workgroup slab): the
+// same elimination as block_gj with pivot blocks of nb columns, so that C is
+// read and rewritten once per block instead of once per pivot.  Per block
+// (D = C_bb, Q = old block column, R = block row):
+//   D^-1 in LDS;  R' = D^-1 R;  C_ij -= Q_i R'_j  (i, j outside the block);
+//   C_bj = R'_j;  C_ib = -Q_i D^-1;  C_bb = D^-1.
+// ws (LDS) holds Q (r x NB), R' (NB x r) and D (NB x NB).
+template <int NB>
+__device__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
+    const int tid = threadIdx.x;
+    double *Qs = ws;                    // Qs[i * NB + c] = C(i, b0 + c)
+    double *Rs = Qs + (long)r * NB;     // Rs[c * r + j] = C(b0 + c, j), then R'
+    double *Ds = Rs + (long)NB * r;     // Ds[c * NB + c'] = D(c, c'), then D^-1
+    bool ok = true;
+    for (int b0 = 0; b0 < r; b0 += NB) {
+        const int nb = min(NB, r - b0);
+        __syncthreads();
+        for (int e = tid; e < r * nb; e += BT_THREADS) {
+            const int i = e % r, c = e / r;
+            Qs[i * NB + c] = C[i + (long)(b0 + c) * ldc];
+        }
+        for (int e = tid; e < nb * r; e += BT_THREADS) {
+            const int c = e % nb, j = e / nb;
+            Rs[c * r + j] = C[(b0 + c) + (long)j * ldc];
+        }
+        __syncthreads();
+        for (int e = tid; e < nb * nb; e += BT_THREADS) {
+            const int c = e % nb, c2 = e / nb;
+            Ds[c * NB + c2] = Qs[(b0 + c) * NB + c2];
+        }
+        // D^-1 in place, one pivot at a time (at most 2 elements per thread)
+        for (int p = 0; p < nb; ++p) {
+            __syncthreads();
+            const double pv = Ds[p * NB + p];
+            if (!(pv > 0.0)) ok = false;
+            const double dinv = 1.0 / pv;
+            double v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int e = tid + h * BT_THREADS;
+                v[h] = 0.0;
+                if (e < nb * nb) {
+                    const int c = e % nb, c2 = e / nb;
+                    const double rp = Ds[p * NB + c2] * dinv, cp = Ds[c * NB + p];
+                    v[h] = (c == p) ? ((c2 == p) ? dinv : rp) : ((c2 == p) ? -cp * dinv : Ds[c * NB + c2] - cp * rp);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int e = tid + h * BT_THREADS;
+                if (e < nb * nb) Ds[(e % nb) * NB + e / nb] = v[h];
+            }
+        }
+        __syncthreads();
+        // R' = D^-1 R (registers first: R is read by every output)
+        constexpr int NRR = NB * 256 / BT_THREADS;   // elements per thread for r <= 256
+        double rn[NRR];
+#pragma unroll
+        for (int h = 0; h < NRR; ++h) {
+            const int e = tid + h * BT_THREADS;
+            rn[h] = 0.0;
+            if (e < nb * r) {
+                const int c = e % nb, j = e / nb;
+                double acc = 0.0;
+                for (int c2 = 0; c2 < nb; ++c2) acc = fma(Ds[c * NB + c2], Rs[c2 * r + j], acc);
+                rn[h] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < NRR; ++h) {
+            const int e = tid + h * BT_THREADS;
+            if (e < nb * r) Rs[(e % nb) * r + e / nb] = rn[h];
+        }
+        __syncthreads();
+        // every element of C, 4 x 4 per thread
+        const int tr = (r + 3) / 4;
+        for (int t = tid; t < tr * tr; t += BT_THREADS) {
+            const int i0 = 4 * (t % tr), j0 = 4 * (t / tr);
+            double q[4][NB];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) q[a][c] = (c < nb && i0 + a < r) ? Qs[(i0 + a) * NB + c] : 0.0;
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const int j = j0 + bb;
+                if (j >= r) continue;
+                const bool jin = j >= b0 && j < b0 + nb;
+                double x[NB];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) x[c] = c < nb ? (jin ? Ds[c * NB + (j - b0)] : Rs[c * r + j]) : 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int i = i0 + a;
+                    if (i >= r) continue;
+                    const bool iin = i >= b0 && i < b0 + nb;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) sum = fma(q[a][c], x[c], sum);
+                    double *cij = C + i + (long)j * ldc;
+                    *cij = iin ? x[i - b0] : (jin ? -sum : *cij - sum);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
 struct BatchDesc {
     const float *G; const float *F; double *W;
     int m, n, ldg, ldf, ldw;
@@ -237,6 +348,11 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
     double *Xv = Tv + (long)nmax * k;                    // nmax x k
 
     const int tid = threadIdx.x;
+    // pivot block width of the blocked Gauss-Jordan: 8 or 4, whichever is the
+    // larger whose panels (2 nmax NB + NB^2 doubles) fit the LDS matrix region
+    int gj_nb = 0;
+    for (int nbc = 8; nbc >= 4; nbc /= 2)
+        if (gj_nb == 0 && (long)nl * nl >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
     for (;;) {
         if (tid == 0) ints[0] = atomicAdd(queue, 1);
         __syncthreads();
@@ -277,8 +393,12 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
             if (i < j) C[i + (long)j * ldc] = C[j + (long)i * ldc];
         }
         __syncthreads();
-        // 4. M = C^-1
-        if (!block_gj(C, ldc, r, rowp, colp) && tid == 0) *status = ST_NOTSPD;
+        // 4. M = C^-1: blocked when C is in the slab and the (then unused) LDS
+        // matrix region holds the block panels
+        const bool ok = (C == Cg && gj_nb == 8)   ? block_gj_blocked<8>(C, ldc, r, big)
+                        : (C == Cg && gj_nb == 4) ? block_gj_blocked<4>(C, ldc, r, big)
+                                                  : block_gj(C, ldc, r, rowp, colp);
+        if (!ok && tid == 0) *status = ST_NOTSPD;
         // 5. X = M T, T = M X, W = L T
         for (int e = tid; e < r * k; e += BT_THREADS) {
             const int i = e % r, q = e / r;
