@@ -179,6 +179,89 @@ __device__ int block_frchol(double *A, long lda, int n, double tol, int *cols, i
     return r;
 }
 
+// The same full-rank Cholesky for A in global memory (the per-workgroup
+// slab), in panels of NB columns: a panel (rows j0..n-1) is factored column
+// by column in LDS (ws, n x NB) with the paper's strict test, written back,
+// and the columns to its right take one rank-NB update (4 x 4 register
+// tiles) instead of one update per column.  Decisions and kept values are
+// those of the column-by-column form up to the grouping of the updates.
+template <int NB>
+__device__ int block_frchol_blocked(double *A, long lda, int n, double tol, int *cols, int *cnt, double *ws) {
+    const int tid = threadIdx.x;
+    double *Ps = ws;   // Ps[i * NB + c] = A(i, j0 + c)
+    if (tid == 0) *cnt = 0;
+    for (int j0 = 0; j0 < n; j0 += NB) {
+        const int nb = min(NB, n - j0);
+        __syncthreads();
+        for (int e = tid; e < (n - j0) * nb; e += BT_THREADS) {
+            const int i = j0 + e % (n - j0), c = e / (n - j0);
+            Ps[i * NB + c] = i >= j0 + c ? A[i + (long)(j0 + c) * lda] : 0.0;
+        }
+        for (int c = 0; c < nb; ++c) {
+            const int j = j0 + c;
+            __syncthreads();
+            const double d = Ps[j * NB + c];
+            const bool keep = d > tol;
+            __syncthreads();   // every thread has read the pivot before it is overwritten
+            if (keep) {
+                const double sq = sqrt(d);
+                for (int i = j + 1 + tid; i < n; i += BT_THREADS) Ps[i * NB + c] /= sq;
+                if (tid == 0) {
+                    Ps[j * NB + c] = sq;
+                    cols[*cnt] = j;
+                    *cnt = *cnt + 1;
+                }
+                __syncthreads();
+                // the panel's later columns: Ps(i, c2) -= L(i, j) L(j0 + c2, j), i >= j0 + c2
+                for (int e = tid; e < (n - j0) * nb; e += BT_THREADS) {
+                    const int i = j0 + e % (n - j0), c2 = e / (n - j0);
+                    if (c2 > c && i >= j0 + c2) Ps[i * NB + c2] -= Ps[i * NB + c] * Ps[(j0 + c2) * NB + c];
+                }
+            } else {
+                for (int i = j + tid; i < n; i += BT_THREADS) Ps[i * NB + c] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < (n - j0) * nb; e += BT_THREADS) {
+            const int i = j0 + e % (n - j0), c = e / (n - j0);
+            if (i >= j0 + c) A[i + (long)(j0 + c) * lda] = Ps[i * NB + c];
+        }
+        // columns l >= j0 + nb, rows i >= l: A(i, l) -= sum_c L(i, j0 + c) L(l, j0 + c)
+        const int t0 = j0 + nb, nt = (n - t0 + 3) / 4;
+        for (int t = tid; t < nt * nt; t += BT_THREADS) {
+            const int ti = t % nt, tl = t / nt;
+            if (ti < tl) continue;   // tiles on or below the diagonal
+            const int i0 = t0 + 4 * ti, l0 = t0 + 4 * tl;
+            double q[4][NB];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) q[a][c] = (c < nb && i0 + a < n) ? Ps[(i0 + a) * NB + c] : 0.0;
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                const int l = l0 + bb;
+                if (l >= n) continue;
+                double x[NB];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) x[c] = c < nb ? Ps[l * NB + c] : 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int i = i0 + a;
+                    if (i >= n || i < l) continue;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) sum = fma(q[a][c], x[c], sum);
+                    A[i + (long)l * lda] -= sum;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int r = *cnt;
+    __syncthreads();
+    return r;
+}
+
 // in-place Gauss-Jordan inverse of the SPD matrix C (r x r, full storage);
 // returns false if a pivot is not positive
 __device__ bool block_gj(double *C, long ldc, int r, double *rowp, double *colp) {
@@ -310,8 +393,11 @@ __device__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
                     double sum = 0.0;
 #pragma unroll
                     for (int c = 0; c < NB; ++c) sum = fma(q[a][c], x[c], sum);
+                    double xi = 0.0;   // x[i - b0] without a dynamically indexed register array
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) xi = (c == i - b0) ? x[c] : xi;
                     double *cij = C + i + (long)j * ldc;
-                    *cij = iin ? x[i - b0] : (jin ? -sum : *cij - sum);
+                    *cij = iin ? xi : (jin ? -sum : *cij - sum);
                 }
             }
         }
@@ -353,6 +439,10 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
     int gj_nb = 0;
     for (int nbc = 8; nbc >= 4; nbc /= 2)
         if (gj_nb == 0 && (long)nl * nl >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
+    // panel width of the blocked Cholesky (panel: nmax x NB doubles in the same region)
+    int fr_nb = 0;
+    for (int nbc = 8; nbc >= 4; nbc /= 2)
+        if (fr_nb == 0 && (long)nl * nl >= (long)nmax * nbc) fr_nb = nbc;
     for (;;) {
         if (tid == 0) ints[0] = atomicAdd(queue, 1);
         __syncthreads();
@@ -371,7 +461,9 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
         // 2. tolerance and full-rank Cholesky in place
         const double tol = block_tol(A, lda, n, user_tol, red, &ints[2]);
         if (ints[2] && tid == 0) *status = ST_NONFINITE;
-        const int r = block_frchol(A, lda, n, tol, cols, &ints[1]);
+        const int r = (A == Lg && fr_nb == 8)   ? block_frchol_blocked<8>(A, lda, n, tol, cols, &ints[1], big)
+                      : (A == Lg && fr_nb == 4) ? block_frchol_blocked<4>(A, lda, n, tol, cols, &ints[1], big)
+                                                : block_frchol(A, lda, n, tol, cols, &ints[1]);
         if (tid == 0) rank[b] = r;
         if (r == 0) {
             for (int e = tid; e < n * k; e += BT_THREADS) d.W[(e % n) + (long)(e / n) * d.ldw] = 0.0;
