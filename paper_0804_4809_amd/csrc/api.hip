@@ -1103,7 +1103,15 @@ int geninv_batch_plan_create(geninv_ctx *c, geninv_batch_plan **plan, int batch,
     std::vector<char> desc(batched_desc_bytes() * std::max(batch, 1));
     for (int b = 0; b < batch; ++b)
         batched_fill_desc(desc.data() + b * batched_desc_bytes(), G[b], F[b], W[b], m[b], n[b], ldg[b], ldf[b], ldw[b]);
-    p->nl = std::min(128, nmax);
+    // default LDS threshold: the largest candidate whose LDS fits a compute unit
+    p->nl = 0;
+    for (int nl : {128, 96, 64, 48, 32}) {
+        const int nlc = std::min(nl, nmax);
+        if (batched_lds_bytes(nlc, nmax, k) <= 160 * 1024) {
+            p->nl = nlc;
+            break;
+        }
+    }
     p->grid = 256 * wgs_per_cu(p->nl, nmax, k);
     p->max_grid = 256 * 4;
     const size_t slab_bytes = batched_slab_doubles(nmax, k) * sizeof(double) * p->max_grid;

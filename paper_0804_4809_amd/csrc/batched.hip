@@ -23,7 +23,7 @@
 namespace geninv {
 
 constexpr int BT_THREADS = 256;
-constexpr int BT_STAGE_ROWS = 8;
+constexpr int BT_STAGE_ROWS = 16;
 
 __device__ __forceinline__ double ldv(const float *p) { return (double)*p; }
 __device__ __forceinline__ double ldv(const double *p) { return *p; }
@@ -80,7 +80,7 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
             }
             __syncthreads();
             if (active) {
-#pragma unroll
+#pragma unroll 4
                 for (int r = 0; r < BT_STAGE_ROWS; ++r) {
                     double av[4], bv[4];
                     const double *srow = stage + r * sw;
