@@ -434,15 +434,17 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
     double *Xv = Tv + (long)nmax * k;                    // nmax x k
 
     const int tid = threadIdx.x;
-    // pivot block width of the blocked Gauss-Jordan: 8 or 4, whichever is the
-    // larger whose panels (2 nmax NB + NB^2 doubles) fit the LDS matrix region
-    int gj_nb = 0;
-    for (int nbc = 8; nbc >= 4; nbc /= 2)
-        if (gj_nb == 0 && (long)nl * nl >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
-    // panel width of the blocked Cholesky (panel: nmax x NB doubles in the same region)
-    int fr_nb = 0;
-    for (int nbc = 8; nbc >= 4; nbc /= 2)
-        if (fr_nb == 0 && (long)nl * nl >= (long)nmax * nbc) fr_nb = nbc;
+    // The blocked Cholesky and Gauss-Jordan keep their panels in the LDS
+    // matrix region and the staging rows behind it (contiguous, and both
+    // idle while A or L'L lives in the slab).  Block width 8 or 4, whichever
+    // is the larger that fits: panels of nmax x NB (Cholesky), 2 nmax NB +
+    // NB^2 doubles (Gauss-Jordan).
+    const long ws_cap = (long)nl * nl + (long)BT_STAGE_ROWS * (nmax + k);
+    int gj_nb = 0, fr_nb = 0;
+    for (int nbc = 8; nbc >= 4; nbc /= 2) {
+        if (gj_nb == 0 && ws_cap >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
+        if (fr_nb == 0 && ws_cap >= (long)nmax * nbc) fr_nb = nbc;
+    }
     for (;;) {
         if (tid == 0) ints[0] = atomicAdd(queue, 1);
         __syncthreads();
@@ -485,8 +487,8 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
             if (i < j) C[i + (long)j * ldc] = C[j + (long)i * ldc];
         }
         __syncthreads();
-        // 4. M = C^-1: blocked when C is in the slab and the (then unused) LDS
-        // matrix region holds the block panels
+        // 4. M = C^-1: blocked when C is in the slab (panels in the LDS matrix
+        // region and staging rows)
         const bool ok = (C == Cg && gj_nb == 8)   ? block_gj_blocked<8>(C, ldc, r, big)
                         : (C == Cg && gj_nb == 4) ? block_gj_blocked<4>(C, ldc, r, big)
                                                   : block_gj(C, ldc, r, rowp, colp);
