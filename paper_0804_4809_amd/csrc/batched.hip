@@ -64,19 +64,17 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
             for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
         for (int k0 = 0; k0 < rows; k0 += BT_STAGE_ROWS) {
             __syncthreads();
+            // branch-free loads (clamped address, then select) so that a
+            // thread's loads of the stage issue back to back
             for (int e = tid; e < BT_STAGE_ROWS * sw; e += BT_THREADS) {
                 const int r = e % BT_STAGE_ROWS, c = e / BT_STAGE_ROWS;
                 const int row = k0 + r;
-                double v = 0.0;
-                if (row < rows) {
-                    if (c < nc) {
-                        const int src = cols ? cols[c] : c;
-                        if (!tri || row >= src) v = ldv(X + row + (long)src * ldx);
-                    } else {
-                        v = ldv(F + row + (long)(c - nc) * ldf);
-                    }
-                }
-                stage[r * sw + c] = v;
+                const bool inx = c < nc;
+                const int src = inx ? (cols ? cols[c] : c) : 0;
+                const bool ok = row < rows && (!inx || !tri || row >= src);
+                const T *p = inx ? X + row + (long)src * ldx : F + row + (long)(c - nc) * ldf;
+                const double v = ldv(ok ? p : X);
+                stage[r * sw + c] = ok ? v : 0.0;
             }
             __syncthreads();
             if (active) {
