@@ -8,7 +8,8 @@
 // one workgroup:
 //
 //   1. A = G'G and B = G'F, float32 inputs accumulated in float64 (register
-//      tiles of 4 x 4 outputs per thread, G staged through LDS 8 rows at a time)
+//      tiles of 8 x 4 outputs per thread, G staged through LDS 16 rows at a
+//      time)
 //   2. tol = 1e-9 min{A_kk > 0} (or the caller's), then the full-rank Cholesky
 //      of A in place, column by column with the paper's strict test
 //   3. C = L'L and T = L'B, as a second Gram product over the kept columns
@@ -35,9 +36,12 @@ __device__ __forceinline__ double ldv(const double *p) { return *p; }
 template <typename T>
 __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *cols, bool tri, const T *F, long ldf,
                            int k, double *Aout, long lda, double *Bout, long ldb, double *stage) {
+    // a thread owns 8 output rows x 4 output columns: tiles (ti, tj) with
+    // 4 tj <= 8 ti + 7 cover the lower triangle of X'X (2 ti + 2 of them in
+    // row block ti), then the blocks of X'F
     const int tid = threadIdx.x;
-    const int nt = (nc + 3) / 4, kt = (k + 3) / 4;
-    const int tri_tiles = nt * (nt + 1) / 2;
+    const int nt = (nc + 7) / 8, kt = (k + 3) / 4;
+    const int tri_tiles = nt * (nt + 1);
     const int ntiles = tri_tiles + nt * kt;
     const int sw = nc + k;                 // stage width (columns)
     for (int base = 0; base < ntiles; base += BT_THREADS) {
@@ -46,10 +50,10 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
         bool fcol = false, active = t < ntiles;
         if (active) {
             if (t < tri_tiles) {
-                ti = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-                while (ti * (ti + 1) / 2 > t) --ti;
-                while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-                tj = t - ti * (ti + 1) / 2;
+                ti = (int)((sqrtf(4.0f * t + 1.0f) - 1.0f) * 0.5f);
+                while (ti * (ti + 1) > t) --ti;
+                while ((ti + 1) * (ti + 2) <= t) ++ti;
+                tj = t - ti * (ti + 1);
             } else {
                 const int u = t - tri_tiles;
                 ti = u / kt;
@@ -57,9 +61,9 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
                 fcol = true;
             }
         }
-        double acc[4][4];
+        double acc[8][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 8; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
         for (int k0 = 0; k0 < rows; k0 += BT_STAGE_ROWS) {
@@ -80,11 +84,11 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
             if (active) {
 #pragma unroll 4
                 for (int r = 0; r < BT_STAGE_ROWS; ++r) {
-                    double av[4], bv[4];
+                    double av[8], bv[4];
                     const double *srow = stage + r * sw;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const int ci = ti * 4 + a;
+                    for (int a = 0; a < 8; ++a) {
+                        const int ci = ti * 8 + a;
                         av[a] = ci < nc ? srow[ci] : 0.0;
                     }
 #pragma unroll
@@ -93,7 +97,7 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
                         bv[b] = (fcol ? (tj * 4 + b < k) : (cj < nc)) ? srow[cj] : 0.0;
                     }
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
+                    for (int a = 0; a < 8; ++a)
 #pragma unroll
                         for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
                 }
@@ -101,10 +105,10 @@ __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *co
         }
         if (active) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 8; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int i = ti * 4 + a, j = tj * 4 + b;
+                    const int i = ti * 8 + a, j = tj * 4 + b;
                     if (i >= nc) continue;
                     if (fcol) {
                         if (j < k) Bout[i + (long)j * ldb] = acc[a][b];
