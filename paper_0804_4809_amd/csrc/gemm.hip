@@ -11,7 +11,10 @@
 // (64 lanes each); each wavefront owns (BM/WM) x (BN/WN) and issues
 // v_mfma_f64_16x16x4_f64 on 16 x 16 blocks.  K is consumed in chunks of BK
 // staged through double-buffered LDS; the next chunk's global loads are in
-// flight while the current chunk feeds the matrix cores.  Operands are read
+// flight while the current chunk feeds the matrix cores.  dgemm_kernel does
+// this through registers (64 x 64 tiles, small and skinny products);
+// dgemm_dma_kernel (128 x 128 tiles, the large products) loads straight into
+// LDS.  Operands are read
 // as 16-byte pairs from per-thread 32-bit offsets computed once, against a
 // chunk origin that is the only thing that moves (few vector instructions per
 // load: the address arithmetic was what held the matrix cores back).

@@ -176,15 +176,15 @@ __global__ __launch_bounds__(256) void slice_rows_t_kernel(const double *X, long
 // A workgroup (8 wavefronts, 4 x 2) owns a 128 x 64 tile of C; a wavefront
 // owns 32 x 32 (2 x 2 MFMA blocks).  K is taken 32 at a time: the 32-wide
 // slab of every slice of both operands (S x 192 rows of 64 bytes) goes
-// straight from global memory into LDS (global_load_lds_dwordx4, double
-// buffered: the next stage's loads are in flight while the current one
-// runs), and each wavefront then forms every slice pair from its registers.
+// straight from global memory into LDS (global_load_lds_dwordx4, three
+// buffers: the loads of stage st + 2 are in flight while stage st runs), and
+// each wavefront then forms the slice pairs from its registers.
 // Such a load writes 16 consecutive bytes per lane, a wavefront a 1 KiB
 // chunk of 16 rows; the four 16-byte granules of row r sit in the chunk
 // XOR-permuted by (r / 4) mod 4, so that the operand reads (16 rows, one
-// granule) meet distinct banks.  The grid is one-dimensional over the needed tiles
-// (lower triangle for the Gram matrix), with the tile order of the float64
-// GEMM (each XCD a contiguous run down the columns of C).
+// granule) meet distinct banks.  The grid is one-dimensional over the needed
+// tiles (lower triangle for the Gram matrix); each XCD takes a contiguous run
+// of a tile order that walks groups of SG_GM tile rows column by column.
 // ---------------------------------------------------------------------------
 constexpr int SG_BM = 128, SG_BN = 64, SG_BK = 32;
 constexpr int SG_ROWS = SG_BM + SG_BN;    // LDS rows per slice per stage: A rows, then B rows
