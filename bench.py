@@ -274,6 +274,39 @@ def bench_incremental(lib, api, workloads, torch, np, steps):
     return out
 
 
+def bench_spd_inverse(lib, api, workloads, torch, np, steps):
+    """The inverse of L'L two ways on the GPU: the Gauss-Jordan sweep of the
+    method's path (geninv_dspdinv) and Newton-Schulz iteration on the matrix
+    cores (geninv_dspdinv_ns), on the L'L of the RBF (8192 x 2048) and SVD
+    family (32768 x 4096) workloads."""
+    dev = torch.device("cuda", 0)
+    sync = torch.cuda.synchronize
+    out = {}
+    for name, G in (("rbf_8192x2048", workloads.c2_problem()[0]), ("svd_32768x4096", workloads.c3_problem()[0])):
+        Gd = torch.from_numpy(G).to(dev)
+        del G
+        A = api.gram(Gd)
+        del Gd
+        fr = api.frchol(A)
+        L = fr.L
+        B = api.dgemm(L, L, transA=True)
+        del A, fr
+        M_gj = api.spd_inverse(B)
+        t_gj = _timed(lambda: api.spd_inverse(B), steps, sync)
+        M_ns, iters, resid = api.spd_inverse_ns(B)
+        t_ns = _timed(lambda: api.spd_inverse_ns(B), max(1, steps // 2), sync)
+        r = B.shape[0]
+        eye = torch.eye(r, dtype=torch.float64, device=dev)
+        res_gj = float(torch.linalg.norm(eye - B @ M_gj) / r ** 0.5)
+        out[name] = {"r": r, "gauss_jordan_ms": round(t_gj, 3), "newton_schulz_ms": round(t_ns, 3),
+                     "newton_schulz_iterations": iters, "residual_newton_schulz": resid,
+                     "residual_gauss_jordan": res_gj,
+                     "relF_between": float(torch.linalg.norm(M_ns - M_gj) / torch.linalg.norm(M_gj))}
+        del B, L, M_gj, M_ns, eye
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_table1(lib, api, workloads, torch, np, steps):
     """The paper's timing family (Section 3, Table 1): m = 2n, rank 7n/8,
     entries in [-1, 1], float64 geninv on the GPU, with the four Penrose
@@ -595,6 +628,7 @@ def main():
                                                        oracle_on)
         forms["table1_sweep"] = bench_table1(lib, api, workloads, torch, np, 5)
         forms["incremental_lstsq"] = bench_incremental(lib, api, workloads, torch, np, 3)
+        forms["spd_inverse_gj_vs_newton_schulz"] = bench_spd_inverse(lib, api, workloads, torch, np, 3)
     if args.large_rbf:
         forms["large_rbf_mixed_vs_fp64"] = bench_large_rbf(lib, api, workloads, torch, np, 2)
 

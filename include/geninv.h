@@ -147,6 +147,19 @@ int geninv_dfrchol(geninv_ctx *ctx, int n, const double *A, int lda, double tol,
  * device status to ENOTSPD. */
 int geninv_dspdinv(geninv_ctx *ctx, int r, const double *B, int ldb, double *M, int ldm);
 
+/* The same inverse by Newton-Schulz iteration X <- X (2I - B X) on the
+ * float64 matrix cores, X_0 = I / ||B||_F: the parallel alternative to the
+ * sequential sweep (Section 2 cites O(log r) parallel time for such
+ * inverses).  Each step forms the residual ||I - B X||_F / sqrt(r) of the
+ * current X (one device-to-host read); the iteration stops when it no longer
+ * falls (about cond(B) u) or after max_iter steps, and M receives the iterate
+ * with the smallest residual.  *iters and *resid (HOST, optional) report the
+ * number of residual evaluations and that residual.  Convergence takes about
+ * log2(cond(B) sqrt(r)) + 6 steps of two r^3 products each.  ENOTSPD if ||B|| = 0,
+ * ENONFINITE on a non-finite residual. */
+int geninv_dspdinv_ns(geninv_ctx *ctx, int r, const double *B, int ldb, double *M, int ldm, int max_iter,
+                      int *iters, double *resid);
+
 /* Y = L M M L' G' (Theorem 1) for given factors: L n x r (ldl >= n),
  * M r x r symmetric (ldm >= r), G m x n (ldg >= m), Y n x m (ldy >= n). */
 int geninv_dchain(geninv_ctx *ctx, int m, int n, int r, const double *L, int ldl,

@@ -50,6 +50,8 @@ _SIGS = [
     ("geninv_dfrchol", ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double, _VP, ctypes.c_int,
                                       _VP, _VP, _VP, _c_int_p]),
     ("geninv_dspdinv", ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
+    ("geninv_dspdinv_ns", ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int,
+                                         _c_int_p, ctypes.POINTER(ctypes.c_double)]),
     ("geninv_dchain", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
                                      ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
     ("geninv_mixed", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double,

@@ -260,6 +260,20 @@ def spd_inverse(B: torch.Tensor):
     return M
 
 
+def spd_inverse_ns(B: torch.Tensor, max_iter: int = 100):
+    """(M, iterations, residual): M = B^-1 for SPD B by Newton-Schulz
+    iteration on the matrix cores (geninv_dspdinv_ns)."""
+    _dev(B, "B")
+    r = B.shape[0]
+    Bc, ldb = colmajor(B)
+    M = empty_colmajor(r, r, B.device)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0.0)
+    _check(load().geninv_dspdinv_ns(_ctx(B.device), r, _p(Bc), ldb, _p(M), max(1, r), int(max_iter),
+                                    ctypes.byref(it), ctypes.byref(res)), "geninv_dspdinv_ns")
+    return M, it.value, res.value
+
+
 def chain(L: torch.Tensor, M: torch.Tensor, G: torch.Tensor):
     """Y = L M M L' G' for given factors (Theorem 1)."""
     for t, nm in ((L, "L"), (M, "M"), (G, "G")):

@@ -2,6 +2,7 @@
 // steps on one HIP stream (declarations and contracts in include/geninv.h).
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -653,6 +654,75 @@ int geninv_dspdinv(geninv_ctx *c, int r, const double *B, int ldb, double *M, in
     CHK(ensure_ws(c, lay.total));
     HIPCHK(launch_copy(B, ldb, M, ldm, hdim(r), hdim(r), c->stream));
     return run_spdinv(c, lay, M, ldm, hdim(r));
+}
+
+}  // extern "C"
+
+namespace geninv {
+hipError_t launch_ns_scaled_eye(double *X, long ldx, int n, double a, hipStream_t s);
+hipError_t launch_ns_two_minus(double *T, long ldt, int n, double *sum2, hipStream_t s);
+hipError_t launch_fro2(const double *B, long ldb, int n, double *sum2, hipStream_t s);
+}  // namespace geninv
+
+extern "C" {
+
+int geninv_dspdinv_ns(geninv_ctx *c, int r, const double *B, int ldb, double *M, int ldm, int max_iter, int *iters,
+                      double *resid) {
+    if (!c || r < 0 || max_iter < 1) return GENINV_EINVAL;
+    if (iters) *iters = 0;
+    if (resid) *resid = 0.0;
+    if (r == 0) return GENINV_OK;
+    if (!B || !M || bad_ld(ldb, r) || bad_ld(ldm, r)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    const Layout lay = make_layout(r, 0);
+    CHK(ensure_ws(c, lay.total + 256));
+    double *X = at<double>(c, lay.slotA), *T = at<double>(c, lay.slotL), *Xn = at<double>(c, lay.slotK);
+    double *sum2 = at<double>(c, lay.total);   // one device scalar after the layout
+    const long ld = r;
+    auto read_sum = [&](double *host) -> int {
+        HIPCHK(hipMemcpyAsync(host, sum2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return GENINV_OK;
+    };
+    double nb2 = 0.0;
+    HIPCHK(launch_fill(sum2, 1, 1, 1, 0.0, c->stream));
+    HIPCHK(launch_fro2(B, ldb, r, sum2, c->stream));
+    CHK(read_sum(&nb2));
+    if (!(nb2 > 0.0) || !std::isfinite(nb2)) return nb2 > 0.0 ? GENINV_ENONFINITE : GENINV_ENOTSPD;
+    // X_0 = I / ||B||_F: the eigenvalues of I - B X_0 lie in [0, 1) for SPD B
+    HIPCHK(launch_ns_scaled_eye(X, ld, r, 1.0 / std::sqrt(nb2), c->stream));
+    // Each step evaluates the residual of the current X first; once it stops
+    // falling (the rounding floor, about cond(B) u), the previous iterate,
+    // still in Xn, is the result.
+    double prev = std::numeric_limits<double>::infinity();
+    const double *result = X;
+    int evals = 0;
+    for (int it = 0; it < max_iter; ++it) {
+        // T = B X, then T := 2I - T with the residual ||I - B X||_F of this X
+        HIPCHK(launch_dgemm(gemm(B, ldb, 0, X, ld, 0, T, ld, hdim(r), hdim(r), hdim(r), 1.0, 0.0), c->stream));
+        double s2 = 0.0;
+        HIPCHK(launch_fill(sum2, 1, 1, 1, 0.0, c->stream));
+        HIPCHK(launch_ns_two_minus(T, ld, r, sum2, c->stream));
+        CHK(read_sum(&s2));
+        ++evals;
+        const double rho = std::sqrt(s2 / r);
+        if (!std::isfinite(rho)) return GENINV_ENONFINITE;
+        if (rho >= prev) {
+            result = Xn;   // X_{k-1}
+            break;
+        }
+        prev = rho;
+        result = X;
+        if (rho < 1e-15) break;
+        // X <- X (2I - B X)
+        HIPCHK(launch_dgemm(gemm(X, ld, 0, T, ld, 0, Xn, ld, hdim(r), hdim(r), hdim(r), 1.0, 0.0), c->stream));
+        std::swap(X, Xn);
+        result = X;   // not yet evaluated; kept if the iteration count runs out
+    }
+    HIPCHK(launch_copy(result, ld, M, ldm, hdim(r), hdim(r), c->stream));
+    if (iters) *iters = evals;
+    if (resid) *resid = prev;
+    return GENINV_OK;
 }
 
 int geninv_dchain(geninv_ctx *c, int m, int n, int r, const double *L, int ldl, const double *M, int ldm,

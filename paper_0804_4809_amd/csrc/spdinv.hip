@@ -310,4 +310,63 @@ hipError_t launch_gj_update(double *B, long ldb, Dim r, int b, const double *D, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Newton-Schulz iteration X <- X (2I - B X) for the inverse of an SPD matrix
+// (the parallel-inverse alternative to the Gauss-Jordan sweep): the two
+// products per step run on the float64 GEMM; these kernels set X_0 = a I,
+// form 2I - T from T = B X while summing the squared residual (I - T), and
+// the squared Frobenius norm of B.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ns_scaled_eye_kernel(double *X, long ldx, int n, double a) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    if (i < n && j < n) X[i + (long)j * ldx] = i == j ? a : 0.0;
+}
+
+// sum2 += sum over the block of v^2 (one atomic per workgroup)
+__device__ __forceinline__ void block_sum_sq(double v, double *sum2) {
+    __shared__ double red[256];
+    red[threadIdx.x] = v * v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(sum2, red[0]);
+}
+
+__global__ __launch_bounds__(256) void ns_two_minus_kernel(double *T, long ldt, int n, double *sum2) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    double d = 0.0;
+    if (i < n && j < n) {
+        const double t = T[i + (long)j * ldt];
+        const double e = i == j ? 1.0 : 0.0;
+        d = e - t;
+        T[i + (long)j * ldt] = 2.0 * e - t;
+    }
+    block_sum_sq(d, sum2);
+}
+
+__global__ __launch_bounds__(256) void fro2_kernel(const double *B, long ldb, int n, double *sum2) {
+    const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+    block_sum_sq(i < n && j < n ? B[i + (long)j * ldb] : 0.0, sum2);
+}
+
+hipError_t launch_ns_scaled_eye(double *X, long ldx, int n, double a, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ns_scaled_eye_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, X, ldx, n, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_two_minus(double *T, long ldt, int n, double *sum2, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(ns_two_minus_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, T, ldt, n, sum2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fro2(const double *B, long ldb, int n, double *sum2, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fro2_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, B, ldb, n, sum2);
+    return hipGetLastError();
+}
+
 }  // namespace geninv

@@ -189,6 +189,26 @@ def test_spdinv_parity():
         assert o.rel_fro(M, ref) <= 50 * cond * 2.2e-16 * r, r
 
 
+@pytest.mark.parametrize("r,smin", [(1, 1.0), (64, 1e-2), (200, 1e-3), (513, 1e-1), (1000, 1e-3)])
+def test_spdinv_newton_schulz_parity(r, smin):
+    """Newton-Schulz inverse of B = X'X (X with singular values log-spaced from
+    1 to smin, cond(B) = smin^-2) against the oracle's SPD inverse, within the
+    same rounding bound as the Gauss-Jordan sweep; it converges in about
+    log2(cond sqrt(r)) + 6 steps (X_0 = I / ||B||_F starts sqrt(r) further
+    from 1 / lambda_max than the ideal scaling)."""
+    _print_case("spdinv_ns", r=r, smin=smin)
+    X = w.svd_family(r + 7, r, r, smin, seed=r)[0]
+    B = X.T @ X
+    ref = o.spd_inverse(B)
+    M, iters, resid = api.spd_inverse_ns(up(B))
+    M = down(M)
+    cond = np.linalg.cond(B)
+    print(f"  cond {cond:.2e} iterations {iters} residual {resid:.2e}", flush=True)
+    assert iters <= np.log2(cond * np.sqrt(r)) + 12
+    assert resid <= 10 * cond * 2.2e-16 * np.sqrt(r) + 1e-15
+    assert o.rel_fro(M, ref) <= 50 * cond * 2.2e-16 * r
+
+
 def test_chain_parity_same_factors():
     _print_case("chain")
     G, _ = w.lowrank_uv(900, 260, 170, seed=31)
