@@ -13,7 +13,7 @@
 //      each of which
 //        - factors the updated diagonal block column by column with the
 //          paper's strict "pivot > tol" test, keeping accepted columns only
-//          (lane i owning row i in registers);
+//          (the block held in registers in a 2-D cyclic layout);
 //        - for its own rows below the block, solves for the new L entries by
 //          forward substitution against the accepted columns, in the same
 //          column order as the paper;
@@ -89,11 +89,22 @@ hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double 
 // ---- panel factor ---------------------------------------------------------
 //
 // Every workgroup is one wavefront.  Each one factors the diagonal block
-// itself (lane i owning row i in registers, the pivot and the scaled column
-// broadcast lane to lane with v_readlane), so that no workgroup waits for
-// another.  Workgroup 0 then writes the block of L, the pivots and the new
-// rank; every other workgroup solves FR_TRS rows below the block against the
-// accepted columns, four lanes per row.
+// itself, so that no workgroup waits for another.  Workgroup 0 then writes
+// the block of L, the pivots and the new rank; every other workgroup solves
+// FR_TRS rows below the block against the accepted columns, four lanes per
+// row.
+//
+// The block is held in a 2-D cyclic layout: lane a + 8 b keeps
+// v[r][c] = A(8 r + a, 8 c + b) for r >= c (register blocks with r < c lie
+// wholly above the diagonal and are never touched).  For an accepted column
+// J the lanes with b = J mod 8 scale their entries of column J and publish
+// L(., J) (zero at rows <= J) as eight doubles per row residue a in LDS;
+// every lane then reads the eight values for its row residue and the eight
+// for its column residue and applies the rank-one update to its registers
+// on or past block J / 8.  A column costs two short LDS round trips and at
+// most 36 fused multiply-adds per lane, where a row-per-lane layout needs a
+// 63-way register broadcast.  Zeros at rows <= J keep finished columns and
+// column J itself unchanged, so no lane tests its own indices.
 //
 // The substitution runs over the accepted columns only, renumbered 0..a-1 in
 // the paper's column order: for row x of the panel restricted to the accepted
@@ -107,8 +118,8 @@ hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double 
 constexpr int FR_TRS = 16;             // rows per workgroup in the substitution
 constexpr int FR_TSEG = 18;            // T row: 4 segments of 18 doubles (16 used): 16-byte aligned, banks spread
 constexpr int FR_TLD = 4 * FR_TSEG;
-constexpr int FR_BC = 16;              // broadcasts in flight per group in the block factorization
 constexpr int FR_CH = 8;               // substitution columns per uniform chunk
+constexpr int FR_RB = FR_NB / 8;       // register blocks per dimension of the cyclic layout
 
 // lane (4 (lane / 4) + Q)'s value of v, within each group of four lanes
 template <int Q>
@@ -119,50 +130,103 @@ __device__ __forceinline__ double quad_bcast(double v) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-struct FrBlock {
-    double row[FR_NB];    // row `lane` of the block (lower triangle), then of L
-    int acc;              // accepted so far (uniform)
-    double mydiag;        // L(lane, lane) if column `lane` is accepted, else 1
-    double mypiv;         // updated pivot value of column `lane`
-    int myc;              // compact index of column `lane` if accepted, else -1
+// LDS the factorization shares within the wavefront
+struct FrShared {
+    double colv[2][8][FR_RB];   // A(8 r + a, J) at [J & 1][a][r] before scaling, zero at rows <= J
+    double dvs[FR_NB];          // pivot value of every column at its test
+    double rdc[FR_NB];          // 1 / L(pivot row of c, c) per compact column c
+    int ccomp[FR_NB];           // compact index of block column j, or -1 if dropped
+    int pcol[FR_NB];            // block column of compact column c
 };
 
+struct FrBlock {
+    double v[FR_RB][FR_RB];   // v[r][c] = A(8 r + a, 8 c + b), then L; r >= c only
+    int acc;                  // accepted so far (uniform)
+    double dv;                // pivot value of block column `lane`
+    int cc;                   // compact index of block column `lane`, or -1
+    int pc;                   // block column of compact column `lane`
+    double rd;                // 1 / L(pivot row, c) of compact column c = `lane`
+};
+
+// 1 / sqrt(d) for a positive normal d: the hardware estimate refined by two
+// Newton steps (within an ulp or so; a much shorter dependency chain than a
+// square root followed by a division)
+__device__ __forceinline__ double rsqrt_refined(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = __builtin_fma(0.5 * y, __builtin_fma(-d * y, y, 1.0), y);
+    return y;
+}
+
+// Orders the LDS accesses of the wavefront's lanes (they execute in program
+// order within one wavefront, so no wait for completion is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Column J of the block: the paper's pivot test, then sqrt, scaling and the
-// rank-one update of the later columns (every index static after expansion).
+// rank-one update of the later columns (every register index static).  The
+// column is published before scaling, so that the LDS round trip overlaps
+// the reciprocal square root; every lane scales what it reads by the same
+// factor, so its L(i, J) equals the owner's bit for bit.
 template <int J>
-__device__ __forceinline__ void fr_column(FrBlock &s, int lane, int w, double tol) {
+__device__ __forceinline__ void fr_column(FrBlock &s, FrShared &sh, int a, int b, int lane, int w, double tol) {
     if (J >= w) return;
-    const double d = lane_bcast(s.row[J], J);   // current pivot of column J
-    const bool keep = d > tol;                   // uniform
-    if (lane == J) {
-        s.mypiv = d;
-        s.myc = keep ? s.acc : -1;
-    }
+    constexpr int jr = J >> 3, jb = J & 7, r0 = jr & ~1;
+    const double d = lane_bcast(s.v[jr][jr], 9 * jb);   // current pivot of column J
+    const bool keep = d > tol;                          // uniform
+    s.dv = lane == J ? d : s.dv;
+    s.cc = lane == J ? (keep ? s.acc : -1) : s.cc;
     if (!keep) return;
-    const double sq = sqrt(d);
-    const double lij = lane > J ? s.row[J] / sq : (lane == J ? sq : 0.0);
-    s.row[J] = lij;
-    if (lane == J) s.mydiag = sq;
+    double(*cv)[FR_RB] = sh.colv[J & 1];
+    if (b == jb) {
 #pragma unroll
-    for (int g = (J + 1) / FR_BC; g < FR_NB / FR_BC; ++g) {
-        // FR_BC broadcasts into distinct scalar registers, then the FMAs
-        double bc[FR_BC];
-#pragma unroll
-        for (int e = 0; e < FR_BC; ++e)
-            if (g * FR_BC + e > J) bc[e] = lane_bcast(lij, g * FR_BC + e);
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int e = 0; e < FR_BC; ++e)
-            if (g * FR_BC + e > J) s.row[g * FR_BC + e] -= lij * bc[e];
-        __builtin_amdgcn_sched_barrier(0);
+        for (int r = r0; r < FR_RB; r += 2) {
+            const double e0 = (r >= jr && 8 * r + a > J) ? s.v[r][jr] : 0.0;
+            const double e1 = 8 * (r + 1) + a > J ? s.v[r + 1][jr] : 0.0;
+            *reinterpret_cast<double2 *>(&cv[a][r]) = double2{e0, e1};
+        }
     }
+    wave_sync();
+    double xi[FR_RB], xl[FR_RB];
+#pragma unroll
+    for (int r = r0; r < FR_RB; r += 2) {
+        const double2 ti = *reinterpret_cast<const double2 *>(&cv[a][r]);
+        const double2 tl = *reinterpret_cast<const double2 *>(&cv[b][r]);
+        xi[r] = ti.x;
+        xi[r + 1] = ti.y;
+        xl[r] = tl.x;
+        xl[r + 1] = tl.y;
+    }
+    const double y = rsqrt_refined(d);
+    s.pc = lane == s.acc ? J : s.pc;
+    s.rd = lane == s.acc ? y : s.rd;
+    if (b == jb) {
+#pragma unroll
+        for (int r = jr; r < FR_RB; ++r) {
+            const int i = 8 * r + a;
+            s.v[r][jr] = i > J ? s.v[r][jr] * y : (i == J ? d * y : s.v[r][jr]);
+        }
+    }
+#pragma unroll
+    for (int r = jr; r < FR_RB; ++r) {
+        xi[r] *= y;
+        xl[r] *= y;
+    }
+#pragma unroll
+    for (int c = jr; c < FR_RB; ++c)
+#pragma unroll
+        for (int r = c; r < FR_RB; ++r) s.v[r][c] = __builtin_fma(-xi[r], xl[c], s.v[r][c]);
+    wave_sync();
     ++s.acc;
 }
 
 template <int... J>
-__device__ __forceinline__ void fr_factor(std::integer_sequence<int, J...>, FrBlock &s, int lane, int w,
-                                          double tol) {
-    (fr_column<J>(s, lane, w, tol), ...);
+__device__ __forceinline__ void fr_factor(std::integer_sequence<int, J...>, FrBlock &s, FrShared &sh, int a, int b,
+                                          int lane, int w, double tol) {
+    (fr_column<J>(s, sh, a, b, lane, w, tol), ...);
 }
 
 // Compact column J of the substitution (branch-free; J >= a contributes 0).
@@ -198,11 +262,13 @@ __global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restri
                                                           double *dvals) {
     __shared__ __align__(16) double T[FR_NB][FR_TLD];   // T[c][seg(c')] = L(pivot row of c', c), 0 unless c' > c
     __shared__ double S[FR_TRS][FR_NB + 1];             // row staging for the renumbering of the columns
-    __shared__ double rdc[FR_NB];                       // 1 / L(pivot row of c, c)
-    __shared__ int pcol[FR_NB];                         // block column of compact column c
+    __shared__ __align__(16) FrShared sh;
+    double *rdc = sh.rdc;
+    int *pcol = sh.pcol;
 
     const int lane = threadIdx.x;
     const int q = lane & 3;
+    const int ra = lane & 7, cb = lane >> 3;   // row and column residue in the cyclic layout
     const int r0 = rank_buf[p];
     const double tol = *tolp;
     const int irel = w + (int)(blockIdx.x - 1) * FR_TRS + (lane >> 2);
@@ -214,47 +280,69 @@ __global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restri
 #pragma unroll
     for (int t = 0; t < 16; ++t) x[t] = ld_or(P, irel + (long)(4 * t + q) * ldp, trs && 4 * t + q < w, 0.0);
 
+    // the lower triangle of the block in the cyclic layout (zero above the
+    // diagonal and past w)
     FrBlock s;
 #pragma unroll
-    for (int l = 0; l < FR_NB; ++l) s.row[l] = ld_or(P, lane + (long)l * ldp, lane < w && l <= lane, 0.0);
+    for (int r = 0; r < FR_RB; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            const int i = 8 * r + ra, j = 8 * c + cb;
+            s.v[r][c] = ld_or(P, i + (long)j * ldp, i < w && j <= i, 0.0);
+        }
     s.acc = 0;
-    s.mydiag = 1.0;
-    s.mypiv = 0.0;
-    s.myc = -1;
+    s.dv = 0.0;
+    s.cc = -1;
+    s.pc = 0;
+    s.rd = 0.0;
     if (blockIdx.x > 0) {
         // zero T, so that the columns of the last chunk past a read zeros
         double *tf = &T[0][0];
 #pragma unroll
         for (int e = 0; e < FR_NB * FR_TLD / 64; ++e) tf[e * 64 + lane] = 0.0;
     }
-    fr_factor(std::make_integer_sequence<int, FR_NB>{}, s, lane, w, tol);
+    __syncthreads();
+    fr_factor(std::make_integer_sequence<int, FR_NB>{}, s, sh, ra, cb, lane, w, tol);
     const int a = s.acc;
+    sh.dvs[lane] = s.dv;
+    sh.ccomp[lane] = s.cc;
+    sh.pcol[lane] = s.pc;
+    sh.rdc[lane] = s.rd;
+    __syncthreads();
+
+    // compact index of the rows and columns this lane holds
+    int ci[FR_RB], cj[FR_RB];
+#pragma unroll
+    for (int r = 0; r < FR_RB; ++r) {
+        ci[r] = sh.ccomp[8 * r + ra];
+        cj[r] = sh.ccomp[8 * r + cb];
+    }
 
     if (blockIdx.x == 0) {
         // diagonal block of L, pivots, pivot values, running rank
-        if (lane < w) {
 #pragma unroll
-            for (int j = 0; j < FR_NB; ++j) {
-                const int cj = __builtin_amdgcn_readlane(s.myc, j);   // uniform
-                if (cj >= 0 && j <= lane) L[(k0 + lane) + (long)(r0 + cj) * ldl] = s.row[j];
+        for (int r = 0; r < FR_RB; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                const int i = 8 * r + ra, j = 8 * c + cb;
+                if (i < w && j <= i && cj[c] >= 0) L[(k0 + i) + (long)(r0 + cj[c]) * ldl] = s.v[r][c];
             }
-            if (dvals) dvals[k0 + lane] = s.mypiv;
-            if (piv && s.myc >= 0) piv[r0 + s.myc] = k0 + lane;
-        }
+        if (lane < w && dvals) dvals[k0 + lane] = sh.dvs[lane];
+        if (lane < a && piv) piv[r0 + lane] = k0 + pcol[lane];
         if (lane == 0) rank_buf[p + 1] = r0 + a;
         return;
     }
 
-    // compact triangle T and the reciprocal pivots, from the registers
+    // compact triangle T from the registers: entries at two accepted columns
+    // i > j (so that ci > cj); the rest stays zero
 #pragma unroll
-    for (int j = 0; j < FR_NB; ++j) {
-        const int cj = __builtin_amdgcn_readlane(s.myc, j);
-        if (cj >= 0 && s.myc >= 0) T[cj][FR_TSEG * (s.myc & 3) + (s.myc >> 2)] = lane > j ? s.row[j] : 0.0;
-    }
-    if (s.myc >= 0) {
-        rdc[s.myc] = 1.0 / s.mydiag;
-        pcol[s.myc] = lane;
-    }
+    for (int r = 0; r < FR_RB; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) {
+            const int i = 8 * r + ra, j = 8 * c + cb;
+            if (i < w && j < i && ci[r] >= 0 && cj[c] >= 0)
+                T[cj[c]][FR_TSEG * (ci[r] & 3) + (ci[r] >> 2)] = s.v[r][c];
+        }
     // renumber the row's entries to compact column order through LDS
     const int rl = lane >> 2;
     if (trs) {
