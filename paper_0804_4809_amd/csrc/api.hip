@@ -124,6 +124,7 @@ void prof_resolve(geninv_ctx *c) {
 struct Layout {
     size_t slotA, slotL, slotK, slotP, part, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, gpart, total;
     int gram_splits;   // split-K factor of the float64 Gram matrix (partials in gpart)
+    size_t split_elems;   // doubles in gpart: the Gram's partials, then those of the later products
 };
 
 constexpr size_t GPART_MAX_BYTES = size_t(2) << 30;   // bound on the Gram's split-K partials
@@ -160,11 +161,19 @@ Layout make_layout(int nn, int k, int kdim = 0) {
     L.t2 = take((size_t)nn * std::max(k, 1) * sizeof(double));
     L.gram_splits = 1;
     L.gpart = 0;
+    L.split_elems = 0;
+    size_t gbytes = 0;
     if (kdim > 0 && nn > 0) {
-        const size_t n2 = (size_t)nn * nn * sizeof(double);
         const int cap = (int)std::max<size_t>(1, std::min<size_t>(16, GPART_MAX_BYTES / n2));
         L.gram_splits = choose_splits(lower_tiles128(nn), kdim, cap);
-        if (L.gram_splits > 1) L.gpart = take(L.gram_splits * n2);
+        if (L.gram_splits > 1) gbytes = L.gram_splits * n2;
+    }
+    // the products after the factorization (L'L, L M, K K') reuse the area
+    // for their own split-K partials, up to 8 n x n layers
+    const size_t cbytes = nn >= 512 ? std::min<size_t>(GPART_MAX_BYTES, 8 * n2) : 0;
+    if (std::max(gbytes, cbytes) > 0) {
+        L.gpart = take(std::max(gbytes, cbytes));
+        L.split_elems = std::max(gbytes, cbytes) / sizeof(double);
     }
     L.total = off;
     return L;
@@ -228,6 +237,60 @@ int gemm_splitk(geninv_ctx *c, const Layout &lay, GemmArgs g, int min_tiles = 25
     p.strideC = (long)g.M.host * g.N.host;
     HIPCHK(launch_dgemm(p, c->stream));
     HIPCHK(launch_splitk_reduce(part, g.M.host, p.strideC, S, C, ldc, g.M, g.N, alpha, beta, g.uplo, c->stream));
+    return GENINV_OK;
+}
+
+// Split count for a product of `tiles` 128 x 128 tiles and depth K that lets
+// the 128 x 128 kernel run: the cheapest S (by the cost model of
+// choose_splits: rounds of 256 workgroups times chunk-steps, plus the
+// reduction) among those with tiles * S >= 256 and at least 256 of K per
+// split; 0 when there is none.
+int fill_splits(long tiles, int K, int maxS) {
+    const double chunk_us = 4.5, reduce_us = 0.035;
+    const int smin = (int)std::max<long>(2, (255 + tiles) / tiles);
+    int best = 0;
+    double bestc = 1e300;
+    for (int S = smin; S <= maxS; ++S) {
+        const long kper = ((long)(K + S - 1) / S + 31) / 32 * 32;
+        if (kper < 256) break;
+        const long rounds = (tiles * S + 255) / 256;
+        const double cost = rounds * (kper / 32) * chunk_us + (S + 1) * tiles * reduce_us;
+        if (cost < bestc) {
+            bestc = cost;
+            best = S;
+        }
+    }
+    return best;
+}
+
+// C = op(A) op(B) for a product with host-known sizes after the
+// factorization.  When its 128 x 128 tiles alone would leave compute units
+// idle, K is split so that the 128 x 128 direct-to-LDS kernel runs full
+// rounds; the partials go to gpart and are summed in a fixed order.
+// Otherwise (or with a rank read from device memory) one launch.
+int gemm_fill(geninv_ctx *c, const Layout &lay, GemmArgs g) {
+    const long M = g.M.host, N = g.N.host;
+    const int K = g.K.host;
+    const bool host = !g.M.dev && !g.N.dev && !g.K.dev;
+    if (!host || M <= 0 || N <= 0 || lay.split_elems == 0 || (g.uplo == GEMM_LOWER && M != N)) {
+        HIPCHK(launch_dgemm(g, c->stream));
+        return GENINV_OK;
+    }
+    const long tiles = g.uplo == GEMM_LOWER ? lower_tiles128((int)M) : ((M + 127) / 128) * ((N + 127) / 128);
+    const int cap = (int)std::min<size_t>(64, lay.split_elems / (size_t)(M * N));
+    const int S = tiles >= 256 ? 0 : fill_splits(tiles, K, cap);
+    if (S < 2) {
+        HIPCHK(launch_dgemm(g, c->stream));
+        return GENINV_OK;
+    }
+    double *part = at<double>(c, lay.gpart);
+    GemmArgs p = g;
+    p.C = part;
+    p.ldc = M;
+    p.splitk = S;
+    p.strideC = M * N;
+    HIPCHK(launch_dgemm(p, c->stream));
+    HIPCHK(launch_splitk_reduce(part, M, M * N, S, g.C, g.ldc, g.M, g.N, g.alpha, g.beta, g.uplo, c->stream));
     return GENINV_OK;
 }
 
@@ -330,7 +393,7 @@ int run_factor_inverse(geninv_ctx *c, const Layout &lay, const double *L, long l
     GemmArgs g = gemm(L, ldl, 1, L, ldl, 0, dst, ldd, r, r, hdim(nn), 1.0, 0.0, GEMM_LOWER);
     {
         ProfScope ps(c, PC_LTL, 0.0);
-        HIPCHK(launch_dgemm(g, c->stream));
+        CHK(gemm_fill(c, lay, g));
     }
     {
         ProfScope ps(c, PC_MIRROR, 0.0);
@@ -736,8 +799,8 @@ int geninv_dchain(geninv_ctx *c, int m, int n, int r, const double *L, int ldl, 
     CHK(ensure_ws(c, lay.total));
     double *K = at<double>(c, lay.slotK);
     double *P = at<double>(c, lay.slotP);
-    HIPCHK(launch_dgemm(gemm(L, ldl, 0, M, ldm, 0, K, n, hdim(n), hdim(r), hdim(r), 1.0, 0.0), c->stream));
-    HIPCHK(launch_dgemm(gemm(K, n, 0, K, n, 1, P, n, hdim(n), hdim(n), hdim(r), 1.0, 0.0, GEMM_LOWER), c->stream));
+    CHK(gemm_fill(c, lay, gemm(L, ldl, 0, M, ldm, 0, K, n, hdim(n), hdim(r), hdim(r), 1.0, 0.0)));
+    CHK(gemm_fill(c, lay, gemm(K, n, 0, K, n, 1, P, n, hdim(n), hdim(n), hdim(r), 1.0, 0.0, GEMM_LOWER)));
     HIPCHK(launch_mirror_lower(P, n, hdim(n), c->stream));
     HIPCHK(launch_dgemm(gemm(P, n, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
     return GENINV_OK;
@@ -775,11 +838,11 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     // 5. K = L M, P = K K' (= (G'G)^+), then Y = P G' or Y = G' P
     {
         ProfScope ps(c, PC_CHAIN_K, 0.0);
-        HIPCHK(launch_dgemm(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0), c->stream));
+        CHK(gemm_fill(c, lay, gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0)));
     }
     {
         ProfScope ps(c, PC_CHAIN_P, 0.0);
-        HIPCHK(launch_dgemm(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER), c->stream));
+        CHK(gemm_fill(c, lay, gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER)));
     }
     {
         ProfScope ps(c, PC_MIRROR, 0.0);
@@ -1050,11 +1113,11 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
     // 5. K = L M, P = K K' (float64)
     {
         ProfScope ps(c, PC_CHAIN_K, 0.0);
-        HIPCHK(launch_dgemm(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0), c->stream));
+        CHK(gemm_fill(c, lay, gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0)));
     }
     {
         ProfScope ps(c, PC_CHAIN_P, 0.0);
-        HIPCHK(launch_dgemm(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER), c->stream));
+        CHK(gemm_fill(c, lay, gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER)));
         HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
     }
     // 6. Newton-Schulz steps on P = (G'G)^+ in factored form: P <- 2P - P A P
