@@ -122,7 +122,7 @@ void prof_resolve(geninv_ctx *c) {
 // Workspace carve-up for a problem whose factored dimension is nn (the
 // smaller of m, n) with k right-hand sides.
 struct Layout {
-    size_t slotA, slotL, slotK, slotP, part, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, gpart, total;
+    size_t slotA, slotL, slotK, slotP, part, lpan, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, gpart, total;
     int gram_splits;   // split-K factor of the float64 Gram matrix (partials in gpart)
     size_t split_elems;   // doubles in gpart: the Gram's partials, then those of the later products
 };
@@ -149,6 +149,7 @@ Layout make_layout(int nn, int k, int kdim = 0) {
     L.slotK = take(n2);
     L.slotP = take(n2);
     L.part = take((size_t)PART_S * nn * std::max(FR_NB, k) * sizeof(double));
+    L.lpan = take((size_t)nn * FR_NB * sizeof(double));
     L.dbuf = take((size_t)GJ_NB * GJ_NB * sizeof(double));
     L.rrow = take((size_t)GJ_NB * nn * sizeof(double));
     L.ccol = take((size_t)nn * GJ_NB * sizeof(double));
@@ -319,13 +320,18 @@ int run_gram(geninv_ctx *c, const Layout &lay, const double *G, long ldg, bool t
 }
 
 // Steps 2-3: tolerance and full-rank Cholesky of the lower triangle of A
-// (nn x nn), which is overwritten panel by panel with the updated panels.
-// L (nn x nn, ldl) is zeroed and receives the compacted factor.
+// (nn x nn), right-looking: after panel p is factored, its new columns
+// (uncompacted in lpan, zero where a column was dropped) are subtracted
+// from the lower triangle of the trailing matrix in place,
+//   A[k1:, k1:] -= Lp[k1:, :w] Lp[k1:, :w]'   (k1 = k0 + w),
+// an MFMA product of depth w with host-known sizes, so that every later
+// panel arrives fully updated.  The zero columns of dropped pivots add
+// nothing.  L (nn x nn, ldl) is zeroed and receives the compacted factor.
 int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, double user_tol, double *L,
                long ldl, int *piv, double *dvals) {
     double *tolp = at<double>(c, lay.tol);
     int *rank_buf = at<int>(c, lay.rank);
-    double *part = at<double>(c, lay.part);
+    double *Lp = at<double>(c, lay.lpan);
     const int np = (nn + FR_NB - 1) / FR_NB;
     {
         ProfScope ps(c, PC_TOL, 0.0);
@@ -336,34 +342,23 @@ int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, do
         HIPCHK(launch_fill(L, ldl, nn, nn, 0.0, c->stream));
         HIPCHK(launch_fill_int(rank_buf, np + 1, 0, c->stream));
     }
-    const long ldp = nn;
-    const long strideP = (long)nn * FR_NB;
     for (int p = 0; p < np; ++p) {
         const int k0 = p * FR_NB;
         const int w = std::min(FR_NB, nn - k0);
-        const int rows = nn - k0;
         double *panel = A + k0 + (long)k0 * lda;
-        if (p > 0) {
-            // panel -= L[k0:, :r0] L[k0:k0+w, :r0]'  (r0 = rank_buf[p], on device)
-            ProfScope ps(c, PC_PANEL_GEMM, 0.0);
-            const int tiles = (rows + 63) / 64;
-            const int S = std::max(1, std::min({PART_S, (512 + tiles - 1) / tiles, std::max(1, k0 / 128)}));
-            GemmArgs g = gemm(L + k0, ldl, 0, L + k0, ldl, 1, panel, lda, hdim(rows), hdim(w),
-                              ddim(k0, rank_buf + p), -1.0, 1.0);
-            if (S == 1) {
-                HIPCHK(launch_dgemm(g, c->stream));
-            } else {
-                g.C = part;
-                g.ldc = ldp;
-                g.splitk = S;
-                g.strideC = strideP;
-                HIPCHK(launch_dgemm(g, c->stream));
-                HIPCHK(launch_splitk_reduce(part, ldp, strideP, S, panel, lda, hdim(rows), hdim(w), -1.0, 1.0,
-                                            GEMM_FULL, c->stream));
-            }
+        {
+            ProfScope ps(c, PC_PANEL_FACTOR, 0.0);
+            HIPCHK(launch_frchol_panel(panel, lda, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals, Lp, nn,
+                                       c->stream));
         }
-        ProfScope ps(c, PC_PANEL_FACTOR, 0.0);
-        HIPCHK(launch_frchol_panel(panel, lda, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals, c->stream));
+        const int k1 = k0 + w;
+        const int rows = nn - k1;
+        if (rows > 0) {
+            ProfScope ps(c, PC_PANEL_GEMM, 2.0 * rows * (rows + 1.0) / 2.0 * w);
+            HIPCHK(launch_dgemm(gemm(Lp + k1, nn, 0, Lp + k1, nn, 1, A + k1 + (long)k1 * lda, lda, hdim(rows),
+                                     hdim(rows), hdim(w), -1.0, 1.0, GEMM_LOWER),
+                                c->stream));
+        }
     }
     return GENINV_OK;
 }

@@ -104,7 +104,8 @@ constexpr int FR_NB = 64;          // panel width
 hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double *tol_out, int *status,
                       hipStream_t s);
 hipError_t launch_frchol_panel(const double *P, long ldp, double *L, long ldl, int *rank_buf, int p, int k0,
-                               int w, int n, const double *tol, int *piv, double *dvals, hipStream_t s);
+                               int w, int n, const double *tol, int *piv, double *dvals, double *Lp, long ldlp,
+                               hipStream_t s);
 
 // SPD inverse by block Gauss-Jordan (spdinv.hip)
 constexpr int GJ_NB = 64;

@@ -1,24 +1,26 @@
 // Full-rank Cholesky factorization with column dropping (Section 2, Eq. (1);
-// the Appendix's loop over k) on gfx950, blocked left-looking.
+// the Appendix's loop over k) on gfx950, blocked right-looking.
 //
 // The paper processes column k of A = G'G by subtracting the contribution of
 // every column of L accepted so far, comparing the updated pivot with tol,
 // and either keeping the column (sqrt and scale) or dropping it.  Here the
-// columns are taken FR_NB at a time (a panel):
+// columns are taken FR_NB at a time (a panel); when panel p starts, every
+// earlier accepted column has already been subtracted from it:
 //
-//   1. panel update (an MFMA GEMM, split over K when the panel is tall and
-//      narrow, gemm.hip): A[k0:n, k0:k0+w] -= L[k0:n, :r0] L[k0:k0+w, :r0]'
-//      over the r0 columns accepted before the panel, written in place;
-//   2. panel factor (this file), one launch of one-wavefront workgroups,
+//   1. panel factor (this file), one launch of one-wavefront workgroups,
 //      each of which
-//        - factors the updated diagonal block column by column with the
-//          paper's strict "pivot > tol" test, keeping accepted columns only
-//          (the block held in registers in a 2-D cyclic layout);
+//        - factors the diagonal block column by column with the paper's
+//          strict "pivot > tol" test, keeping accepted columns only (the
+//          block held in registers in a 2-D cyclic layout);
 //        - for its own rows below the block, solves for the new L entries by
 //          forward substitution against the accepted columns, in the same
-//          column order as the paper;
+//          column order as the paper, and writes them both compacted into L
+//          and uncompacted (zero columns where a pivot was dropped) into the
+//          n x FR_NB panel buffer Lp;
 //      workgroup 0 writes the diagonal block of L, the pivot indices and the
-//      new running rank rank_buf[p+1] = r0 + (accepted in this panel).
+//      new running rank rank_buf[p+1] = r0 + (accepted in this panel);
+//   2. trailing update (an MFMA GEMM, gemm.hip): the lower triangle of
+//      A[k1:n, k1:n] (k1 = k0 + w) loses Lp[k1:n, :] Lp[k1:n, :]', in place.
 //
 // Accepted columns are written compacted (column r0, r0+1, ...), so L comes
 // out n x r with zeros above each column's pivot row.  The running rank lives
@@ -259,7 +261,7 @@ __device__ __forceinline__ void trs_solve(std::integer_sequence<int, G...>, doub
 __global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restrict__ P, long ldp,
                                                           double *__restrict__ L, long ldl, int *rank_buf, int p,
                                                           int k0, int w, int n, const double *tolp, int *piv,
-                                                          double *dvals) {
+                                                          double *dvals, double *__restrict__ Lp, long ldlp) {
     __shared__ __align__(16) double T[FR_NB][FR_TLD];   // T[c][seg(c')] = L(pivot row of c', c), 0 unless c' > c
     __shared__ double S[FR_TRS][FR_NB + 1];             // row staging for the renumbering of the columns
     __shared__ __align__(16) FrShared sh;
@@ -364,14 +366,24 @@ __global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restri
 #pragma unroll
     for (int t = 0; t < 16; ++t)
         if (4 * t + q < a) lrow[(long)(4 * t + q) * ldl] = x[t];
+    // the same row of the panel's new columns, uncompacted: block column j of
+    // L, or zero where column j was dropped
+    double *prow = Lp + (k0 + irel);
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int c = 4 * t + q;
+        if (c < a) prow[(long)pcol[c] * ldlp] = x[t];
+        if (c < w && sh.ccomp[c] < 0) prow[(long)c * ldlp] = 0.0;
+    }
 }
 
 hipError_t launch_frchol_panel(const double *P, long ldp, double *L, long ldl, int *rank_buf, int p, int k0, int w,
-                               int n, const double *tol, int *piv, double *dvals, hipStream_t s) {
+                               int n, const double *tol, int *piv, double *dvals, double *Lp, long ldlp,
+                               hipStream_t s) {
     const int below = n - k0 - w;   // rows under the block
     dim3 grid(1 + (below + FR_TRS - 1) / FR_TRS);
     hipLaunchKernelGGL(frchol_panel_kernel, grid, dim3(64), 0, s, P, ldp, L, ldl, rank_buf, p, k0, w, n, tol, piv,
-                       dvals);
+                       dvals, Lp, ldlp);
     return hipGetLastError();
 }
 
