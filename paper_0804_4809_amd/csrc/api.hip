@@ -125,6 +125,7 @@ struct Layout {
     size_t slotA, slotL, slotK, slotP, part, lpan, dbuf, rrow, ccol, dvals, tol, rank, piv, t0, t1, t2, gpart, total;
     int gram_splits;   // split-K factor of the float64 Gram matrix (partials in gpart)
     size_t split_elems;   // doubles in gpart: the Gram's partials, then those of the later products
+    size_t part_elems;    // doubles in part
 };
 
 constexpr size_t GPART_MAX_BYTES = size_t(2) << 30;   // bound on the Gram's split-K partials
@@ -148,7 +149,8 @@ Layout make_layout(int nn, int k, int kdim = 0) {
     L.slotL = take(n2);
     L.slotK = take(n2);
     L.slotP = take(n2);
-    L.part = take((size_t)PART_S * nn * std::max(FR_NB, k) * sizeof(double));
+    L.part_elems = (size_t)PART_S * nn * std::max(FR_NB, k);
+    L.part = take(L.part_elems * sizeof(double));
     L.lpan = take((size_t)nn * FR_NB * sizeof(double));
     L.dbuf = take((size_t)GJ_NB * GJ_NB * sizeof(double));
     L.rrow = take((size_t)GJ_NB * nn * sizeof(double));
@@ -220,9 +222,12 @@ GemmArgs gemm(const double *A, long lda, int tA, const double *B, long ldb, int 
 int gemm_splitk(geninv_ctx *c, const Layout &lay, GemmArgs g, int min_tiles = 256) {
     const int tiles = ((g.M.host + 63) / 64) * ((g.N.host + 63) / 64);
     int S = 1;
-    // the partial buffer holds PART_S * nn * max(64, k) doubles and M.host <= nn
-    if (tiles < min_tiles && g.K.host >= 512)
-        S = std::min({PART_S, (min_tiles + tiles - 1) / tiles, g.K.host / 256});
+    // about 1024 workgroups (several fit on a compute unit: these launches
+    // are bound by load latency), at least 256 of K each, within `part`
+    if (tiles < min_tiles && g.K.host >= 512) {
+        S = (int)std::min<long>({64L, (1024 + tiles - 1) / tiles, (long)g.K.host / 256});
+        while (S > 1 && (size_t)S * g.M.host * g.N.host > lay.part_elems) --S;
+    }
     if (S <= 1) {
         HIPCHK(launch_dgemm(g, c->stream));
         return GENINV_OK;
@@ -650,10 +655,12 @@ int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, dou
     GemmArgs a = gemm(A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0, C, ldc, hdim(M), hdim(N), hdim(K), alpha,
                       beta);
     ProfScope ps(c, PC_GEMM, 2.0 * M * N * K);
-    // a skinny product (few output tiles, long K) is split over K
+    // a skinny product (few output tiles, long K) is split over K: about 1024
+    // workgroups (several fit on a compute unit; these launches are bound by
+    // load latency), at least 256 of K each
     const long tiles = gemm_tiles(a, 64);
     if (tiles < 256 && K >= 1024) {
-        const int S = (int)std::min<long>({PART_S, (256 + tiles - 1) / tiles, K / 256});
+        const int S = (int)std::min<long>({64L, (1024 + tiles - 1) / tiles, (long)K / 256});
         if (S > 1) {
             CHK(ensure_ws(c, (size_t)S * M * N * sizeof(double)));
             GemmArgs p = a;

@@ -360,6 +360,29 @@ def test_geninv_c2_full_size():
     assert rg <= rr * (1.0 + 10 * spread)
 
 
+def test_geninv_split_products_parity():
+    """A size at which L'L, L M and K K' are split over K (partials summed in
+    a fixed order, so that the 128 x 128 kernel fills the chip): rank and Y
+    as the oracle's within the float64 bound, and the device-resident-rank
+    form, which launches the same products unsplit, within that bound of it."""
+    _print_case("geninv split products", cfg="lowrank 6000x1536 r1200")
+    G, _ = w.lowrank_uv(6000, 1536, 1200, 61)
+    ref = o.geninv(G)
+    Y, r = api.geninv(up(G))
+    assert r == ref.rank == 1200
+    bound = max(FP64_TOL, 10 * o.self_spread(G, base=ref))
+    err = o.rel_fro(down(Y), ref.Y)
+    print(f"  relF(Y)={err:.3e} bound={bound:.3e}", flush=True)
+    assert err <= bound
+    try:
+        api.set_host_sync(False, DEV)
+        Y2, r2 = api.geninv(up(G))
+    finally:
+        api.set_host_sync(True, DEV)
+    assert r2 == r
+    assert o.rel_fro(down(Y2), down(Y)) <= bound
+
+
 @pytest.mark.parametrize("case", ["c1", "lowrank_1000x300_r200", "wide_300x700_r120", "zero", "lstsq_3000x257"])
 def test_host_sync_off_matches_on(case):
     """Device-resident rank (every later launch sized for the bound) gives the
