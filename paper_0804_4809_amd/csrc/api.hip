@@ -33,6 +33,14 @@ struct ProfState {
 
 struct geninv_batch_plan;
 
+namespace geninv {
+// skinny.hip
+int skinny_padded_width(int N);
+hipError_t launch_skinny_gemm(const double *A, long lda, const double *B, long ldb, int transB, int M, int N, int K,
+                              double alpha, double beta, double *C, long ldc, int kchunk, double *Bt, double *part,
+                              hipStream_t s);
+}  // namespace geninv
+
 struct geninv_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -655,6 +663,20 @@ int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, dou
     GemmArgs a = gemm(A, lda, transA ? 1 : 0, B, ldb, transB ? 1 : 0, C, ldc, hdim(M), hdim(N), hdim(K), alpha,
                       beta);
     ProfScope ps(c, PC_GEMM, 2.0 * M * N * K);
+    // at most 16 output columns, A not transposed, long K: bound by reading A
+    // once (skinny.hip), split into up to 64 chunks of at least 128 of K
+    if (!transA && N <= 16 && K >= 1024) {
+        const long rowblocks = (M + 255) / 256;
+        const int S = (int)std::max<long>(1, std::min<long>({64L, (1024 + rowblocks - 1) / rowblocks, (long)K / 128}));
+        const int kchunk = (K + S - 1) / S;
+        const int Sx = (K + kchunk - 1) / kchunk;
+        const size_t pelems = (size_t)Sx * M * N;
+        CHK(ensure_ws(c, (pelems + (size_t)K * skinny_padded_width(N)) * sizeof(double)));
+        double *part = at<double>(c, 0);
+        HIPCHK(launch_skinny_gemm(A, lda, B, ldb, transB ? 1 : 0, M, N, K, alpha, beta, C, ldc, kchunk, part + pelems,
+                                  part, c->stream));
+        return GENINV_OK;
+    }
     // a skinny product (few output tiles, long K) is split over K: about 1024
     // workgroups (several fit on a compute unit; these launches are bound by
     // load latency), at least 256 of K each

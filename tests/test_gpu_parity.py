@@ -58,6 +58,9 @@ def _print_case(label, **kw):
     # transposition, an odd leading dimension (staged loads only), all-interior
     (2100, 2060, 333, 0, 0), (2100, 2060, 333, 1, 0), (2100, 2060, 333, 0, 1), (2100, 2060, 333, 1, 1),
     (2101, 2049, 257, 1, 0), (2048, 2048, 4096, 1, 0),
+    # skinny products (N <= 16, long K: row-per-thread kernel, K split in chunks)
+    (3001, 1, 5000, 0, 0), (2048, 8, 8192, 0, 0), (999, 5, 2000, 0, 1), (4097, 16, 1500, 0, 0),
+    (513, 3, 1024, 0, 1),
 ])
 def test_dgemm_parity(M, N, K, tA, tB):
     _print_case("dgemm", M=M, N=N, K=K, tA=tA, tB=tB)
