@@ -167,7 +167,12 @@ int geninv_dchain(geninv_ctx *ctx, int m, int n, int r, const double *L, int ldl
 
 /* C = alpha * op(A) op(B) + beta * C with the library's float64 MFMA GEMM
  * (the contraction every step above is built from).  op(X) = X or X'
- * (transX = 0 / 1); C is M x N (ldc >= M).  Exposed for parity testing. */
+ * (transX = 0 / 1); C is M x N (ldc >= M).  Products with few output tiles
+ * and a long K are split over K into the context's workspace (which may
+ * grow) and summed in a fixed order; with A not transposed, N <= 16 and
+ * K >= 1024 (right-hand sides such as W = Y F) a bandwidth-bound
+ * row-per-thread kernel is used instead of MFMA tiles.  Used by the
+ * benchmark for W and exposed for parity testing. */
 int geninv_dgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, double alpha,
                  const double *A, int lda, const double *B, int ldb, double beta, double *C,
                  int ldc);
