@@ -281,6 +281,18 @@ int geninv_batch_plan_run(geninv_batch_plan *plan, int use_graph);
 int geninv_batch_plan_autotune(geninv_batch_plan *plan, int reps, int *best_nl, int *best_grid,
                                double *best_ms);
 
+/* One-shot form of the batched solve, with the arguments of
+ * geninv_batch_plan_create: builds a plan with the default launch
+ * configuration, runs it once (no graph) and destroys it, which synchronizes
+ * the context stream.  status (HOST int, optional) receives the device
+ * status word as geninv_sync_status() returns it (0, or GENINV_ENONFINITE
+ * for non-finite data).  For repeated solves of one problem set keep a plan:
+ * it orders the problems and uploads their descriptors once. */
+int geninv_lstsq_batched(geninv_ctx *ctx, int batch, const int *m, const int *n, int k,
+                         const float *const *G, const int *ldg, const float *const *F,
+                         const int *ldf, double tol, double *const *W, const int *ldw, int *rank,
+                         int *status);
+
 /* Set or read the launch configuration directly (e.g. from a cached tuning). */
 int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid);
 int geninv_batch_plan_get_config(geninv_batch_plan *plan, int *nl, int *grid);

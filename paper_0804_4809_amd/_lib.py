@@ -70,6 +70,9 @@ _SIGS = [
                                                 ctypes.c_int, ctypes.POINTER(_VP), _c_int_p, ctypes.POINTER(_VP),
                                                 _c_int_p, ctypes.POINTER(_VP), _c_int_p, ctypes.c_double, _VP]),
     ("geninv_batch_plan_destroy", ctypes.c_int, [_VP]),
+    ("geninv_lstsq_batched", ctypes.c_int, [_VP, ctypes.c_int, _c_int_p, _c_int_p, ctypes.c_int,
+                                            ctypes.POINTER(_VP), _c_int_p, ctypes.POINTER(_VP), _c_int_p,
+                                            ctypes.c_double, ctypes.POINTER(_VP), _c_int_p, _VP, _c_int_p]),
     ("geninv_batch_plan_run", ctypes.c_int, [_VP, ctypes.c_int]),
     ("geninv_batch_plan_autotune", ctypes.c_int, [_VP, ctypes.c_int, _c_int_p, _c_int_p,
                                                   ctypes.POINTER(ctypes.c_double)]),

@@ -321,15 +321,13 @@ def sync_status(device=None):
     return load().geninv_sync_status(_ctx(dev))
 
 
-class BatchPlan:
-    """Batched least squares W_b = G_b^+ F_b (geninv_batch_plan_*).
+class _PackedBatch:
+    """G_b (m_b x n_b) and F_b (m_b x k), float32, packed column-major into
+    two device buffers, with W_b (n_b x k, float64) and the ranks as outputs,
+    and the C argument arrays (device pointers per problem, sizes) that the
+    batched entry points take."""
 
-    G_b (m_b x n_b) and F_b (m_b x k) are float32; they are packed
-    column-major into two device buffers owned by the plan (``load`` refills
-    them in place).  W_b (n_b x k, float64) and the ranks are outputs.
-    """
-
-    def __init__(self, Gs, Fs, tol: float | None = None, device=None):
+    def __init__(self, Gs, Fs, device=None):
         import numpy as np
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
         self.batch = len(Gs)
@@ -349,21 +347,13 @@ class BatchPlan:
         self.Wbuf = torch.zeros(int(self.w_off[-1]), dtype=torch.float64, device=self.device)
         self.rank = torch.zeros(max(1, self.batch), dtype=torch.int32, device=self.device)
         self.load(Gs, Fs)
-        lib = load()
         vp = ctypes.c_void_p
         gb, fb, wb = self.Gbuf.data_ptr(), self.Fbuf.data_ptr(), self.Wbuf.data_ptr()
-        Gp = (vp * self.batch)(*[gb + 4 * int(o) for o in self.g_off[:-1]])
-        Fp = (vp * self.batch)(*[fb + 4 * int(o) for o in self.f_off[:-1]])
-        Wp = (vp * self.batch)(*[wb + 8 * int(o) for o in self.w_off[:-1]])
+        self.Gp = (vp * self.batch)(*[gb + 4 * int(o) for o in self.g_off[:-1]])
+        self.Fp = (vp * self.batch)(*[fb + 4 * int(o) for o in self.f_off[:-1]])
+        self.Wp = (vp * self.batch)(*[wb + 8 * int(o) for o in self.w_off[:-1]])
         ci = ctypes.c_int * self.batch
-        m_c, n_c = ci(*self.m.tolist()), ci(*self.n.tolist())
-        h = vp()
-        self._lib = lib
-        self._ctx = _ctx(self.device)
-        _check(lib.geninv_batch_plan_create(self._ctx, ctypes.byref(h), self.batch, m_c, n_c, self.k, Gp, m_c, Fp,
-                                            m_c, Wp, n_c, float(tol or 0.0), _p(self.rank)),
-               "geninv_batch_plan_create")
-        self._plan = h
+        self.m_c, self.n_c = ci(*self.m.tolist()), ci(*self.n.tolist())
 
     def load(self, Gs, Fs):
         """Copy new G_b, F_b (same shapes) into the plan's packed buffers."""
@@ -372,6 +362,32 @@ class BatchPlan:
         f = np.concatenate([np.asarray(x, np.float32).ravel(order="F") for x in Fs]) if self.batch else np.zeros(0)
         self.Gbuf.copy_(torch.from_numpy(g.astype(np.float32)))
         self.Fbuf.copy_(torch.from_numpy(f.astype(np.float32)))
+
+    def W(self, b: int):
+        o = int(self.w_off[b])
+        n = int(self.n[b])
+        return self.Wbuf[o:o + n * self.k].view(self.k, n).t()
+
+
+class BatchPlan(_PackedBatch):
+    """Batched least squares W_b = G_b^+ F_b (geninv_batch_plan_*).
+
+    G_b (m_b x n_b) and F_b (m_b x k) are float32; they are packed
+    column-major into two device buffers owned by the plan (``load`` refills
+    them in place).  W_b (n_b x k, float64) and the ranks are outputs.
+    """
+
+    def __init__(self, Gs, Fs, tol: float | None = None, device=None):
+        super().__init__(Gs, Fs, device)
+        lib = load()
+        h = ctypes.c_void_p()
+        self._lib = lib
+        self._ctx = _ctx(self.device)
+        _check(lib.geninv_batch_plan_create(self._ctx, ctypes.byref(h), self.batch, self.m_c, self.n_c, self.k,
+                                            self.Gp, self.m_c, self.Fp, self.m_c, self.Wp, self.n_c,
+                                            float(tol or 0.0), _p(self.rank)),
+               "geninv_batch_plan_create")
+        self._plan = h
 
     def run(self, use_graph: bool = True):
         _ctx(self.device)   # follow torch's current stream
@@ -392,11 +408,6 @@ class BatchPlan:
                "geninv_batch_plan_get_config")
         return a.value, b.value
 
-    def W(self, b: int):
-        o = int(self.w_off[b])
-        n = int(self.n[b])
-        return self.Wbuf[o:o + n * self.k].view(self.k, n).t()
-
     def close(self):
         if getattr(self, "_plan", None):
             self._lib.geninv_batch_plan_destroy(self._plan)
@@ -407,3 +418,15 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def lstsq_batched(Gs, Fs, tol: float | None = None, device=None):
+    """One-shot batched least squares (geninv_lstsq_batched): W_b = G_b^+ F_b
+    for float32 G_b, F_b.  Synchronizes.  Returns (packed batch with ``W(b)``
+    and ``rank``, device status word)."""
+    pb = _PackedBatch(Gs, Fs, device)
+    st = ctypes.c_int(0)
+    _check(load().geninv_lstsq_batched(_ctx(pb.device), pb.batch, pb.m_c, pb.n_c, pb.k, pb.Gp, pb.m_c, pb.Fp,
+                                       pb.m_c, float(tol or 0.0), pb.Wp, pb.n_c, _p(pb.rank), ctypes.byref(st)),
+           "geninv_lstsq_batched")
+    return pb, st.value

@@ -1303,6 +1303,18 @@ int geninv_batch_plan_destroy(geninv_batch_plan *p) {
     return GENINV_OK;
 }
 
+int geninv_lstsq_batched(geninv_ctx *c, int batch, const int *m, const int *n, int k, const float *const *G,
+                         const int *ldg, const float *const *F, const int *ldf, double tol, double *const *W,
+                         const int *ldw, int *rank, int *status) {
+    geninv_batch_plan *p = nullptr;
+    CHK(geninv_batch_plan_create(c, &p, batch, m, n, k, G, ldg, F, ldf, W, ldw, tol, rank));
+    const int st = geninv_batch_plan_run(p, 0);
+    (void)geninv_batch_plan_destroy(p);   // synchronizes the context stream
+    if (st != GENINV_OK) return st;
+    if (status) *status = geninv_sync_status(c);
+    return GENINV_OK;
+}
+
 int geninv_batch_plan_config(geninv_batch_plan *p, int nl, int grid) {
     if (!p || nl < 0 || grid < 1 || grid > p->max_grid) return GENINV_EINVAL;
     if (batched_lds_bytes(nl, p->nmax, p->k) > 160 * 1024) return GENINV_EINVAL;

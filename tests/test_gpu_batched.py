@@ -69,6 +69,23 @@ def test_batched_edge_cases(use_graph):
     plan.close()
 
 
+def test_one_shot_batched_call_matches_a_plan():
+    """geninv_lstsq_batched (plan created, run once, destroyed) gives the
+    plan's results bit for bit (same default launch configuration) and the
+    oracle's ranks; its status word is 0 on finite data."""
+    print("[case] batched one-shot vs plan", flush=True)
+    Gs, Fs = _edge_problems()
+    pb, st = api.lstsq_batched(Gs, Fs)
+    assert st == 0
+    plan = api.BatchPlan(Gs, Fs)
+    plan.run(use_graph=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(pb.rank.cpu().numpy(), plan.rank.cpu().numpy())
+    assert torch.equal(pb.Wbuf, plan.Wbuf)
+    _check(pb, Gs, Fs)
+    plan.close()
+
+
 def test_batched_random_uneven_sizes_all_lds_thresholds():
     print("[case] batched 96 problems", flush=True)
     B = w.batch_lowrank(96, seed=11, m_hi=600, n_hi=200)
