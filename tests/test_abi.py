@@ -56,6 +56,8 @@ def test_null_context_is_einval(lib):
     assert lib.geninv_dgemm(None, 0, 0, 2, 2, 2, 1.0, None, 2, None, 2, 0.0, None, 2) == -1
     assert lib.geninv_set_stream(None, None) == -1
     assert lib.geninv_sync_status(None) == -1
+    assert lib.geninv_lstsq_batched(None, 0, None, None, 4, None, None, None, None, 0.0, None, None, None,
+                                    None) == -1
     assert lib.geninv_destroy(None) == 0
 
 
