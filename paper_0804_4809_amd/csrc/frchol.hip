@@ -92,35 +92,34 @@ hipError_t launch_tol(const double *A, long lda, int n, double user_tol, double 
 //
 // Every workgroup is one wavefront.  Each one factors the diagonal block
 // itself, so that no workgroup waits for another.  Workgroup 0 then writes
-// the block of L, the pivots and the new rank; every other workgroup solves
-// FR_TRS rows below the block against the accepted columns, four lanes per
-// row.
+// the block of L, the pivots and the new rank; every other workgroup also
+// solves FR_TRS rows below the block against the accepted columns, four
+// lanes per row, as it goes.
 //
 // The block is held in a 2-D cyclic layout: lane a + 8 b keeps
 // v[r][c] = A(8 r + a, 8 c + b) for r >= c (register blocks with r < c lie
 // wholly above the diagonal and are never touched).  For an accepted column
-// J the lanes with b = J mod 8 scale their entries of column J and publish
-// L(., J) (zero at rows <= J) as eight doubles per row residue a in LDS;
-// every lane then reads the eight values for its row residue and the eight
-// for its column residue and applies the rank-one update to its registers
-// on or past block J / 8.  A column costs two short LDS round trips and at
-// most 36 fused multiply-adds per lane, where a row-per-lane layout needs a
-// 63-way register broadcast.  Zeros at rows <= J keep finished columns and
-// column J itself unchanged, so no lane tests its own indices.
+// J the lanes with b = J mod 8 publish column J (zero at rows <= J) in LDS
+// before scaling, so that the round trip overlaps the reciprocal square
+// root; every lane then reads the eight values for its row residue and the
+// eight for its column residue, scales them, and applies the rank-one update
+// to its registers on or past block J / 8.  A column costs two short LDS
+// round trips and at most 36 fused multiply-adds per lane, where a
+// row-per-lane layout needs a 63-way register broadcast.  Zeros at rows <= J
+// keep finished columns and column J itself unchanged, so no lane tests its
+// own indices.
 //
-// The substitution runs over the accepted columns only, renumbered 0..a-1 in
-// the paper's column order: for row x of the panel restricted to the accepted
-// columns and T the a x a lower triangle of the block at the pivot rows,
-//   x_c <- x_c / T_cc,  then  x_c' -= x_c T_c'c  for c' > c,
-// which is the paper's column-by-column update of these rows.  Lane q of a
-// row holds columns c = 4t + q (t = 0..15); the new x_c is passed within the
-// four lanes by a DPP quad broadcast, and T is read from LDS, laid out so that
-// lane q reads its own 16 entries of a column contiguously.
+// The rows below the block follow the paper's column-by-column update in the
+// same loop: lane q of a row holds its entries at block columns 4t + q
+// (t = 0..15), and at accepted column J
+//   x_J <- x_J / L(J, J),  then  x_J' -= x_J L(J', J)  for J' > J.
+// The new x_J is passed within the four lanes by a DPP quad broadcast, and
+// L(J', J) comes from a second copy of column J in LDS laid out so that lane
+// q reads its sixteen entries contiguously (zero at rows <= J, so the entries
+// of finished columns are left alone).  Dropped columns leave the rows as
+// they are.  At the end x holds the row of L at the accepted columns.
 
 constexpr int FR_TRS = 16;             // rows per workgroup in the substitution
-constexpr int FR_TSEG = 18;            // T row: 4 segments of 18 doubles (16 used): 16-byte aligned, banks spread
-constexpr int FR_TLD = 4 * FR_TSEG;
-constexpr int FR_CH = 8;               // substitution columns per uniform chunk
 constexpr int FR_RB = FR_NB / 8;       // register blocks per dimension of the cyclic layout
 
 // lane (4 (lane / 4) + Q)'s value of v, within each group of four lanes
@@ -135,19 +134,19 @@ __device__ __forceinline__ double quad_bcast(double v) {
 // LDS the factorization shares within the wavefront
 struct FrShared {
     double colv[2][8][FR_RB];   // A(8 r + a, J) at [J & 1][a][r] before scaling, zero at rows <= J
+    double coll[2][4][16];      // the same column at [J & 1][i mod 4][i / 4], for the row solve
     double dvs[FR_NB];          // pivot value of every column at its test
-    double rdc[FR_NB];          // 1 / L(pivot row of c, c) per compact column c
     int ccomp[FR_NB];           // compact index of block column j, or -1 if dropped
     int pcol[FR_NB];            // block column of compact column c
 };
 
 struct FrBlock {
     double v[FR_RB][FR_RB];   // v[r][c] = A(8 r + a, 8 c + b), then L; r >= c only
+    double x[16];             // the lane's entries of its row below the block (block columns 4t + q)
     int acc;                  // accepted so far (uniform)
     double dv;                // pivot value of block column `lane`
     int cc;                   // compact index of block column `lane`, or -1
     int pc;                   // block column of compact column `lane`
-    double rd;                // 1 / L(pivot row, c) of compact column c = `lane`
 };
 
 // 1 / sqrt(d) for a positive normal d: the hardware estimate refined by two
@@ -169,26 +168,32 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Column J of the block: the paper's pivot test, then sqrt, scaling and the
-// rank-one update of the later columns (every register index static).  The
-// column is published before scaling, so that the LDS round trip overlaps
-// the reciprocal square root; every lane scales what it reads by the same
-// factor, so its L(i, J) equals the owner's bit for bit.
+// rank-one update of the later columns (every register index static), and,
+// with `rows`, the same column's step of the row solve.  Every lane scales
+// what it reads by the same factor, so its L(i, J) equals the owner's bit
+// for bit.
 template <int J>
-__device__ __forceinline__ void fr_column(FrBlock &s, FrShared &sh, int a, int b, int lane, int w, double tol) {
+__device__ __forceinline__ void fr_column(FrBlock &s, FrShared &sh, int a, int b, int q, int lane, int w, double tol,
+                                          bool rows) {
     if (J >= w) return;
-    constexpr int jr = J >> 3, jb = J & 7, r0 = jr & ~1;
+    constexpr int jr = J >> 3, jb = J & 7, r0 = jr & ~1, jt = J >> 2, jq = J & 3;
     const double d = lane_bcast(s.v[jr][jr], 9 * jb);   // current pivot of column J
     const bool keep = d > tol;                          // uniform
     s.dv = lane == J ? d : s.dv;
     s.cc = lane == J ? (keep ? s.acc : -1) : s.cc;
     if (!keep) return;
     double(*cv)[FR_RB] = sh.colv[J & 1];
+    double(*cl)[16] = sh.coll[J & 1];
     if (b == jb) {
 #pragma unroll
         for (int r = r0; r < FR_RB; r += 2) {
             const double e0 = (r >= jr && 8 * r + a > J) ? s.v[r][jr] : 0.0;
             const double e1 = 8 * (r + 1) + a > J ? s.v[r + 1][jr] : 0.0;
             *reinterpret_cast<double2 *>(&cv[a][r]) = double2{e0, e1};
+            if (rows) {
+                cl[(8 * r + a) & 3][(8 * r + a) >> 2] = e0;
+                cl[(8 * r + 8 + a) & 3][(8 * r + 8 + a) >> 2] = e1;
+            }
         }
     }
     wave_sync();
@@ -202,9 +207,17 @@ __device__ __forceinline__ void fr_column(FrBlock &s, FrShared &sh, int a, int b
         xl[r] = tl.x;
         xl[r + 1] = tl.y;
     }
+    double lc[16];
+    if (rows) {
+#pragma unroll
+        for (int t = jt & ~1; t < 16; t += 2) {
+            const double2 u = *reinterpret_cast<const double2 *>(&cl[q][t]);
+            lc[t] = u.x;
+            lc[t + 1] = u.y;
+        }
+    }
     const double y = rsqrt_refined(d);
     s.pc = lane == s.acc ? J : s.pc;
-    s.rd = lane == s.acc ? y : s.rd;
     if (b == jb) {
 #pragma unroll
         for (int r = jr; r < FR_RB; ++r) {
@@ -221,70 +234,50 @@ __device__ __forceinline__ void fr_column(FrBlock &s, FrShared &sh, int a, int b
     for (int c = jr; c < FR_RB; ++c)
 #pragma unroll
         for (int r = c; r < FR_RB; ++r) s.v[r][c] = __builtin_fma(-xi[r], xl[c], s.v[r][c]);
+    if (rows) {
+        // x_J / L(J, J) = x_J * y, from the lane holding column J of the row;
+        // the entries at rows <= J of the copy are zero, so the update leaves
+        // x_J and the finished entries alone
+        const double xj = quad_bcast<jq>(s.x[jt] * y);
+#pragma unroll
+        for (int t = jt; t < 16; ++t) s.x[t] = __builtin_fma(-xj, lc[t] * y, s.x[t]);
+        s.x[jt] = q == jq ? xj : s.x[jt];
+    }
     wave_sync();
     ++s.acc;
 }
 
 template <int... J>
 __device__ __forceinline__ void fr_factor(std::integer_sequence<int, J...>, FrBlock &s, FrShared &sh, int a, int b,
-                                          int lane, int w, double tol) {
-    (fr_column<J>(s, sh, a, b, lane, w, tol), ...);
+                                          int q, int lane, int w, double tol, bool rows) {
+    (fr_column<J>(s, sh, a, b, q, lane, w, tol, rows), ...);
 }
 
-// Compact column J of the substitution (branch-free; J >= a contributes 0).
-template <int J>
-__device__ __forceinline__ void trs_column(double (&x)[16], const double (&rd)[16], int q, int a, const double *tq) {
-    const double xj0 = quad_bcast<J & 3>(x[J >> 2] * rd[J >> 2]);
-    const double xj = J < a ? xj0 : 0.0;
-    const double upd = x[J >> 2] - xj * tq[J * FR_TLD + (J >> 2)];
-    x[J >> 2] = q == (J & 3) ? xj : upd;
-#pragma unroll
-    for (int t = (J >> 2) + 1; t < 16; ++t) x[t] -= xj * tq[J * FR_TLD + t];
-}
-
-template <int G, int... E>
-__device__ __forceinline__ void trs_chunk(std::integer_sequence<int, E...>, double (&x)[16], const double (&rd)[16],
-                                          int q, int a, const double *tq) {
-    if (G * FR_CH >= a) return;   // uniform
-    (trs_column<G * FR_CH + E>(x, rd, q, a, tq), ...);
-}
-
-template <int... G>
-__device__ __forceinline__ void trs_solve(std::integer_sequence<int, G...>, double (&x)[16], const double (&rd)[16],
-                                          int q, int a, const double *tq) {
-    (trs_chunk<G>(std::make_integer_sequence<int, FR_CH>{}, x, rd, q, a, tq), ...);
-}
-
-// P points at the updated panel: rows k0..n-1 of the panel's w columns
-// (leading dimension ldp), A minus the contribution of the columns accepted
-// before the panel.
+// P points at the panel: rows k0..n-1 of the panel's w columns (leading
+// dimension ldp), A minus the contribution of every column accepted before
+// the panel.
 __global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restrict__ P, long ldp,
                                                           double *__restrict__ L, long ldl, int *rank_buf, int p,
                                                           int k0, int w, int n, const double *tolp, int *piv,
                                                           double *dvals, double *__restrict__ Lp, long ldlp) {
-    __shared__ __align__(16) double T[FR_NB][FR_TLD];   // T[c][seg(c')] = L(pivot row of c', c), 0 unless c' > c
-    __shared__ double S[FR_TRS][FR_NB + 1];             // row staging for the renumbering of the columns
     __shared__ __align__(16) FrShared sh;
-    double *rdc = sh.rdc;
-    int *pcol = sh.pcol;
 
     const int lane = threadIdx.x;
     const int q = lane & 3;
     const int ra = lane & 7, cb = lane >> 3;   // row and column residue in the cyclic layout
     const int r0 = rank_buf[p];
     const double tol = *tolp;
+    const bool rows = blockIdx.x > 0;         // uniform: this workgroup solves rows below the block
     const int irel = w + (int)(blockIdx.x - 1) * FR_TRS + (lane >> 2);
-    const bool trs = blockIdx.x > 0 && k0 + irel < n;
+    const bool trs = rows && k0 + irel < n;
 
+    FrBlock s;
     // this lane's entries of its row below the block (block column order),
-    // in flight during the factorization
-    double x[16];
+    // in flight with the block's loads
 #pragma unroll
-    for (int t = 0; t < 16; ++t) x[t] = ld_or(P, irel + (long)(4 * t + q) * ldp, trs && 4 * t + q < w, 0.0);
-
+    for (int t = 0; t < 16; ++t) s.x[t] = ld_or(P, irel + (long)(4 * t + q) * ldp, trs && 4 * t + q < w, 0.0);
     // the lower triangle of the block in the cyclic layout (zero above the
     // diagonal and past w)
-    FrBlock s;
 #pragma unroll
     for (int r = 0; r < FR_RB; ++r)
 #pragma unroll
@@ -296,84 +289,41 @@ __global__ __launch_bounds__(64) void frchol_panel_kernel(const double *__restri
     s.dv = 0.0;
     s.cc = -1;
     s.pc = 0;
-    s.rd = 0.0;
-    if (blockIdx.x > 0) {
-        // zero T, so that the columns of the last chunk past a read zeros
-        double *tf = &T[0][0];
-#pragma unroll
-        for (int e = 0; e < FR_NB * FR_TLD / 64; ++e) tf[e * 64 + lane] = 0.0;
-    }
-    __syncthreads();
-    fr_factor(std::make_integer_sequence<int, FR_NB>{}, s, sh, ra, cb, lane, w, tol);
+    fr_factor(std::make_integer_sequence<int, FR_NB>{}, s, sh, ra, cb, q, lane, w, tol, rows);
     const int a = s.acc;
     sh.dvs[lane] = s.dv;
     sh.ccomp[lane] = s.cc;
     sh.pcol[lane] = s.pc;
-    sh.rdc[lane] = s.rd;
     __syncthreads();
 
-    // compact index of the rows and columns this lane holds
-    int ci[FR_RB], cj[FR_RB];
-#pragma unroll
-    for (int r = 0; r < FR_RB; ++r) {
-        ci[r] = sh.ccomp[8 * r + ra];
-        cj[r] = sh.ccomp[8 * r + cb];
-    }
-
-    if (blockIdx.x == 0) {
+    if (!rows) {
         // diagonal block of L, pivots, pivot values, running rank
 #pragma unroll
         for (int r = 0; r < FR_RB; ++r)
 #pragma unroll
             for (int c = 0; c <= r; ++c) {
                 const int i = 8 * r + ra, j = 8 * c + cb;
-                if (i < w && j <= i && cj[c] >= 0) L[(k0 + i) + (long)(r0 + cj[c]) * ldl] = s.v[r][c];
+                const int cj = sh.ccomp[j];
+                if (i < w && j <= i && cj >= 0) L[(k0 + i) + (long)(r0 + cj) * ldl] = s.v[r][c];
             }
         if (lane < w && dvals) dvals[k0 + lane] = sh.dvs[lane];
-        if (lane < a && piv) piv[r0 + lane] = k0 + pcol[lane];
+        if (lane < a && piv) piv[r0 + lane] = k0 + sh.pcol[lane];
         if (lane == 0) rank_buf[p + 1] = r0 + a;
         return;
     }
-
-    // compact triangle T from the registers: entries at two accepted columns
-    // i > j (so that ci > cj); the rest stays zero
-#pragma unroll
-    for (int r = 0; r < FR_RB; ++r)
-#pragma unroll
-        for (int c = 0; c <= r; ++c) {
-            const int i = 8 * r + ra, j = 8 * c + cb;
-            if (i < w && j < i && ci[r] >= 0 && cj[c] >= 0)
-                T[cj[c]][FR_TSEG * (ci[r] & 3) + (ci[r] >> 2)] = s.v[r][c];
-        }
-    // renumber the row's entries to compact column order through LDS
-    const int rl = lane >> 2;
-    if (trs) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t)
-            if (4 * t + q < w) S[rl][4 * t + q] = x[t];
-    }
-    __syncthreads();
     if (!trs) return;
-    double rd[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int c = 4 * t + q;
-        x[t] = c < a ? S[rl][pcol[c]] : 0.0;
-        rd[t] = c < a ? rdc[c] : 0.0;
-    }
-    trs_solve(std::make_integer_sequence<int, FR_NB / FR_CH>{}, x, rd, q, a, &T[0][FR_TSEG * q]);
+    // the row of L, compacted into L and uncompacted (zero where a column was
+    // dropped) into the panel buffer Lp
     double *lrow = L + (k0 + irel) + (long)r0 * ldl;
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-        if (4 * t + q < a) lrow[(long)(4 * t + q) * ldl] = x[t];
-    // the same row of the panel's new columns, uncompacted: block column j of
-    // L, or zero where column j was dropped
     double *prow = Lp + (k0 + irel);
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-        const int c = 4 * t + q;
-        if (c < a) prow[(long)pcol[c] * ldlp] = x[t];
-        if (c < w && sh.ccomp[c] < 0) prow[(long)c * ldlp] = 0.0;
+        const int j = 4 * t + q;
+        if (j < w) {
+            const int cj = sh.ccomp[j];
+            if (cj >= 0) lrow[(long)cj * ldl] = s.x[t];
+            prow[(long)j * ldlp] = cj >= 0 ? s.x[t] : 0.0;
+        }
     }
 }
 
