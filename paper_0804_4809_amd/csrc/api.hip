@@ -254,29 +254,6 @@ int gemm_splitk(geninv_ctx *c, const Layout &lay, GemmArgs g, int min_tiles = 25
     return GENINV_OK;
 }
 
-// Split count for a product of `tiles` 128 x 128 tiles and depth K that lets
-// the 128 x 128 kernel run: the cheapest S (by the cost model of
-// choose_splits: rounds of 256 workgroups times chunk-steps, plus the
-// reduction) among those with tiles * S >= 256 and at least 256 of K per
-// split; 0 when there is none.
-int fill_splits(long tiles, int K, int maxS) {
-    const double chunk_us = 4.5, reduce_us = 0.035;
-    const int smin = (int)std::max<long>(2, (255 + tiles) / tiles);
-    int best = 0;
-    double bestc = 1e300;
-    for (int S = smin; S <= maxS; ++S) {
-        const long kper = ((long)(K + S - 1) / S + 31) / 32 * 32;
-        if (kper < 256) break;
-        const long rounds = (tiles * S + 255) / 256;
-        const double cost = rounds * (kper / 32) * chunk_us + (S + 1) * tiles * reduce_us;
-        if (cost < bestc) {
-            bestc = cost;
-            best = S;
-        }
-    }
-    return best;
-}
-
 // C = op(A) op(B) for a product with host-known sizes after the
 // factorization.  When its 128 x 128 tiles alone would leave compute units
 // idle, K is split so that the 128 x 128 direct-to-LDS kernel runs full

@@ -89,6 +89,7 @@ enum { ST_OK = 0, ST_NONFINITE = -4, ST_NOTSPD = -5 };
 hipError_t launch_dgemm(const GemmArgs &a, hipStream_t s);
 long gemm_tiles(const GemmArgs &a, int bm);   // workgroups a launch would use with bm x bm tiles
 int choose_splits(long tiles, int K, int maxS); // split-K factor for `tiles` 128 x 128 tiles of depth K
+int fill_splits(long tiles, int K, int maxS);   // the same, restricted to launches of >= 256 workgroups (0: none)
 hipError_t launch_splitk_reduce(const double *part, long ldp, long strideP, int S, double *C, long ldc,
                                 Dim M, Dim N, double alpha, double beta, int uplo, hipStream_t s);
 hipError_t launch_fill(double *X, long ldx, int rows, int cols, double v, hipStream_t s);

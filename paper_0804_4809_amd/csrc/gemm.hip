@@ -592,23 +592,47 @@ static hipError_t launch_cfg(const GemmArgs &a, hipStream_t s) {
                     : launch_cfg_t<BM, BN, BK, WM, WN, false, false>(a, s);
 }
 
-// Split-K factor for an output of `tiles` 128 x 128 tiles (one workgroup per
-// compute unit at a time, so launches run in rounds of 256 tiles) and depth
-// K: the time is about rounds(S) x K / S chunk-steps plus the reduction of the
-// S partial results.  Every split keeps at least 256 of K (a whole flush
-// period of the two-level summation).  A small launch pays for its last,
-// partly idle round; splitting K fills it.
-int choose_splits(long tiles, int K, int maxS) {
+// Split-K cost model for an output of `tiles` 128 x 128 tiles (one
+// workgroup per compute unit at a time, so launches run in rounds of 256
+// tiles) and depth K: the time is about rounds(S) x K / S chunk-steps plus the
+// reduction of the S partial results, in microseconds.  Every split keeps at
+// least 256 of K (a whole flush period of the two-level summation); S splits
+// that leave less cost +infinity.
+static double split_cost(long tiles, int K, int S) {
     const double chunk_us = 4.5;      // one 128 x 128 x 32 chunk of one workgroup
     const double reduce_us = 0.035;   // reading and adding one partial 128 x 128 tile
+    const long kper = ((long)(K + S - 1) / S + 31) / 32 * 32;
+    if (S > 1 && kper < 256) return __builtin_huge_val();
+    const long rounds = (tiles * S + 255) / 256;
+    return rounds * (kper / 32) * chunk_us + (S > 1 ? (S + 1) * tiles * reduce_us : 0.0);
+}
+
+// The cheapest split count up to maxS.  A small launch pays for its last,
+// partly idle round; splitting K fills it.
+int choose_splits(long tiles, int K, int maxS) {
     int best = 1;
     double bestc = 1e300;
     for (int S = 1; S <= maxS; ++S) {
-        const long kper = ((long)(K + S - 1) / S + 31) / 32 * 32;
-        if (S > 1 && kper < 256) break;
-        const long rounds = (tiles * S + 255) / 256;
-        const double c = rounds * (kper / 32) * chunk_us + (S > 1 ? (S + 1) * tiles * reduce_us : 0.0);
+        const double c = split_cost(tiles, K, S);
+        if (c == __builtin_huge_val()) break;
         if (c < bestc * 0.98) {
+            bestc = c;
+            best = S;
+        }
+    }
+    return best;
+}
+
+// The cheapest split count among those that give the 128 x 128 kernel at
+// least 256 workgroups (tiles * S >= 256, S >= 2); 0 when there is none.
+int fill_splits(long tiles, int K, int maxS) {
+    const int smin = (int)std::max<long>(2, (255 + tiles) / tiles);
+    int best = 0;
+    double bestc = 1e300;
+    for (int S = smin; S <= maxS; ++S) {
+        const double c = split_cost(tiles, K, S);
+        if (c == __builtin_huge_val()) break;
+        if (c < bestc) {
             bestc = c;
             best = S;
         }
