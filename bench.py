@@ -599,8 +599,6 @@ def main():
         unit_flops = 2.0 * n * n * m
     elif dom == "gram":
         unit_flops = m * n * (n + 1.0)
-    elif dom == "panel_gemm":
-        unit_flops = sum(2.0 * (n - kk) * rk for kk, rk in enumerate(r_before)) / max(1, dcnt.value / args.steps)
     else:
         unit_flops = dfl.value / max(1, dcnt.value)
     achieved = unit_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0

@@ -14,11 +14,11 @@ using namespace geninv;
 
 // Kernel classes for the optional event timers (geninv_prof_*).
 enum ProfClass {
-    PC_GRAM, PC_TOL, PC_FILL, PC_PANEL_GEMM, PC_PANEL_FACTOR, PC_LTL, PC_INV_PANEL, PC_INV_UPDATE,
+    PC_GRAM, PC_TOL, PC_FILL, PC_TRAILING, PC_PANEL_FACTOR, PC_LTL, PC_INV_PANEL, PC_INV_UPDATE,
     PC_MIRROR, PC_CHAIN_K, PC_CHAIN_P, PC_CHAIN_Y, PC_LSTSQ, PC_GEMM, PC_SLICE, PC_NS, PC_BATCHED, PC_COUNT
 };
 static const char *const kProfNames[PC_COUNT] = {
-    "gram", "tol", "fill", "panel_gemm", "panel_factor", "ltl", "inv_panel", "inv_update",
+    "gram", "tol", "fill", "trailing_update", "panel_factor", "ltl", "inv_panel", "inv_update",
     "mirror", "chain_k", "chain_p", "chain_y", "lstsq_apply", "gemm", "slice", "newton_schulz", "batched"};
 
 struct ProfState {
@@ -344,7 +344,7 @@ int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, do
         const int k1 = k0 + w;
         const int rows = nn - k1;
         if (rows > 0) {
-            ProfScope ps(c, PC_PANEL_GEMM, 2.0 * rows * (rows + 1.0) / 2.0 * w);
+            ProfScope ps(c, PC_TRAILING, 2.0 * rows * (rows + 1.0) / 2.0 * w);
             HIPCHK(launch_dgemm(gemm(Lp + k1, nn, 0, Lp + k1, nn, 1, A + k1 + (long)k1 * lda, lda, hdim(rows),
                                      hdim(rows), hdim(w), -1.0, 1.0, GEMM_LOWER),
                                 c->stream));
