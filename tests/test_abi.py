@@ -85,3 +85,14 @@ def test_python_api_refuses_cpu_tensors():
         api.geninv(torch.zeros((4, 3), dtype=torch.float64))
     with pytest.raises(ValueError, match="GPU"):
         api.lstsq(torch.zeros((4, 3), dtype=torch.float64), torch.zeros((4, 1), dtype=torch.float64))
+
+
+def test_batched_python_api_checks_shapes_before_touching_a_device():
+    pytest.importorskip("torch")
+    import numpy as np
+    from paper_0804_4809_amd import api
+    G = np.zeros((6, 3), np.float32)
+    with pytest.raises(ValueError, match="differ in length"):
+        api.lstsq_batched([G, G], [np.zeros((6, 2), np.float32)])
+    with pytest.raises(ValueError, match="same number of columns"):
+        api.lstsq_batched([G, G], [np.zeros((6, 2), np.float32), np.zeros((6, 3), np.float32)])
