@@ -7,10 +7,10 @@ exact duplicates of earlier ones, F 8192 x 8): Gram matrix, tolerance,
 full-rank Cholesky with column dropping, (L'L)^-1, Y = L M M L' G', and the
 least-squares weights W = Y F.  Inputs are resident in HBM before timing.
 
-Prints one JSON line.  `value` is algorithmic TFLOP/s of the step (flop model
-in the design doc); `roofline` covers the kernel class that takes the most time,
-timed with HIP events on the library's stream during the timed steps;
-`cpu_baseline` is the float64 CPU oracle on the same input.
+Prints one JSON line.  `value` is algorithmic TFLOP/s of the step (the flop
+model of `algorithmic_flops` below); `roofline` covers the kernel class that
+takes the most time, timed with HIP events on the library's stream during the
+timed steps; `cpu_baseline` is the float64 CPU oracle on the same input.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -511,7 +511,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "copies": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

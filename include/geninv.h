@@ -53,7 +53,7 @@ typedef enum {
     GENINV_EHIP = -3,        /* a HIP runtime call failed */
     GENINV_ENONFINITE = -4,  /* G (or its Gram matrix) holds Inf/NaN; r is set to 0 */
     GENINV_ENOTSPD = -5,     /* L'L lost positive definiteness in the inverse */
-    GENINV_ENOTSUP = -6      /* valid request that this build does not support */
+    GENINV_ENOTSUP = -6      /* valid request that the library does not support */
 } geninv_status;
 
 /* ---- context ------------------------------------------------------------ */

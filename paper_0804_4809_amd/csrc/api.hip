@@ -550,7 +550,7 @@ const char *geninv_strerror(int s) {
         case GENINV_EHIP: return "HIP runtime error";
         case GENINV_ENONFINITE: return "input holds Inf or NaN (or its Gram matrix overflows)";
         case GENINV_ENOTSPD: return "L'L is not positive definite in floating point";
-        case GENINV_ENOTSUP: return "not supported by this build";
+        case GENINV_ENOTSUP: return "not supported by the library";
         default: return "unknown status";
     }
 }
