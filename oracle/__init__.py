@@ -6,11 +6,11 @@ baseline leg of the benchmark use it.  It shares no code with the GPU path.
 
 * ``geninv_ref`` -- float64 NumPy implementation of the paper's algorithm,
   step by step (Gram, tolerance, full-rank Cholesky, (L'L)^-1, product chain)
-  plus least squares and the Penrose error measures.
+  plus least squares, the Penrose error measures, the rounding-sensitivity
+  and decision-band checkers, and the Newton-Schulz refinement step.
 * ``exact``      -- exact rational pseudoinverse of tiny integer matrices by
   an independent formula, used to pin ``geninv_ref``.
 * ``ozaki_ref``  -- float64/integer reference of the fixed-point column
-  slicing and sliced products used by the mixed-precision form, and of the
-  Newton-Schulz refinement step.
+  slicing and sliced products used by the mixed-precision form.
 """
 from . import geninv_ref, exact  # noqa: F401

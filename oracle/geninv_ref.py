@@ -280,6 +280,28 @@ def ambiguity_band(A: np.ndarray, tol: float, keep: np.ndarray | None = None, *,
     return (safety * spread + 2.0 * (n + 1) * u * np.abs(np.diag(A))) / tol
 
 
+def newton_schulz_step(X: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """One Newton-Schulz step for the pseudoinverse, X <- X (2I - G X), in
+    float64 with two plain matrix products (the refinement the mixed form
+    applies; the iteration of Ben-Israel and Cohen for G^+).  X is n x m for
+    an m x n G.  If I - G X restricted to the range of G has spectral radius
+    below one and X starts in the row/column spaces of G', the iterates
+    converge quadratically to G^+: the residual I - G X is squared by each
+    step."""
+    X = np.asarray(X, np.float64)
+    G = np.asarray(G, np.float64)
+    return 2.0 * X - (X @ G) @ X
+
+
+def newton_schulz_factored_step(P: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """The same step written on P with X = P G' and A = G'G:
+    P <- 2P - P A P, since X (2I - G X) = (2P - P G'G P) G'.  P and A are
+    n x n and symmetric."""
+    P = np.asarray(P, np.float64)
+    A = np.asarray(A, np.float64)
+    return 2.0 * P - (P @ A) @ P
+
+
 def rel_fro(X: np.ndarray, Ref: np.ndarray) -> float:
     """||X - Ref||_F / ||Ref||_F (0 when both are zero)."""
     num = float(np.linalg.norm(np.asarray(X, np.float64) - Ref))
