@@ -12,5 +12,7 @@ baseline leg of the benchmark use it.  It shares no code with the GPU path.
   an independent formula, used to pin ``geninv_ref``.
 * ``ozaki_ref``  -- float64/integer reference of the fixed-point column
   slicing and sliced products used by the mixed-precision form.
+* ``crt_ref``    -- reference of the int8 engine's products: the exact
+  product of fixed-point integer representations, rounded once.
 """
 from . import geninv_ref, exact  # noqa: F401
