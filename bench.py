@@ -1,18 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the full-rank-Cholesky Moore-Penrose inverse on one MI355X.
 
-One step = the whole float64 method on the RBF design workload (8192 inputs
-uniform in [0,1]^4, 2048 Gaussian centers with sigma 0.3 of which 256 are
-exact duplicates of earlier ones, F 8192 x 8): Gram matrix, tolerance,
-full-rank Cholesky with column dropping, (L'L)^-1, Y = L M M L' G', and the
-least-squares weights W = Y F.  Inputs are resident in HBM before timing.
+One step = the whole float64 method on the large RBF design workload
+(131072 inputs uniform in [0,1]^8, 8192 Gaussian centers with sigma 0.5 of
+which 1192 are exact duplicates of earlier ones, F 131072 x 16): Gram
+matrix, tolerance, full-rank Cholesky with column dropping, (L'L)^-1,
+Y = L M M L' G', and the least-squares weights W = Y F.  Inputs are resident
+in HBM before timing.  ``--workload c2`` times the 8192 x 2048 RBF design
+(sigma 0.3, 256 duplicates, F 8192 x 8) instead.
 
 Prints one JSON line.  `value` is algorithmic TFLOP/s of the step (the flop
 model of `algorithmic_flops` below); `roofline` covers the kernel class that
 takes the most time, timed with HIP events on the library's stream during the
-timed steps; `cpu_baseline` is the float64 CPU oracle on the same input.
+timed steps; `cpu_baseline` is the float64 CPU oracle timed on a row sample
+of the same design.  `forms` adds the mixed-precision form beside the
+float64 one on the same input, the smaller RBF design with its accuracy
+against the oracle, the mixed form on G = P diag(s) Q', the batched form,
+the paper's Table 1 sweep, incremental least squares and the two inverses
+of L'L.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--skip-forms] [--workload c5|c2]
 """
 from __future__ import annotations
 
@@ -63,12 +71,13 @@ def lstsq_flops(m: int, n: int, r: int, k: int) -> float:
     return f
 
 
-def _counter_traffic(kernel_class: str):
+def _counter_traffic(kernel_class: str, tag: str):
     """HBM bytes per launch of `kernel_class` (FETCH_SIZE + WRITE_SIZE, scaled
-    by a plain copy) from the committed counter summary, or None when the
-    summary has no such line or the kernel sources changed since it was taken."""
+    by a plain copy) from the committed counter summary of workload `tag`, or
+    None when the summary has no such line or the kernel sources changed
+    since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "fp64_rbf_8192x2048_hbm_bytes.md")
+    path = os.path.join(ROOT, "profiles", f"fp64_{tag}_hbm_bytes.md")
     try:
         lines = open(path).read().splitlines()
     except OSError:
@@ -96,6 +105,29 @@ def _timed(fn, steps, sync):
     return (time.perf_counter() - t0) * 1e3 / steps
 
 
+# mixed-form variants: (key, precision, gram digits, chain digits, Newton-Schulz steps)
+# precision 1 = bfloat16 slices (digits = 8-bit slices), 2 = int8 residues
+# (digits = moduli; 16 give float64-accurate products)
+MIXED_C3 = [
+    ("int8_m16", 2, 16, 16, 0),
+    ("int8_m13", 2, 13, 13, 0),
+    ("int8_m16_ns1", 2, 16, 16, 1),
+    ("bf16_s4", 1, 4, 4, 0),
+    ("bf16_s4_ns1", 1, 4, 4, 1),
+]
+MIXED_C5 = [
+    ("int8_m16", 2, 16, 16, 0),
+    ("int8_m16_ns1", 2, 16, 16, 1),
+    ("bf16_s4", 1, 4, 4, 0),
+]
+
+
+def _mixed_call(lib, ctx, m, n, G, ldg, Y, variant, rank=None, est=None):
+    _, prec, gd, cd, ns = variant
+    return lib.geninv_mixed(ctx, m, n, ctypes.c_void_p(G.data_ptr()), ldg, 0.0, prec, gd, cd, ns, 0.0,
+                            ctypes.c_void_p(Y.data_ptr()), n, rank, None, est)
+
+
 def bench_mixed(lib, api, workloads, torch, np, steps, keep_host):
     """Mixed-precision form vs the float64 form on G = P diag(s) Q'
     (32768 x 4096, rank 3072, s log-spaced in [1e-3, 1]).  Returns the
@@ -118,12 +150,6 @@ def bench_mixed(lib, api, workloads, torch, np, steps, keep_host):
         st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, vp(Y64.data_ptr()), n, None, None)
         assert st == 0, st
 
-    def runmx(cs, ns):
-        def f():
-            st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n, None,
-                                  None)
-            assert st == 0, st
-        return f
 
     r_c = ctypes.c_int(0)
     lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, vp(Y64.data_ptr()), n, ctypes.byref(r_c),
@@ -139,15 +165,19 @@ def bench_mixed(lib, api, workloads, torch, np, steps, keep_host):
     out["fp64"] = {"ms": round(t64, 3), "tflops": round(flops / t64 / 1e9, 3), "rank": r}
     if host is not None:
         host["Y"]["fp64"] = Y64.cpu().numpy()
-    for cs, ns, key in [(4, 0, "mixed_s4_chain4"), (0, 0, "mixed_s4_chain_fp64"), (4, 1, "mixed_s4_chain4_ns1")]:
-        f = runmx(cs, ns)
+    for variant in MIXED_C3:
+        key = variant[0]
+
+        def f():
+            st = _mixed_call(lib, ctx, m, n, Gc, ldg, Ymx, variant)
+            assert st == 0, st
         r2 = ctypes.c_int(0)
-        st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), ldg, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n,
-                              ctypes.byref(r2), None)
+        est = ctypes.c_double(0.0)
+        st = _mixed_call(lib, ctx, m, n, Gc, ldg, Ymx, variant, ctypes.byref(r2), ctypes.byref(est))
         assert st == 0, st
         t = _timed(f, steps, sync)
         out[key] = {"ms": round(t, 3), "tflops_fp64_equivalent": round(flops / t / 1e9, 3), "rank": r2.value,
-                    "speedup_vs_fp64": round(t64 / t, 3),
+                    "speedup_vs_fp64": round(t64 / t, 3), "err_est": est.value,
                     "relF_vs_fp64_gpu": float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64))}
         if host is not None:
             host["Y"][key] = Ymx.cpu().numpy()
@@ -156,83 +186,29 @@ def bench_mixed(lib, api, workloads, torch, np, steps, keep_host):
     return out, host
 
 
-def bench_large_rbf(lib, api, workloads, torch, np, steps):
-    """Mixed vs float64 on the large RBF design (131072 inputs in [0,1]^8,
-    8192 centers with sigma 0.5, 1192 of them exact duplicates, F 131072 x 16).
-    The float64 CPU oracle is out of reach at this size (minutes); the mixed
-    result is compared with the float64 GPU form, which is parity-tested
-    against the oracle at the sizes the oracle finishes."""
-    c0 = time.perf_counter()
-    G, F, _ = workloads.c5_problem()
-    gen_s = time.perf_counter() - c0
-    m, n = G.shape
-    dev = torch.device("cuda", 0)
-    Gc = torch.from_numpy(G).to(dev).t().contiguous().t()
-    Fd = torch.from_numpy(F).to(dev)
-    del G, F
-    ctx = api._ctx(dev)
-    vp = ctypes.c_void_p
-    Y64 = api.empty_colmajor(n, m, dev)
-    Ymx = api.empty_colmajor(n, m, dev)
-    sync = torch.cuda.synchronize
-    out = {"workload": "RBF design: m=131072 inputs uniform in [0,1]^8, n=8192 centers (7000 uniform + 1192 exact "
-                       "duplicates), sigma=0.5, F 131072x16", "generate_s": round(gen_s, 1)}
-
-    def run64():
-        st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, vp(Y64.data_ptr()), n, None, None)
-        assert st == 0, st
-
-    r64 = ctypes.c_int(0)
-    st = lib.geninv_dgeninv(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, vp(Y64.data_ptr()), n, ctypes.byref(r64), None)
-    assert st == 0, st
-    t64 = _timed(run64, steps, sync)
-    W64 = Y64 @ Fd
-    fn = torch.linalg.norm(Fd)
-    # least-squares residual |G W - F| / |F|: a backward-stable figure of
-    # merit on this ill-conditioned design (cond(L'L) ~ 4e13), where no two
-    # float64 evaluations of Y agree closely
-    out["fp64"] = {"ms": round(t64, 2), "rank": r64.value,
-                   "ls_residual": float(torch.linalg.norm(Gc @ W64 - Fd) / fn)}
-    for cs, ns, key in [(4, 0, "mixed_s4_chain4"), (4, 1, "mixed_s4_chain4_ns1")]:
-        def f():
-            st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n, None, None)
-            assert st == 0, st
-        rm = ctypes.c_int(0)
-        st = lib.geninv_mixed(ctx, m, n, vp(Gc.data_ptr()), m, 0.0, 4, cs, ns, vp(Ymx.data_ptr()), n,
-                              ctypes.byref(rm), None)
-        assert st == 0, st
-        t = _timed(f, steps, sync)
-        Wmx = Ymx @ Fd
-        out[key] = {"ms": round(t, 2), "rank": rm.value, "speedup_vs_fp64": round(t64 / t, 3),
-                    "relF_Y_vs_fp64_gpu": float(torch.linalg.norm(Ymx - Y64) / torch.linalg.norm(Y64)),
-                    "relF_W_vs_fp64_gpu": float(torch.linalg.norm(Wmx - W64) / torch.linalg.norm(W64)),
-                    "ls_residual": float(torch.linalg.norm(Gc @ Wmx - Fd) / fn)}
-        del Wmx
-    del Gc, Fd, Y64, Ymx, W64
-    torch.cuda.empty_cache()
-    return out
-
-
 def _incremental_run(api, torch, Gd, Fd, first, batch, steps):
     m, n = Gd.shape
     k = Fd.shape[1]
     sync = torch.cuda.synchronize
-    # warm both paths (workspace growth) at the full size
-    inc = api.IncrementalLstsq(n, k)
-    inc.append(Gd, Fd)
-    inc.solve()
+    # warm every path (workspace growth) at the full size
+    for refactor in (False, True):
+        inc = api.IncrementalLstsq(n, k, refactor=refactor)
+        inc.append(Gd, Fd)
+        inc.solve()
     api.lstsq(Gd, Fd)
-    inc = api.IncrementalLstsq(n, k)
+    incs = {False: api.IncrementalLstsq(n, k), True: api.IncrementalLstsq(n, k, refactor=True)}
     rows = []
     n_t = 0
     for n_new in [first] + list(range(first + batch, n + 1, batch)):
         Gv = Gd[:, :n_new]
-        sync()
-        t0 = time.perf_counter()
-        inc.append(Gv, Fd)
-        W_inc, r_inc = inc.solve()
-        sync()
-        t_inc = (time.perf_counter() - t0) * 1e3
+        res = {}
+        for refactor, inc in incs.items():
+            sync()
+            t0 = time.perf_counter()
+            inc.append(Gv, Fd)
+            Wi, ri = inc.solve()
+            sync()
+            res[refactor] = ((time.perf_counter() - t0) * 1e3, Wi, ri)
         one = []
         for _ in range(max(1, steps)):
             sync()
@@ -240,19 +216,24 @@ def _incremental_run(api, torch, Gd, Fd, first, batch, steps):
             W_one, r_one = api.lstsq(Gv, Fd)
             sync()
             one.append((time.perf_counter() - t0) * 1e3)
-        rows.append({"columns": n_new, "appended": n_new - n_t, "incremental_ms": round(t_inc, 3),
-                     "one_shot_ms": round(sorted(one)[len(one) // 2], 3), "rank_incremental": r_inc,
-                     "rank_one_shot": r_one,
-                     "relF_W_vs_one_shot": float(torch.linalg.norm(W_inc - W_one) / torch.linalg.norm(W_one))})
+        t_one = sorted(one)[len(one) // 2]
+        t_inc, W_inc, r_inc = res[False]
+        t_ref, W_ref, r_ref = res[True]
+        rows.append({"columns": n_new, "appended": n_new - n_t, "incremental_factor_ms": round(t_inc, 3),
+                     "refactor_from_gram_ms": round(t_ref, 3), "one_shot_ms": round(t_one, 3),
+                     "speedup_vs_one_shot": round(t_one / t_inc, 2),
+                     "rank_incremental": r_inc, "rank_refactor": r_ref, "rank_one_shot": r_one,
+                     "relF_W_incremental_vs_one_shot": float(torch.linalg.norm(W_inc - W_one) / torch.linalg.norm(W_one)),
+                     "relF_W_refactor_vs_one_shot": float(torch.linalg.norm(W_ref - W_one) / torch.linalg.norm(W_one))})
         n_t = n_new
     return rows
 
 
 def bench_incremental(lib, api, workloads, torch, np, steps):
-    """Incremental least squares (appended Gram and G'F rows, then the method
-    from the Gram matrix) against geninv_dlstsq on the whole matrix so far,
-    on the RBF design and on a tall low-rank matrix where the Gram matrix
-    dominates the cost.  Times include each solve's rank read-back."""
+    """Incremental least squares (appended Gram and G'F rows; the factor and
+    (L'L)^-1 extended, or the method rerun from the Gram matrix) against
+    geninv_dlstsq on the whole matrix so far, on the RBF design and on a tall
+    low-rank matrix.  Times include each call's host synchronizations."""
     dev = torch.device("cuda", 0)
     out = {}
     G, F, _ = workloads.c2_problem()
@@ -385,8 +366,17 @@ def bench_batched(api, workloads, torch, np, steps, keep_host):
                                    vp(Ws[b].data_ptr()), n_b, None)
             assert st == 0, st
 
+    # the float64 form reads each problem's rank back to the host once per
+    # call by default (geninv_set_host_sync); timed both with that
+    # synchronization and without it (later launches sized for n_b)
     run64()
-    t64 = _timed(run64, 2, torch.cuda.synchronize)
+    t64_sync = _timed(run64, 2, torch.cuda.synchronize)
+    api.set_host_sync(False, dev)
+    try:
+        run64()
+        t64 = _timed(run64, 2, torch.cuda.synchronize)
+    finally:
+        api.set_host_sync(True, dev)
     rel = np.array([float(torch.linalg.norm(plan.W(b) - Ws[b]) / torch.linalg.norm(Ws[b]))
                     for b in range(len(B.G))])
     # ranks of the float64 form (one synchronous call per problem, untimed)
@@ -400,8 +390,12 @@ def bench_batched(api, workloads, torch, np, steps, keep_host):
         r64[b] = rc.value
     same = r64 == ranks
     out["fp64_form"] = {"ms": round(t64, 3), "solves_per_s": round(len(B.G) / (t64 * 1e-3), 1),
-                        "note": "geninv_dlstsq once per problem, float64 inputs, no host sync between calls"}
+                        "ms_with_rank_readback": round(t64_sync, 3),
+                        "note": "geninv_dlstsq once per problem on the library's stream, float64 inputs; 'ms' "
+                                "with geninv_set_host_sync(0) (no host synchronization inside or between "
+                                "calls), 'ms_with_rank_readback' with the default one rank read-back per call"}
     out["speedup_vs_fp64_form"] = round(t64 / t, 2)
+    out["speedup_vs_fp64_form_with_rank_readback"] = round(t64_sync / t, 2)
     out["rank_equals_fp64_form"] = int(same.sum())
     out["relF_vs_fp64_form_same_rank"] = {"median": float(np.median(rel[same])), "max": float(rel[same].max()),
                                           "above_1e-6": int((rel[same] > 1e-6).sum())}
@@ -417,33 +411,235 @@ def bench_batched(api, workloads, torch, np, steps, keep_host):
     return out, host
 
 
-def cpu_oracle_leg(workloads, np, G, F, flops, mixed_host, batched_host, forms):
-    """Everything that runs the CPU oracle: its timing on the headline
-    workload (cpu_baseline) and the reference results that the other forms'
-    accuracy figures are stated against."""
+WORKLOADS = {
+    "c5": ("rbf_131072x8192",
+           "float64 geninv + W = G^+ F on a Gaussian RBF design matrix: m=131072 inputs uniform in [0,1]^8, "
+           "n=8192 centers (7000 uniform + 1192 exact duplicates), sigma=0.5, F 131072x16"),
+    "c2": ("rbf_8192x2048",
+           "float64 geninv + W = G^+ F on a Gaussian RBF design matrix: m=8192 inputs uniform in [0,1]^4, "
+           "n=2048 centers (1792 uniform + 256 exact duplicates), sigma=0.3, F 8192x8"),
+}
+
+
+def _generate(workloads, key):
+    if key == "c5":
+        G, F, _ = workloads.c5_problem()
+    else:
+        G, F, _ = workloads.c2_problem()
+    return G, F
+
+
+def _upload_colmajor(torch, X, dev):
+    """Host row-major array -> device column-major tensor (copy through a
+    transposed device view, no second host copy)."""
+    T = torch.from_numpy(X).to(dev)
+    C = T.t().contiguous().t()
+    del T
+    return C
+
+
+def _gpu_quality(torch, Gd, Y, Fd, W):
+    """Backward-stable figures of merit of a pseudoinverse on the GPU:
+    ||G Y G - G||_F / ||G||_F and the least-squares residual ||G W - F|| / ||F||
+    (products in torch, outside any timed region)."""
+    YG = Y @ Gd
+    gyg = float(torch.linalg.norm(Gd @ YG - Gd) / torch.linalg.norm(Gd))
+    del YG
+    ls = float(torch.linalg.norm(Gd @ W - Fd) / torch.linalg.norm(Fd))
+    return {"gyg_minus_g_relF": gyg, "ls_residual": ls}
+
+
+class Fp64Step:
+    """The timed step: geninv_dgeninv (Y, rank, pivots) then W = Y F with the
+    library's GEMM, on device-resident inputs."""
+
+    def __init__(self, lib, api, torch, np, G, F, dev):
+        self.lib, self.torch, self.np = lib, torch, np
+        self.m, self.n = G.shape
+        self.k = F.shape[1]
+        self.Gd = _upload_colmajor(torch, G, dev)
+        self.Fd = _upload_colmajor(torch, F, dev)
+        self.Y = api.empty_colmajor(self.n, self.m, dev)
+        self.W = api.empty_colmajor(self.n, self.k, dev)
+        self.piv = torch.empty(self.n, dtype=torch.int32, device=dev)
+        self.ctx = api._ctx(dev)
+
+    def __call__(self, rank=None):
+        vp = ctypes.c_void_p
+        st = self.lib.geninv_dgeninv(self.ctx, self.m, self.n, vp(self.Gd.data_ptr()), self.m, 0.0,
+                                     vp(self.Y.data_ptr()), self.n, rank, vp(self.piv.data_ptr()))
+        if st != 0:
+            raise RuntimeError(f"geninv_dgeninv failed: {st}")
+        st = self.lib.geninv_dgemm(self.ctx, 0, 0, self.n, self.k, self.m, 1.0, vp(self.Y.data_ptr()), self.n,
+                                   vp(self.Fd.data_ptr()), self.m, 0.0, vp(self.W.data_ptr()), self.n)
+        if st != 0:
+            raise RuntimeError(f"geninv_dgemm failed: {st}")
+
+    def rank_and_flops(self):
+        r_c = ctypes.c_int(0)
+        self(ctypes.byref(r_c))
+        r = r_c.value
+        pv = self.piv[:r].cpu().numpy()
+        acc = self.np.zeros(self.n, bool)
+        acc[pv] = True
+        r_before = self.np.concatenate([[0], self.np.cumsum(acc)[:-1]])
+        return r, pv, algorithmic_flops(self.m, self.n, r_before, r, self.k)
+
+    def free(self):
+        del self.Gd, self.Fd, self.Y, self.W, self.piv
+
+
+def measure_fp64(lib, step, steps, warmup, torch, tag):
+    """Warm-up, rank and flops, one step with every kernel class timed (the
+    dominant class), then `steps` timed steps with event timers on that class
+    only.  Returns (report, roofline, per-class ms of one step)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    r, pv, flops = step.rank_and_flops()
+    ctx = step.ctx
+    ncls = lib.geninv_prof_classes()
+    names = [lib.geninv_prof_name(c).decode() for c in range(ncls)]
+    lib.geninv_prof_enable(ctx, (1 << ncls) - 1)
+    step()
+    torch.cuda.synchronize()
+    per_class = {}
+    for c in range(ncls):
+        t = ctypes.c_double(0.0)
+        cnt = ctypes.c_long(0)
+        fl = ctypes.c_double(0.0)
+        lib.geninv_prof_read(ctx, c, ctypes.byref(t), ctypes.byref(cnt), ctypes.byref(fl))
+        per_class[names[c]] = (t.value, cnt.value, fl.value)
+    dom = max(per_class, key=lambda name: per_class[name][0])
+    dom_idx = names.index(dom)
+    lib.geninv_prof_enable(ctx, 1 << dom_idx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    dt = ctypes.c_double(0.0)
+    dcnt = ctypes.c_long(0)
+    dfl = ctypes.c_double(0.0)
+    lib.geninv_prof_read(ctx, dom_idx, ctypes.byref(dt), ctypes.byref(dcnt), ctypes.byref(dfl))
+    lib.geninv_prof_enable(ctx, 0)
+    avg_ms = dt.value / max(1, dcnt.value)
+    m, n = step.m, step.n
+    # algorithmic work per launch of the dominant class
+    if dom == "chain_y":
+        unit_flops = 2.0 * n * n * m
+    elif dom == "gram":
+        unit_flops = m * n * (n + 1.0)
+    else:
+        unit_flops = dfl.value / max(1, dcnt.value)
+    achieved = unit_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    roofline = {
+        "kernel": dom,
+        "bound": "mfma",
+        "achieved": round(achieved, 3),
+        "peak": FP64_MFMA_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
+        "traffic": _counter_traffic(dom, tag),
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_flops_per_launch": unit_flops,
+        "avg_launch_ms": round(avg_ms, 4),
+        "launches_per_step": dcnt.value / steps,
+    }
+    rep = {"ms_per_step": round(ms_per_step, 4), "tflops": round(flops / (ms_per_step * 1e-3) / 1e12, 4),
+           "rank": r, "flops_per_step": flops}
+    breakdown = {name: round(v[0], 4) for name, v in per_class.items() if v[1] > 0}
+    return rep, roofline, breakdown, pv
+
+
+def bench_mixed_same_input(lib, api, torch, step, steps, variants):
+    """The mixed-precision form beside the float64 one on the headline's
+    device-resident G: time, rank, and the backward-stable figures of each
+    (the float64 form's Y and W are the step's last outputs)."""
+    m, n, k = step.m, step.n, step.k
+    vp = ctypes.c_void_p
+    dev = step.Gd.device
+    sync = torch.cuda.synchronize
+    t64 = None
+    out = {"fp64": dict(_gpu_quality(torch, step.Gd, step.Y, step.Fd, step.W))}
+    Ymx = api.empty_colmajor(n, m, dev)
+    for variant in variants:
+        key = variant[0]
+
+        def f(rank=None, est=None):
+            st = _mixed_call(lib, step.ctx, m, n, step.Gd, m, Ymx, variant, rank, est)
+            if st != 0:
+                raise RuntimeError(f"geninv_mixed failed: {st}")
+        rm = ctypes.c_int(0)
+        est = ctypes.c_double(0.0)
+        f(ctypes.byref(rm), ctypes.byref(est))
+        t = _timed(f, steps, sync)
+        Wmx = Ymx @ step.Fd
+        rep = {"ms": round(t, 3), "rank": rm.value, "speedup_vs_fp64": None, "err_est": est.value,
+               "relF_Y_vs_fp64_gpu": float(torch.linalg.norm(Ymx - step.Y) / torch.linalg.norm(step.Y)),
+               "relF_W_vs_fp64_gpu": float(torch.linalg.norm(Wmx - step.W) / torch.linalg.norm(step.W))}
+        rep.update(_gpu_quality(torch, step.Gd, Ymx, step.Fd, Wmx))
+        out[key] = rep
+        del Wmx
+    del Ymx
+    return out
+
+
+def cpu_oracle_leg(workloads, np, headline_key, flops_fn, c2_host, mixed_host, batched_host, forms):
+    """Everything that runs the CPU oracle: its timing on a row sample of the
+    headline workload (cpu_baseline), and the reference results that the
+    other forms' accuracy figures are stated against."""
     from oracle import geninv_ref as o
     try:
         from threadpoolctl import threadpool_info
         threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
     except Exception:  # pragma: no cover
         threads = int(os.environ.get("OPENBLAS_NUM_THREADS", "1"))
+    G, F = _generate(workloads, headline_key)
+    m, n = G.shape
+    rows = min(m, 16384)
+    Gs = np.ascontiguousarray(G[:rows])
+    Fs = np.ascontiguousarray(F[:rows])
+    del G, F
     times = []
     budget = 25.0
     while not times or (sum(times) + times[-1] < budget and len(times) < 3):
         c0 = time.perf_counter()
-        res = o.geninv(G)
-        _ = res.Y @ F
+        W, res = o.lstsq(Gs, Fs)
         times.append(time.perf_counter() - c0)
     med = sorted(times)[len(times) // 2]
+    acc = np.zeros(res.d.size, bool)
+    acc[res.piv] = True
+    r_before = np.concatenate([[0], np.cumsum(acc)[:-1]])
+    flops = flops_fn(rows, n, r_before, res.rank, Fs.shape[1])
     cpu = {"value": round(flops / med / 1e12, 5), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
            "sample": f"whole float64 oracle (Gram, tol, column-by-column full-rank Cholesky, (L'L)^-1, "
-                     f"chain, W = Y F) on the full workload, median of {len(times)} run(s), "
-                     f"{med:.2f} s each; rank {res.rank}",
+                     f"chain, W = Y F) on the first {rows} of the {m} rows of the same design (all {n} "
+                     f"columns), median of {len(times)} run(s), {med:.2f} s each; rank {res.rank}; "
+                     f"TFLOP/s by the same flop model as value",
            "seconds": round(med, 3)}
+    del Gs, Fs, W, res
 
     def relf(a, b):
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
+    if c2_host is not None:
+        co = forms["fp64_rbf_8192x2048"]
+        Gc, Fc = c2_host["G"], c2_host["F"]
+        ref = o.geninv(Gc)
+        acc = co["accuracy"]
+        acc["oracle_rank"] = ref.rank
+        acc["relF_Y_vs_oracle"] = relf(c2_host["Y"], ref.Y)
+        acc["oracle_self_spread"] = o.self_spread(Gc, base=ref)
+        Wref = ref.Y @ Fc
+        acc["relF_W_vs_oracle"] = relf(c2_host["W"], Wref)
+        acc["oracle_gyg_minus_g_relF"] = relf(Gc @ (ref.Y @ Gc), Gc)
+        acc["oracle_ls_residual"] = float(np.linalg.norm(Gc @ Wref - Fc) / np.linalg.norm(Fc))
+        acc["oracle_penrose_max_abs"] = max(o.penrose_errors(Gc, ref.Y).values())
+        acc["penrose_max_abs"] = max(o.penrose_errors(Gc, c2_host["Y"]).values())
+        same = np.array_equal(np.sort(ref.piv), np.sort(c2_host["piv"]))
+        acc["pivots_equal_oracle"] = bool(same)
     if mixed_host is not None:
         mo = forms["mixed_vs_fp64"]
         Gm = mixed_host["G"]
@@ -457,11 +653,12 @@ def cpu_oracle_leg(workloads, np, G, F, flops, mixed_host, batched_host, forms):
         # from arithmetic error
         from oracle import ozaki_ref as z
         Ssl, esl = z.slice_columns(Gm, 4)
-        Gs = z.reconstruct(Ssl, esl)
+        Gsl = z.reconstruct(Ssl, esl)
         del Ssl
-        ref_s = o.geninv(Gs).Y
-        del Gs
+        ref_s = o.geninv(Gsl).Y
+        del Gsl
         mo["oracle_on_sliced_G_relF_vs_oracle"] = relf(ref_s, ref.Y)
+        mo["oracle_relF_vs_closed_form"] = relf(ref.Y, Ytrue)
         for key, Y in mixed_host["Y"].items():
             mo[key]["relF_vs_oracle"] = relf(Y, ref.Y)
             mo[key]["relF_vs_closed_form"] = relf(Y, Ytrue)
@@ -487,16 +684,35 @@ def cpu_oracle_leg(workloads, np, G, F, flops, mixed_host, batched_host, forms):
     return cpu
 
 
+def bench_c2_form(lib, api, workloads, torch, np, steps, keep_host):
+    """The float64 form on the 8192 x 2048 RBF design: time, rank, and the
+    figures its accuracy is stated with (host copies for the oracle leg)."""
+    G, F = _generate(workloads, "c2")
+    dev = torch.device("cuda", 0)
+    step = Fp64Step(lib, api, torch, np, G, F, dev)
+    rep, roof, breakdown, pv = measure_fp64(lib, step, steps, 2, torch, WORKLOADS["c2"][0])
+    rep["workload"] = WORKLOADS["c2"][1]
+    rep["dominant_kernel"] = {k: roof[k] for k in ("kernel", "achieved", "frac", "avg_launch_ms")}
+    rep["kernel_ms_one_step"] = breakdown
+    rep["accuracy"] = _gpu_quality(torch, step.Gd, step.Y, step.Fd, step.W)
+    host = None
+    if keep_host:
+        host = {"G": G, "F": F, "Y": step.Y.cpu().numpy(), "W": step.W.cpu().numpy(), "piv": pv}
+    step.free()
+    torch.cuda.empty_cache()
+    return rep, host
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c5",
+                    help="headline workload: c5 (131072 x 8192 RBF design, default) or c2 (8192 x 2048)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--skip-forms", action="store_true", help="only the float64 RBF workload")
+    ap.add_argument("--skip-forms", action="store_true", help="only the headline float64 workload")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle checks of the other forms")
-    ap.add_argument("--large-rbf", action="store_true",
-                    help="also run mixed vs float64 on the 131072 x 8192 RBF design (about a minute more)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for hardware byte counters) and exit")
     args = ap.parse_args()
@@ -524,138 +740,83 @@ def main():
     lib = load()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    tag, desc = WORKLOADS[args.workload]
 
-    G, F, _ = workloads.c2_problem()
-    m, n = G.shape
-    k = F.shape[1]
-    Gd, ldg = api.colmajor(torch.from_numpy(G).to(dev))
-    Fd, ldf = api.colmajor(torch.from_numpy(F).to(dev))
-    Y = api.empty_colmajor(n, m, dev)
-    W = api.empty_colmajor(n, k, dev)
-    piv = torch.empty(n, dtype=torch.int32, device=dev)
-    ctx = api._ctx(dev)
-    vp = ctypes.c_void_p
-
-    def step():
-        st = lib.geninv_dgeninv(ctx, m, n, vp(Gd.data_ptr()), ldg, 0.0, vp(Y.data_ptr()), n, None,
-                                vp(piv.data_ptr()))
-        if st != 0:
-            raise RuntimeError(f"geninv_dgeninv failed: {st}")
-        st = lib.geninv_dgemm(ctx, 0, 0, n, k, m, 1.0, vp(Y.data_ptr()), n, vp(Fd.data_ptr()), ldf, 0.0,
-                              vp(W.data_ptr()), n)
-        if st != 0:
-            raise RuntimeError(f"geninv_dgemm failed: {st}")
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    # rank and pivots of this input (same call, synchronous form)
-    r_c = ctypes.c_int(0)
-    st = lib.geninv_dgeninv(ctx, m, n, vp(Gd.data_ptr()), ldg, 0.0, vp(Y.data_ptr()), n, ctypes.byref(r_c),
-                            vp(piv.data_ptr()))
-    if st != 0:
-        raise RuntimeError(f"geninv_dgeninv failed: {st}")
-    r = r_c.value
-    pv = piv[:r].cpu().numpy()
-    acc = np.zeros(n, bool)
-    acc[pv] = True
-    r_before = np.concatenate([[0], np.cumsum(acc)[:-1]])
-    flops = algorithmic_flops(m, n, r_before, r, k)
-
-    # one profiled step with every kernel class timed: find the dominant class
-    ncls = lib.geninv_prof_classes()
-    lib.geninv_prof_enable(ctx, (1 << ncls) - 1)
-    step()
-    torch.cuda.synchronize()
-    per_class = {}
-    for c in range(ncls):
-        t = ctypes.c_double(0.0)
-        cnt = ctypes.c_long(0)
-        fl = ctypes.c_double(0.0)
-        lib.geninv_prof_read(ctx, c, ctypes.byref(t), ctypes.byref(cnt), ctypes.byref(fl))
-        per_class[lib.geninv_prof_name(c).decode()] = (t.value, cnt.value, fl.value)
-    dom = max(per_class, key=lambda name: per_class[name][0])
-    dom_idx = [lib.geninv_prof_name(c).decode() for c in range(ncls)].index(dom)
-
-    # timed steps: only the dominant class carries event timers (two events per launch)
-    lib.geninv_prof_enable(ctx, 1 << dom_idx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    dt = ctypes.c_double(0.0)
-    dcnt = ctypes.c_long(0)
-    dfl = ctypes.c_double(0.0)
-    lib.geninv_prof_read(ctx, dom_idx, ctypes.byref(dt), ctypes.byref(dcnt), ctypes.byref(dfl))
-    lib.geninv_prof_enable(ctx, 0)
-    avg_ms = dt.value / max(1, dcnt.value)
-
-    # algorithmic work per launch of the dominant class
-    if dom == "chain_y":
-        unit_flops = 2.0 * n * n * m
-    elif dom == "gram":
-        unit_flops = m * n * (n + 1.0)
-    else:
-        unit_flops = dfl.value / max(1, dcnt.value)
-    achieved = unit_flops / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-    roofline = {
-        "kernel": dom,
-        "bound": "mfma",
-        "achieved": round(achieved, 3),
-        "peak": FP64_MFMA_PEAK_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4),
-        "traffic": _counter_traffic(dom),
-        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "avg_launch_ms": round(avg_ms, 4),
-        "launches_per_step": dcnt.value / args.steps,
-    }
-    breakdown = {name: round(v[0], 4) for name, v in per_class.items() if v[1] > 0}
+    c0 = time.perf_counter()
+    G, F = _generate(workloads, args.workload)
+    gen_s = time.perf_counter() - c0
+    step = Fp64Step(lib, api, torch, np, G, F, dev)
+    m, n, k = step.m, step.n, step.k
+    del G, F
+    print(f"[bench] {tag} generated in {gen_s:.1f} s, uploaded", file=sys.stderr, flush=True)
+    rep, roofline, breakdown, _ = measure_fp64(lib, step, args.steps, args.warmup, torch, tag)
+    print(f"[bench] {tag} float64: {rep['ms_per_step']} ms/step", file=sys.stderr, flush=True)
 
     oracle_on = not args.no_cpu_baseline and not args.no_oracle
     forms = {}
-    mixed_host = batched_host = None
+    mixed_host = batched_host = c2_host = None
     if not args.skip_forms:
+        fsteps = max(2, min(args.steps, 3)) if args.workload == "c5" else max(2, min(args.steps, 5))
+        mo = bench_mixed_same_input(lib, api, torch, step, fsteps, MIXED_C5 if args.workload == "c5" else MIXED_C3)
+        mo["fp64"]["ms"] = rep["ms_per_step"]
+        for key, v in mo.items():
+            if isinstance(v, dict) and v.get("speedup_vs_fp64", 0) is None:
+                v["speedup_vs_fp64"] = round(rep["ms_per_step"] / v["ms"], 3)
+        forms["mixed_vs_fp64_same_input"] = mo
+        forms["mixed_vs_fp64_same_input"]["workload"] = desc.replace("float64 geninv + W = G^+ F on ", "")
+    headline_quality = _gpu_quality(torch, step.Gd, step.Y, step.Fd, step.W)
+    step.free()
+    del step
+    torch.cuda.empty_cache()
+    if not args.skip_forms:
+        print("[bench] forms", file=sys.stderr, flush=True)
+        def note(what):
+            print(f"[bench] form {what}", file=sys.stderr, flush=True)
+
+        if args.workload != "c2":
+            note("fp64_rbf_8192x2048")
+            forms["fp64_rbf_8192x2048"], c2_host = bench_c2_form(lib, api, workloads, torch, np, 20, oracle_on)
         fsteps = max(2, min(args.steps, 5))
+        note("mixed_vs_fp64")
         forms["mixed_vs_fp64"], mixed_host = bench_mixed(lib, api, workloads, torch, np, fsteps, oracle_on)
+        note("batched")
         forms["batched"], batched_host = bench_batched(api, workloads, torch, np, max(3, min(args.steps, 10)),
                                                        oracle_on)
+        note("table1_sweep")
         forms["table1_sweep"] = bench_table1(lib, api, workloads, torch, np, 5)
+        note("incremental_lstsq")
         forms["incremental_lstsq"] = bench_incremental(lib, api, workloads, torch, np, 3)
+        note("spd_inverse")
         forms["spd_inverse_gj_vs_newton_schulz"] = bench_spd_inverse(lib, api, workloads, torch, np, 3)
-    if args.large_rbf:
-        forms["large_rbf_mixed_vs_fp64"] = bench_large_rbf(lib, api, workloads, torch, np, 2)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_oracle_leg(workloads, np, G, F, flops, mixed_host if oracle_on else None,
-                             batched_host if oracle_on else None, forms)
-    del mixed_host, batched_host
+        print("[bench] oracle leg", file=sys.stderr, flush=True)
+        cpu = cpu_oracle_leg(workloads, np, args.workload, algorithmic_flops, c2_host if oracle_on else None,
+                             mixed_host if oracle_on else None, batched_host if oracle_on else None, forms)
+    del mixed_host, batched_host, c2_host
 
     out = {
         "metric": METRIC,
-        "value": round(flops / (ms_per_step * 1e-3) / 1e12, 4),
+        "value": rep["tflops"],
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": rep["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "float64 geninv + W = G^+ F on a Gaussian RBF design matrix: m=8192 inputs uniform "
-                        "in [0,1]^4, n=2048 centers (1792 uniform + 256 exact duplicates), sigma=0.3, F 8192x8",
-            "m": m, "n": n, "k": k, "rank": r, "flops_per_step": flops,
+            "workload": desc,
+            "m": m, "n": n, "k": k, "rank": rep["rank"], "flops_per_step": rep["flops_per_step"],
+            "generate_s": round(gen_s, 1),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "accuracy": headline_quality,
         "kernel_ms_one_step": breakdown,
         "forms": forms,
     }

@@ -53,8 +53,16 @@ typedef enum {
     GENINV_EHIP = -3,        /* a HIP runtime call failed */
     GENINV_ENONFINITE = -4,  /* G (or its Gram matrix) holds Inf/NaN; r is set to 0 */
     GENINV_ENOTSPD = -5,     /* L'L lost positive definiteness in the inverse */
-    GENINV_ENOTSUP = -6      /* valid request that the library does not support */
+    GENINV_ENOTSUP = -6,     /* valid request that the library does not support */
+    GENINV_EACCURACY = -7    /* mixed form: outputs written, but the error estimate exceeds the target */
 } geninv_status;
+
+/* Arithmetic of a whole-method call (geninv_mixed, geninv_workspace_bytes). */
+typedef enum {
+    GENINV_FP64 = 0,         /* every product in float64 (geninv_dgeninv, geninv_dlstsq) */
+    GENINV_MIXED_BF16 = 1,   /* Gram and chain products from 8-bit slices on the bfloat16 matrix cores */
+    GENINV_MIXED_INT8 = 2    /* Gram and chain products from int8 residues modulo coprime moduli */
+} geninv_precision;
 
 /* ---- context ------------------------------------------------------------ */
 
@@ -91,10 +99,13 @@ const char *geninv_strerror(int status);
 /* Library version as 10000*major + 100*minor + patch. */
 int geninv_version(void);
 
-/* Device workspace (bytes) the float64 calls need for an m x n problem with
- * k right-hand sides (k = 0 for geninv).  Calls grow the workspace to this
- * size on first use. */
-size_t geninv_workspace_bytes(int m, int n, int k);
+/* Device workspace (bytes) a call needs for an m x n problem: with
+ * precision GENINV_FP64, geninv_dgeninv (k = 0) or geninv_dlstsq with k
+ * right-hand sides (the digit and step arguments are ignored); with
+ * GENINV_MIXED_BF16 or GENINV_MIXED_INT8, geninv_mixed with those
+ * gram_digits, chain_digits and ns_steps (k ignored).  0 for invalid
+ * arguments.  Calls grow the context's workspace to this size on first use. */
+size_t geninv_workspace_bytes(int m, int n, int k, int precision, int gram_digits, int chain_digits, int ns_steps);
 
 /* ---- whole method, float64 --------------------------------------------- */
 
@@ -114,8 +125,9 @@ int geninv_dgeninv(geninv_ctx *ctx, int m, int n, const double *G, int ldg, doub
 
 /* W = G^+ F, the minimum-norm least-squares solution of min ||G W - F|| (Section 1).
  *   F m x k (ldf >= m), W n x k (ldw >= n); rank as in geninv_dgeninv.
- * Evaluated as W = L (M (M (L' (G' F)))) without forming Y; requires m >= n
- * (EINVAL otherwise; use geninv_dgeninv for wide G). */
+ * Evaluated as W = L (M (M (L' (G' F)))) without forming Y; when m < n the
+ * Appendix's transpose branch factors G G' and evaluates
+ * W = G' (L (M (M (L' F)))).  k <= 4096 (ENOTSUP above). */
 int geninv_dlstsq(geninv_ctx *ctx, int m, int n, int k, const double *G, int ldg,
                   const double *F, int ldf, double tol, double *W, int ldw, int *rank);
 
@@ -201,30 +213,101 @@ int geninv_inc_gram(geninv_ctx *ctx, int m, int n_old, int p, int k, const doubl
 int geninv_dlstsq_gram(geninv_ctx *ctx, int n, int k, const double *A, int lda, const double *B, int ldb,
                        double tol, double *W, int ldw, int *rank);
 
+/* Incremental full-rank Cholesky (Section 4: basis functions added to a
+ * network, rank deficiency allowed).  A is the Gram matrix of the n_old + p
+ * columns seen so far (lower triangle and the new rows, as geninv_inc_gram
+ * leaves it; lda >= n_old + p).  L (ldl >= n_old + p), piv and dvals
+ * (int / double [n_old + p]) and M (ldm >= n_old + p) hold the factor of the
+ * first n_old columns from the previous call: L's kept columns, their pivot
+ * rows, every column's updated pivot value and M = (L'L)^-1 (r x r).
+ * *rank_io (HOST) is that factor's rank r on entry and the new rank on
+ * return; *tol_io (HOST) the threshold it used (written, not read, when
+ * n_old = 0).  tol <= 0 selects the paper's default for all n_old + p
+ * columns.
+ * The earlier columns' factor does not change when columns are appended (the
+ * Appendix loop is left to right), so the call computes only: the new rows
+ * of L from the triangular system L_P X = B_P with the earlier pivot rows
+ * L_P = L(piv, :) and B_P(c, i) = A(n_old + i, piv[c]) (blocked, MFMA
+ * products); the full-rank Cholesky of the new columns' Schur complement
+ * A_new - X'X with the same strict test; and M by a block update
+ * (Woodbury for L_old'L_old + X X', then the Schur complement of the new
+ * kept columns), O(r^2 p) instead of O(r^3).  When the default threshold
+ * falls (a new column with a smaller diagonal) so far that an earlier
+ * decision would change, the call refactors all n_old + p columns instead.
+ * n_old = 0 factors from scratch.  Synchronizes (reads the new rank). */
+int geninv_inc_factor(geninv_ctx *ctx, int n_old, int p, const double *A, int lda, double tol, double *L, int ldl,
+                      int *piv, double *dvals, double *M, int ldm, int *rank_io, double *tol_io);
+
+/* W = L (M (M (L' B))) (n x k, ldw >= n) for a factor L (n x r, ldl >= n)
+ * and M = (L'L)^-1 (r x r, ldm >= r), e.g. from geninv_inc_factor, and
+ * B = G'F (n x k, ldb >= n): the method's least-squares weights from the
+ * factors (Theorem 1 with Section 1's W = G^+ F). */
+int geninv_factored_lstsq(geninv_ctx *ctx, int n, int r, int k, const double *L, int ldl, const double *M, int ldm,
+                          const double *B, int ldb, double *W, int ldw);
+
 /* ---- mixed precision: error-free split products on bfloat16 matrix cores - */
 
-/* Y = G^+ (Theorem 1) with the two dense products on the bfloat16 matrix
- * cores as sums of exact products of 8-bit operand slices (the error-free
- * splitting of Ozaki, Ogita, Oishi and Rump): every column of G (every row of
- * P and G in the chain) is scaled by a power of two and cut into `slices`
- * signed 8-bit integer slices; slice pairs are multiplied exactly (float32
- * sums of each weight class, exact integers, moved into float64 totals).
- * The Gram matrix takes every pair, so it is the exactly rounded Gram matrix
- * of the 8*slices-bit representation of G (a truncated pair set would not be
- * the Gram matrix of any matrix, and a rank-deficient G would turn its
- * first-order error in the null space into a large error in G^+).  The chain
- * product takes the pairs t + u <= s of weight >= 2^(-8 (s+2)) (13 of 16 at
- * s = 4); the pairs left out weigh less than the s-slice truncation itself.
- * The tolerance, the pivot decisions, the Cholesky factor and (L'L)^-1 are
- * float64, as in geninv_dgeninv.
- *   slices        1..4, slices of G in the Gram matrix (4: 32-bit representation)
- *   chain_slices  0..4, slices of P and G in Y = P G'; 0 evaluates it in float64
- *   ns_steps      >= 0 Newton-Schulz steps X <- X (2I - G X), taken in the
- *                 factored form P <- 2P - P A P (X = P G') in float64 with the
- *                 sliced Gram matrix A
- * Other arguments as in geninv_dgeninv.  Requires m >= n (ENOTSUP otherwise). */
-int geninv_mixed(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double tol, int slices,
-                 int chain_slices, int ns_steps, double *Y, int ldy, int *rank, int *piv);
+/* Y = G^+ (Theorem 1) with the two dense products (the Gram matrix and
+ * Y = P G', P = L M M L') on reduced-precision matrix cores, everything the
+ * method decides in float64: the tolerance, the pivot decisions, the
+ * Cholesky factor, (L'L)^-1, K = L M and P = K K'.  When m < n the Appendix's
+ * transpose branch factors G G' and forms Y = G' P.
+ *   precision  GENINV_MIXED_BF16: every column of G (every row of P and of G
+ *              in the chain) is scaled by a power of two and cut into 8-bit
+ *              integer slices (the error-free splitting of Ozaki, Ogita,
+ *              Oishi and Rump); slice pairs are exact bfloat16 products with
+ *              exact float32 class sums moved into float64 totals.  The Gram
+ *              matrix takes every pair (the exactly rounded Gram matrix of
+ *              the 8*digits-bit representation of G: a truncated pair set
+ *              would not be the Gram matrix of any matrix); the chain the
+ *              pairs t + u <= digits.  digits 1..4.
+ *              GENINV_MIXED_INT8: every row/column is scaled by a power of
+ *              two and rounded to an integer of beta bits; the integer
+ *              product is formed exactly from int8 matrix products modulo
+ *              `digits` pairwise coprime moduli <= 255 (Ozaki, Uchino and
+ *              Imamura's modular scheme) and the Chinese remainder theorem,
+ *              then rounded once to float64.  beta is the largest bit count
+ *              (<= 52) the moduli allow for the product's depth K
+ *              (K 2^(2 beta) < prod p / 2): 16 moduli give beta = 52 up to
+ *              K = 2^17, i.e. float64 accuracy.  digits 1..16 (EINVAL when
+ *              too few moduli leave no bits for this K).
+ *   gram_digits   slices or moduli of the Gram matrix
+ *   chain_digits  slices or moduli of Y = P G'; 0 evaluates it in float64
+ *   ns_steps   0..16 Newton-Schulz steps X <- X (2I - G X), in the factored
+ *              form P <- 2P - P A P (X = P G') with the engine's Gram matrix
+ *              A and float64 products; a step is taken only while its
+ *              correction ||P A P - P||_F / ||P||_F falls (each step reads
+ *              one number back to the host).
+ *   target     > 0: return GENINV_EACCURACY (outputs still written) when the
+ *              error estimate exceeds it; <= 0: no check
+ *   err_est    HOST double* or NULL.  When non-NULL or target > 0 the call
+ *              estimates the relative error of the result with 16 random
+ *              sign probes and float64 products that use the caller's G
+ *              (one host synchronization): ||P A P w - P w|| / ||P w|| with
+ *              A = G'G applied through G (it sees the engine's
+ *              representation error of the Gram matrix and the
+ *              factorization's rounding), plus ||Y v - P G' v|| / ||P G' v||
+ *              (the chain product's own error).  The estimate is of the
+ *              error against the exact pseudoinverse of G restricted to the
+ *              accepted columns; on inputs where float64 itself is
+ *              ill-conditioned (cond(L'L) u not small) it reports that
+ *              floor too.
+ * Other arguments as in geninv_dgeninv. */
+int geninv_mixed(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double tol, int precision,
+                 int gram_digits, int chain_digits, int ns_steps, double target, double *Y, int ldy, int *rank,
+                 int *piv, double *err_est);
+
+/* C = op(A) op(B) (M x N, ldc >= M) on the int8 engine with `moduli`
+ * moduli, exactly as geninv_mixed forms its products with
+ * GENINV_MIXED_INT8: op(A) = A' when transA (A is K x M), A otherwise
+ * (M x K); op(B) likewise.  lower != 0 (M == N) writes only the lower
+ * triangle, diagonal included.  The product of the integer representations
+ * is exact; the result is that product rounded to float64 (error about
+ * 2 u |C| beyond the representation error).  For parity testing and as a
+ * float64-accurate product at moduli = 16.  EINVAL when the moduli leave no
+ * bits for this K. */
+int geninv_mgemm(geninv_ctx *ctx, int transA, int transB, int M, int N, int K, const double *A, int lda,
+                 const double *B, int ldb, int moduli, int lower, double *C, int ldc);
 
 /* The slicing step on its own, for parity testing.  transposed == 0: column
  * exponents e[cols] and planes[t][i + j*ldp] = slice t of X(i, j) (ldp >= rows,
@@ -292,6 +375,13 @@ int geninv_lstsq_batched(geninv_ctx *ctx, int batch, const int *m, const int *n,
                          const float *const *G, const int *ldg, const float *const *F,
                          const int *ldf, double tol, double *const *W, const int *ldw, int *rank,
                          int *status);
+
+/* Optional per-problem pivot output: piv is a HOST array of `batch` DEVICE
+ * pointers (int[n_b] each, or NULL entries), or NULL to switch the output
+ * off.  Each run then writes the 0-based indices of the r_b columns problem
+ * b kept, increasing (as geninv_dgeninv's piv).  Synchronizes the stream;
+ * a graph captured earlier keeps reading the descriptors, so it follows. */
+int geninv_batch_plan_set_pivots(geninv_batch_plan *plan, int *const *piv);
 
 /* Set or read the launch configuration directly (e.g. from a cached tuning). */
 int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid);

@@ -20,7 +20,11 @@ _lib = None
 _lock = threading.Lock()
 
 GENINV_OK = 0
-STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENOTSPD", -6: "ENOTSUP"}
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENOTSPD", -6: "ENOTSUP",
+                -7: "EACCURACY"}
+GENINV_EACCURACY = -7
+# geninv_precision
+GENINV_FP64, GENINV_MIXED_BF16, GENINV_MIXED_INT8 = 0, 1, 2
 
 
 class GeninvError(RuntimeError):
@@ -40,7 +44,8 @@ _SIGS = [
     ("geninv_sync_status", ctypes.c_int, [_VP]),
     ("geninv_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("geninv_version", ctypes.c_int, []),
-    ("geninv_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    ("geninv_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("geninv_dgeninv", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double,
                                       _VP, ctypes.c_int, _c_int_p, _VP]),
     ("geninv_dlstsq", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
@@ -55,7 +60,11 @@ _SIGS = [
     ("geninv_dchain", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
                                      ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
     ("geninv_mixed", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _c_int_p, _VP]),
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _VP,
+                                    ctypes.c_int, _c_int_p, _VP, ctypes.POINTER(ctypes.c_double)]),
+    ("geninv_mgemm", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    _VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
+                                    ctypes.c_int]),
     ("geninv_bslice", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, _VP, ctypes.c_int, _VP]),
     ("geninv_bgram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_int, _VP,
@@ -66,6 +75,11 @@ _SIGS = [
                                        ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
     ("geninv_dlstsq_gram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int,
                                           ctypes.c_double, _VP, ctypes.c_int, _c_int_p]),
+    ("geninv_inc_factor", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double, _VP,
+                                         ctypes.c_int, _VP, _VP, _VP, ctypes.c_int, _c_int_p,
+                                         ctypes.POINTER(ctypes.c_double)]),
+    ("geninv_factored_lstsq", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
+                                             ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int]),
     ("geninv_batch_plan_create", ctypes.c_int, [_VP, ctypes.POINTER(_VP), ctypes.c_int, _c_int_p, _c_int_p,
                                                 ctypes.c_int, ctypes.POINTER(_VP), _c_int_p, ctypes.POINTER(_VP),
                                                 _c_int_p, ctypes.POINTER(_VP), _c_int_p, ctypes.c_double, _VP]),
@@ -76,6 +90,7 @@ _SIGS = [
     ("geninv_batch_plan_run", ctypes.c_int, [_VP, ctypes.c_int]),
     ("geninv_batch_plan_autotune", ctypes.c_int, [_VP, ctypes.c_int, _c_int_p, _c_int_p,
                                                   ctypes.POINTER(ctypes.c_double)]),
+    ("geninv_batch_plan_set_pivots", ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
     ("geninv_batch_plan_config", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
     ("geninv_batch_plan_get_config", ctypes.c_int, [_VP, _c_int_p, _c_int_p]),
     ("geninv_prof_classes", ctypes.c_int, []),

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 import torch
 
-from ._lib import GeninvError, load
+from ._lib import GENINV_EACCURACY, GeninvError, load
 
 _ctxs: dict = {}
 
@@ -91,22 +91,64 @@ def geninv(G: torch.Tensor, tol: float | None = None, *, return_piv: bool = Fals
     return Y, r.value
 
 
-def mixed(G: torch.Tensor, tol: float | None = None, slices: int = 4, chain_slices: int = 4, ns_steps: int = 0,
-          *, return_piv: bool = False):
-    """Y = G^+ with the Gram matrix and Y = P G' as exact sliced bfloat16
-    products (geninv_mixed); pivots and (L'L)^-1 in float64.  m >= n."""
+ENGINES = {"bf16": 1, "int8": 2}
+
+
+@dataclass
+class MixedResult:
+    Y: torch.Tensor
+    rank: int
+    piv: torch.Tensor
+    err_est: float
+    status: int          # 0, or the EACCURACY status when err_est exceeds the target
+
+
+def mixed(G: torch.Tensor, tol: float | None = None, engine: str = "int8", gram_digits: int = 16,
+          chain_digits: int = 16, ns_steps: int = 0, target: float = 0.0, *, return_result: bool = False):
+    """Y = G^+ with the Gram matrix and Y = P G' on reduced-precision matrix
+    cores (geninv_mixed): engine "int8" (digits = moduli, 16 give float64
+    accuracy) or "bf16" (digits = 8-bit slices, at most 4); pivots, the
+    factor and (L'L)^-1 in float64.  Returns (Y, r), or a MixedResult with
+    the error estimate and status when return_result (then a missed target
+    is reported in .status instead of raised)."""
     _dev(G, "G")
     m, n = G.shape
     Gc, ldg = colmajor(G)
     Y = empty_colmajor(n, m, G.device)
     piv = torch.empty(max(1, min(m, n)), dtype=torch.int32, device=G.device)
     r = ctypes.c_int(0)
-    st = load().geninv_mixed(_ctx(G.device), m, n, _p(Gc), ldg, float(tol or 0.0), int(slices), int(chain_slices),
-                             int(ns_steps), _p(Y), max(1, n), ctypes.byref(r), _p(piv))
+    est = ctypes.c_double(0.0)
+    st = load().geninv_mixed(_ctx(G.device), m, n, _p(Gc), ldg, float(tol or 0.0), ENGINES[engine],
+                             int(gram_digits), int(chain_digits), int(ns_steps), float(target), _p(Y), max(1, n),
+                             ctypes.byref(r), _p(piv), ctypes.byref(est))
+    if return_result and st == GENINV_EACCURACY:
+        return MixedResult(Y, r.value, piv[: r.value], est.value, st)
     _check(st, "geninv_mixed")
-    if return_piv:
-        return Y, r.value, piv[: r.value]
+    if return_result:
+        return MixedResult(Y, r.value, piv[: r.value], est.value, st)
     return Y, r.value
+
+
+def mgemm(A: torch.Tensor, B: torch.Tensor, transA: bool = False, transB: bool = False, moduli: int = 16,
+          lower: bool = False):
+    """C = op(A) op(B) on the int8 modular engine (geninv_mgemm)."""
+    _dev(A, "A")
+    _dev(B, "B")
+    Ac, lda = colmajor(A)
+    Bc, ldb = colmajor(B)
+    M = A.shape[1] if transA else A.shape[0]
+    K = A.shape[0] if transA else A.shape[1]
+    N = B.shape[0] if transB else B.shape[1]
+    if (B.shape[1] if transB else B.shape[0]) != K:
+        raise ValueError("inner dimensions differ")
+    C = empty_colmajor(M, N, A.device)
+    if lower:
+        C.zero_()
+    if Ac.data_ptr() == Bc.data_ptr() and lda == ldb:
+        Bc = Ac
+    _check(load().geninv_mgemm(_ctx(A.device), int(transA), int(transB), M, N, K, _p(Ac), lda, _p(Bc), ldb,
+                               int(moduli), int(lower), _p(C), max(1, M)), "geninv_mgemm")
+    return C
 
 
 def bslice(X: torch.Tensor, slices: int = 4, transposed: bool = False):
@@ -139,15 +181,25 @@ def bgram(G: torch.Tensor, slices: int = 4):
 class IncrementalLstsq:
     """Least squares W = G^+ F while columns are appended to G (Section 4's
     incremental learning): the Gram matrix G'G and G'F grow by the rows of
-    the new columns (geninv_inc_gram), and each solve runs the method from
-    them (geninv_dlstsq_gram).  Column-major device buffers sized for
-    ``nmax`` columns are held here."""
+    the new columns (geninv_inc_gram), the full-rank Cholesky factor and
+    (L'L)^-1 are extended rather than recomputed (geninv_inc_factor), and a
+    solve applies them (geninv_factored_lstsq).  ``refactor=True`` instead
+    runs the method from the Gram matrix on every solve
+    (geninv_dlstsq_gram).  Column-major device buffers sized for ``nmax``
+    columns are held here."""
 
-    def __init__(self, nmax: int, k: int, device=None):
+    def __init__(self, nmax: int, k: int, device=None, tol: float | None = None, refactor: bool = False):
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         self.nmax, self.k, self.n = int(nmax), int(k), 0
-        self.A = torch.zeros((self.nmax, self.nmax), dtype=torch.float64, device=self.device).t()
+        self.tol = float(tol or 0.0)
+        self.refactor = refactor
+        z = lambda: torch.zeros((self.nmax, self.nmax), dtype=torch.float64, device=self.device).t()
+        self.A = z()
         self.B = torch.zeros((max(1, self.k), self.nmax), dtype=torch.float64, device=self.device).t()
+        self.L, self.M = z(), z()
+        self.piv = torch.zeros(self.nmax, dtype=torch.int32, device=self.device)
+        self.dvals = torch.zeros(self.nmax, dtype=torch.float64, device=self.device)
+        self.rank, self.tol_used, self.n_factored = 0, 0.0, 0
 
     def append(self, G: torch.Tensor, F: torch.Tensor):
         """G: m x n_total, the columns seen so far followed by the new ones; F: m x k."""
@@ -158,18 +210,36 @@ class IncrementalLstsq:
             raise ValueError("G must hold the earlier columns first, at most nmax in all; F must be m x k")
         Gc, ldg = colmajor(G)
         Fc, ldf = colmajor(F)
-        _check(load().geninv_inc_gram(_ctx(self.device), m, self.n, n_total - self.n, self.k, _p(Gc), ldg, _p(Fc),
+        ctx = _ctx(self.device)
+        _check(load().geninv_inc_gram(ctx, m, self.n, n_total - self.n, self.k, _p(Gc), ldg, _p(Fc),
                                       ldf, _p(self.A), self.nmax, _p(self.B), self.nmax), "geninv_inc_gram")
         self.n = n_total
+        if not self.refactor:
+            r = ctypes.c_int(self.rank)
+            t = ctypes.c_double(self.tol_used)
+            _check(load().geninv_inc_factor(ctx, self.n_factored, self.n - self.n_factored, _p(self.A), self.nmax,
+                                            self.tol, _p(self.L), self.nmax, _p(self.piv), _p(self.dvals),
+                                            _p(self.M), self.nmax, ctypes.byref(r), ctypes.byref(t)),
+                   "geninv_inc_factor")
+            self.rank, self.tol_used, self.n_factored = r.value, t.value, self.n
 
     def solve(self, tol: float | None = None):
         """(W, rank) for the columns appended so far."""
         W = empty_colmajor(self.n, self.k, self.device)
+        if not self.refactor:
+            _check(load().geninv_factored_lstsq(_ctx(self.device), self.n, self.rank, self.k, _p(self.L), self.nmax,
+                                                _p(self.M), self.nmax, _p(self.B), self.nmax, _p(W), max(1, self.n)),
+                   "geninv_factored_lstsq")
+            return W, self.rank
         r = ctypes.c_int(0)
         _check(load().geninv_dlstsq_gram(_ctx(self.device), self.n, self.k, _p(self.A), self.nmax, _p(self.B),
-                                         self.nmax, float(tol or 0.0), _p(W), max(1, self.n), ctypes.byref(r)),
+                                         self.nmax, float(tol or self.tol or 0.0), _p(W), max(1, self.n),
+                                         ctypes.byref(r)),
                "geninv_dlstsq_gram")
         return W, r.value
+
+    def pivots(self):
+        return self.piv[: self.rank]
 
 
 def bchain(P: torch.Tensor, G: torch.Tensor, slices: int = 4):
@@ -189,7 +259,8 @@ def bchain(P: torch.Tensor, G: torch.Tensor, slices: int = 4):
 
 
 def lstsq(G: torch.Tensor, F: torch.Tensor, tol: float | None = None):
-    """W = G^+ F (n x k), minimum-norm least squares (Section 1); m >= n."""
+    """W = G^+ F (n x k), minimum-norm least squares (Section 1); m < n
+    takes the Appendix's transpose branch."""
     _dev(G, "G")
     _dev(F, "F")
     m, n = G.shape
@@ -388,6 +459,20 @@ class BatchPlan(_PackedBatch):
                                             float(tol or 0.0), _p(self.rank)),
                "geninv_batch_plan_create")
         self._plan = h
+
+    def enable_pivots(self):
+        """Allocate per-problem pivot outputs (geninv_batch_plan_set_pivots);
+        piv(b) then returns the kept column indices of problem b."""
+        import numpy as np
+        self.p_off = np.concatenate([[0], np.cumsum(self.n.astype(np.int64))])
+        self.Pbuf = torch.zeros(max(1, int(self.p_off[-1])), dtype=torch.int32, device=self.device)
+        pb = self.Pbuf.data_ptr()
+        self.Pp = (ctypes.c_void_p * self.batch)(*[pb + 4 * int(o) for o in self.p_off[:-1]])
+        _check(self._lib.geninv_batch_plan_set_pivots(self._plan, self.Pp), "geninv_batch_plan_set_pivots")
+
+    def piv(self, b: int):
+        o = int(self.p_off[b])
+        return self.Pbuf[o:o + int(self.rank[b])]
 
     def run(self, use_graph: bool = True):
         _ctx(self.device)   # follow torch's current stream

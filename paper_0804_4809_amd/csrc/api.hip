@@ -511,11 +511,157 @@ int run_sliced(geninv_ctx *c, SlicedGemmArgs g, double *part, size_t part_elems)
     return GENINV_OK;
 }
 
+// ---- int8 modular engine ---------------------------------------------------
+
+// Workspace and launch shape of one engine product C = op(A) op(B) (M x N,
+// depth K): int8 residue planes of both operands (shared for a Gram matrix),
+// their exponents, and the residue planes of the result.
+struct ModPlan {
+    int M = 0, N = 0, K = 0, Kpad = 0, beta = -1, splitk = 1, lower = 0;
+    bool same = false;
+    long sa = 0, sb = 0, strideR = 0;
+    size_t pa = 0, pb = 0, ea = 0, eb = 0, res = 0, total = 0;
+};
+
+ModPlan mod_plan(size_t base, int M, int N, int K, const ModConsts &mc, bool same, int lower) {
+    ModPlan P;
+    P.M = M;
+    P.N = N;
+    P.K = K;
+    P.lower = lower;
+    P.same = same;
+    P.Kpad = (int)pad64(std::max(K, 1));
+    P.beta = mod_beta(mc, K);
+    // split K when the tiles of all moduli leave the compute units short
+    // (about three workgroups each), keeping at least 16 stages per slice
+    const long tiles = mod_tiles(M, N, lower);
+    const int nst = P.Kpad / 64;
+    int S = mod_min_splits(P.Kpad);
+    while (S < 16 && tiles * mc.n * S < 768 && nst / (S + 1) >= 16) ++S;
+    P.splitk = S;
+    size_t off = base;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    P.sa = (long)P.Kpad * M;
+    P.pa = take((size_t)mc.n * P.sa);
+    P.sb = same ? P.sa : (long)P.Kpad * N;
+    P.pb = same ? P.pa : take((size_t)mc.n * P.sb);
+    P.ea = take((size_t)std::max(M, 1) * sizeof(int));
+    P.eb = same ? P.ea : take((size_t)std::max(N, 1) * sizeof(int));
+    P.strideR = (long)mod_residue_bytes(M, N, lower);
+    P.res = take((size_t)mc.n * S * P.strideR);
+    P.total = off;
+    return P;
+}
+
+// C = op(A) op(B) through the engine: op(A)(i, k) = A(k, i) when transA
+// (columns of A, column exponents), A(i, k) otherwise (rows of A through the
+// transposing slicer); op(B)(k, j) = B(k, j) unless transB.  With P.same the
+// operands are one matrix (A = B, transA, !transB) sliced once.
+int run_mod_product(geninv_ctx *c, const ModPlan &P, const ModConsts &mc, int transA, const double *A, long lda,
+                    int transB, const double *B, long ldb, double *C, long ldc) {
+    if (P.M <= 0 || P.N <= 0) return GENINV_OK;
+    if (P.beta < 0) return GENINV_EINVAL;
+    int8_t *pa = at<int8_t>(c, P.pa), *pb = at<int8_t>(c, P.pb);
+    int *ea = at<int>(c, P.ea), *eb = at<int>(c, P.eb);
+    if (transA) {
+        HIPCHK(launch_col_exponents(A, lda, P.K, P.M, ea, c->stream));
+        HIPCHK(launch_mod_slice_cols(A, lda, P.K, P.M, ea, P.beta, mc, pa, P.Kpad, P.sa, c->stream));
+    } else {
+        HIPCHK(launch_row_exponents(A, lda, P.M, P.K, ea, c->stream));
+        HIPCHK(launch_mod_slice_rows_t(A, lda, P.M, P.K, ea, P.beta, mc, pa, P.Kpad, P.sa, c->stream));
+    }
+    if (!P.same) {
+        if (!transB) {
+            HIPCHK(launch_col_exponents(B, ldb, P.K, P.N, eb, c->stream));
+            HIPCHK(launch_mod_slice_cols(B, ldb, P.K, P.N, eb, P.beta, mc, pb, P.Kpad, P.sb, c->stream));
+        } else {
+            HIPCHK(launch_row_exponents(B, ldb, P.N, P.K, eb, c->stream));
+            HIPCHK(launch_mod_slice_rows_t(B, ldb, P.N, P.K, eb, P.beta, mc, pb, P.Kpad, P.sb, c->stream));
+        }
+    }
+    int8_t *res = at<int8_t>(c, P.res);
+    ModGemmArgs g{};
+    g.A = pa; g.lda = P.Kpad; g.sa = P.sa;
+    g.B = pb; g.ldb = P.Kpad; g.sb = P.sb;
+    g.M = P.M; g.N = P.N; g.Kpad = P.Kpad;
+    g.lower = P.lower;
+    g.splitk = P.splitk;
+    g.R = res; g.strideR = P.strideR;
+    g.mc = mc;
+    HIPCHK(launch_mod_gemm(g, c->stream));
+    ModRecArgs r{};
+    r.R = res; r.strideR = P.strideR;
+    r.M = P.M; r.N = P.N; r.lower = P.lower; r.splitk = P.splitk; r.beta = P.beta;
+    r.ea = ea; r.eb = P.same ? ea : eb;
+    r.C = C; r.ldc = ldc;
+    r.mc = mc;
+    HIPCHK(launch_mod_reconstruct(r, c->stream));
+    return GENINV_OK;
+}
+
+// ---- the mixed form's workspace ---------------------------------------------
+
+constexpr int PROBES = 16;   // random sign vectors of the error estimate
+
+// After the float64 layout of the factored dimension nn: the engine's
+// operands (bf16 slice planes, or the int8 plans of the Gram matrix and of
+// the chain, which run at different times and share one region) and the
+// error estimate's probe blocks, sums and Gram diagonal.
+struct MixedPlan {
+    int precision = 0, gd = 0, cd = 0, ns = 0;
+    MixedLayout bf{};
+    ModConsts mg{}, mch{};
+    ModPlan pg{}, pch{};
+    size_t probe = 0, norms = 0, total = 0;
+    long pld = 0;   // rows of each probe block
+};
+
+int make_mixed_plan(size_t base, int m, int n, int precision, int gd, int cd, int ns, MixedPlan &P) {
+    const bool tr = m < n;
+    const int nn = tr ? m : n, mm = tr ? n : m;
+    P.precision = precision;
+    P.gd = gd;
+    P.cd = cd;
+    P.ns = ns;
+    size_t off = base;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    if (precision == GENINV_MIXED_BF16) {
+        P.bf = make_mixed_layout(off, mm, nn, gd, cd, false);
+        off = P.bf.total;
+    } else {
+        if (!mod_consts(gd, P.mg)) return GENINV_EINVAL;
+        P.pg = mod_plan(off, nn, nn, mm, P.mg, true, 1);
+        if (P.pg.beta < 0) return GENINV_EINVAL;
+        size_t end = P.pg.total;
+        if (cd > 0) {
+            if (!mod_consts(cd, P.mch)) return GENINV_EINVAL;
+            // Y (n x m) = P G' or G' P: depth nn
+            P.pch = mod_plan(off, n, m, nn, P.mch, false, 0);
+            if (P.pch.beta < 0) return GENINV_EINVAL;
+            end = std::max(end, P.pch.total);
+        }
+        off = end;
+    }
+    P.pld = std::max(m, n);
+    P.probe = take((size_t)8 * P.pld * PROBES * sizeof(double));
+    P.norms = take((size_t)(8 + nn) * sizeof(double));   // sums, then the Gram diagonal
+    P.total = off;
+    return GENINV_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int geninv_version(void) { return 100; }
+int geninv_version(void) { return 200; }
 
 int geninv_prof_classes(void) { return PC_COUNT; }
 
@@ -551,6 +697,7 @@ const char *geninv_strerror(int s) {
         case GENINV_ENONFINITE: return "input holds Inf or NaN (or its Gram matrix overflows)";
         case GENINV_ENOTSPD: return "L'L is not positive definite in floating point";
         case GENINV_ENOTSUP: return "not supported by the library";
+        case GENINV_EACCURACY: return "result written, but its error estimate exceeds the requested accuracy";
         default: return "unknown status";
     }
 }
@@ -625,9 +772,15 @@ int geninv_sync_status(geninv_ctx *c) {
     return st;
 }
 
-size_t geninv_workspace_bytes(int m, int n, int k) {
+size_t geninv_workspace_bytes(int m, int n, int k, int precision, int gram_digits, int chain_digits, int ns_steps) {
     if (m <= 0 || n <= 0 || k < 0) return 0;
-    return make_layout(std::min(m, n), k, std::max(m, n)).total;
+    if (precision == GENINV_FP64) return make_layout(std::min(m, n), k, std::max(m, n)).total;
+    const int dmax = precision == GENINV_MIXED_BF16 ? SG_MAX_S : (precision == GENINV_MIXED_INT8 ? MOD_MAX : 0);
+    if (gram_digits < 1 || gram_digits > dmax || chain_digits < 0 || chain_digits > dmax || ns_steps < 0) return 0;
+    const Layout lay = make_layout(std::min(m, n), PROBES);
+    MixedPlan mp;
+    if (make_mixed_plan(lay.total, m, n, precision, gram_digits, chain_digits, ns_steps, mp) != GENINV_OK) return 0;
+    return mp.total;
 }
 
 int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, double alpha, const double *A,
@@ -857,8 +1010,12 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     return finish_rank(c, rdev, rank);
 }
 
-int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf,
-                  double tol, double *W, int ldw, int *rank) {
+}  // extern "C"
+
+namespace {
+
+int dlstsq_run(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf, double tol,
+               double *W, int ldw, int *rank, bool noalloc) {
     if (!c || m < 0 || n < 0 || k < 0) return GENINV_EINVAL;
     if (n == 0 || m == 0) {
         // G^+ is n x 0 or 0 x m: W = 0 (n x k)
@@ -870,13 +1027,13 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
         if (rank) *rank = 0;
         return GENINV_OK;
     }
-    if (m < n) return GENINV_EINVAL;
     if (!G || !F || !W || bad_ld(ldg, m) || bad_ld(ldf, m) || bad_ld(ldw, n)) return GENINV_EINVAL;
     if (k > 4096) return GENINV_ENOTSUP;
     DeviceGuard g(c->device);
-    const int nn = n;
-    const Layout lay = make_layout(nn, k, m);
-    CHK(ensure_ws(c, lay.total));
+    const bool tr = m < n;              // Appendix: factor G G' when m < n
+    const int nn = tr ? m : n;
+    const Layout lay = make_layout(nn, k, tr ? n : m);
+    if (!noalloc) CHK(ensure_ws(c, lay.total));
     double *A = at<double>(c, lay.slotA);
     double *L = at<double>(c, lay.slotL);
     double *T0 = at<double>(c, lay.t0);
@@ -884,13 +1041,13 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
     double *T2 = at<double>(c, lay.t2);
     const long ld = nn;
 
-    CHK(run_gram(c, lay, G, ldg, false, nn, m));
+    CHK(run_gram(c, lay, G, ldg, tr, nn, tr ? n : m));
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, at<int>(c, lay.piv), at<double>(c, lay.dvals)));
     const int *rdev = at<int>(c, lay.rank) + (nn + FR_NB - 1) / FR_NB;
     Dim r;
     CHK(rank_dim(c, nn, rdev, &r));
     CHK(run_factor_inverse(c, lay, L, ld, nn, r, A, ld));
-    if (k > 0) {
+    if (k > 0 && !tr) {
         // W = L (M (M (L' (G' F))))
         ProfScope ps(c, PC_LSTSQ, 0.0);
         CHK(gemm_splitk(c, lay, gemm(G, ldg, 1, F, ldf, 0, T0, ld, hdim(nn), hdim(k), hdim(m), 1.0, 0.0)));
@@ -898,9 +1055,27 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
         HIPCHK(launch_dgemm(gemm(A, ld, 0, T1, ld, 0, T2, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
         HIPCHK(launch_dgemm(gemm(A, ld, 0, T2, ld, 0, T1, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
         HIPCHK(launch_dgemm(gemm(L, ld, 0, T1, ld, 0, W, ldw, hdim(nn), hdim(k), r, 1.0, 0.0), c->stream));
+    } else if (k > 0) {
+        // transpose branch, Y = G' L M M L': W = G' (L (M (M (L' F))))
+        ProfScope ps(c, PC_LSTSQ, 0.0);
+        HIPCHK(launch_dgemm(gemm(L, ld, 1, F, ldf, 0, T1, ld, r, hdim(k), hdim(nn), 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(A, ld, 0, T1, ld, 0, T2, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(A, ld, 0, T2, ld, 0, T1, ld, r, hdim(k), r, 1.0, 0.0), c->stream));
+        HIPCHK(launch_dgemm(gemm(L, ld, 0, T1, ld, 0, T0, ld, hdim(nn), hdim(k), r, 1.0, 0.0), c->stream));
+        CHK(gemm_splitk(c, lay, gemm(G, ldg, 1, T0, ld, 0, W, ldw, hdim(n), hdim(k), hdim(m), 1.0, 0.0)));
     }
     return finish_rank(c, rdev, rank);
 }
+
+}  // namespace
+
+extern "C" {
+
+int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf,
+                  double tol, double *W, int ldw, int *rank) {
+    return dlstsq_run(c, m, n, k, G, ldg, F, ldf, tol, W, ldw, rank, false);
+}
+
 
 // C (M x N, ldc) = op(A) op(B) split over K into `part` when the output is
 // too small to fill the compute units (S partial results, then a reduction)
@@ -950,6 +1125,210 @@ int geninv_inc_gram(geninv_ctx *c, int m, int n_old, int p, int k, const double 
     if (k > 0)
         CHK(rows_gemm(c, gemm(Gn, ldg, 1, F, ldf, 0, B + n_old, ldb, hdim(p), hdim(k), hdim(m), 1.0, 0.0), part,
                       part_elems));
+    return GENINV_OK;
+}
+
+}  // extern "C"
+
+namespace geninv {
+hipError_t launch_ns_scaled_eye(double *X, long ldx, int n, double a, hipStream_t s);
+}
+
+namespace {
+
+Layout shift_layout(Layout L, size_t base) {
+    for (size_t *f : {&L.slotA, &L.slotL, &L.slotK, &L.slotP, &L.part, &L.lpan, &L.dbuf, &L.rrow, &L.ccol, &L.dvals,
+                      &L.tol, &L.rank, &L.piv, &L.t0, &L.t1, &L.t2, &L.gpart, &L.total})
+        *f += base;
+    return L;
+}
+
+// Full factorization of the Gram matrix A (n x n) for geninv_inc_factor:
+// L, piv, dvals, M = (L'L)^-1, rank and tol_used.
+int inc_full(geninv_ctx *c, int n, const double *A, long lda, double tol, double *L, long ldl, int *piv,
+             double *dvals, double *M, long ldm, int *rank, double *tol_io) {
+    const Layout lay = make_layout(n, 0);
+    CHK(ensure_ws(c, lay.total));
+    double *Aw = at<double>(c, lay.slotA);
+    HIPCHK(launch_copy(A, lda, Aw, n, hdim(n), hdim(n), c->stream));
+    CHK(run_frchol(c, lay, Aw, n, n, tol, L, ldl, piv, dvals));
+    const int *rdev = at<int>(c, lay.rank) + (n + FR_NB - 1) / FR_NB;
+    int r = 0;
+    double t = 0.0;
+    HIPCHK(hipMemcpyAsync(c->hpin, rdev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&t, at<double>(c, lay.tol), sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    r = *c->hpin;
+    if (r < 0 || r > n) return GENINV_EHIP;
+    if (r > 0) CHK(run_factor_inverse(c, lay, L, ldl, n, hdim(r), M, ldm));
+    *rank = r;
+    *tol_io = t;
+    return GENINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int geninv_inc_factor(geninv_ctx *c, int n_old, int p, const double *A, int lda, double tol, double *L, int ldl,
+                      int *piv, double *dvals, double *M, int ldm, int *rank_io, double *tol_io) {
+    if (!c || n_old < 0 || p < 0 || !rank_io || !tol_io) return GENINV_EINVAL;
+    const int n = n_old + p;
+    if (n == 0) {
+        *rank_io = 0;
+        return GENINV_OK;
+    }
+    if (!A || !L || !piv || !dvals || !M || bad_ld(lda, n) || bad_ld(ldl, n) || bad_ld(ldm, n)) return GENINV_EINVAL;
+    const int r0 = n_old > 0 ? *rank_io : 0;
+    if (r0 < 0 || r0 > n_old) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    if (p == 0) return GENINV_OK;
+    if (n_old == 0 || r0 == 0) return inc_full(c, n, A, lda, tol, L, ldl, piv, dvals, M, ldm, rank_io, tol_io);
+
+    // the threshold for all n columns (the paper's default follows the
+    // smallest positive diagonal); the earlier decisions stand unless a
+    // dropped pivot lies between the new threshold and the old one
+    const Layout full = make_layout(n, 0);
+    CHK(ensure_ws(c, full.total));
+    double tol_new = tol;
+    {
+        double *tp = at<double>(c, full.tol);
+        HIPCHK(launch_tol(A, lda, n, tol, tp, c->status, c->stream));
+        HIPCHK(hipMemcpyAsync(&tol_new, tp, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    if (tol_new != *tol_io) {
+        std::vector<double> dv(n_old);
+        std::vector<int> pv(r0);
+        HIPCHK(hipMemcpy(dv.data(), dvals, sizeof(double) * n_old, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(pv.data(), piv, sizeof(int) * r0, hipMemcpyDeviceToHost));
+        std::vector<char> kept(n_old, 0);
+        for (int q : pv) kept[q] = 1;
+        bool flips = false;
+        for (int k = 0; k < n_old; ++k) {
+            const bool keep_new = dv[k] > tol_new, keep_old = kept[k] != 0;
+            flips = flips || keep_new != keep_old;
+        }
+        if (flips) return inc_full(c, n, A, lda, tol, L, ldl, piv, dvals, M, ldm, rank_io, tol_io);
+    }
+
+    // workspace: the incremental step's blocks, then a layout for the p x p
+    // Schur complement
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const int nbk = (r0 + 63) / 64;
+    const size_t oLp = take(sizeof(double) * r0 * (size_t)r0), oBw = take(sizeof(double) * r0 * (size_t)p),
+                 oX = take(sizeof(double) * r0 * (size_t)p), oDi = take(sizeof(double) * 4096 * (size_t)nbk),
+                 oS = take(sizeof(double) * p * (size_t)p), oLS = take(sizeof(double) * p * (size_t)p),
+                 oPs = take(sizeof(int) * (size_t)p), oDs = take(sizeof(double) * (size_t)p),
+                 oZ = take(sizeof(double) * r0 * (size_t)p), oH = take(sizeof(double) * p * (size_t)p),
+                 oQ = take(sizeof(double) * r0 * (size_t)p), oB12 = take(sizeof(double) * r0 * (size_t)p),
+                 oU = take(sizeof(double) * r0 * (size_t)p), oV = take(sizeof(double) * r0 * (size_t)p),
+                 oT = take(sizeof(double) * p * (size_t)p);
+    const Layout sub = shift_layout(make_layout(p, 0), off);
+    CHK(ensure_ws(c, sub.total));
+    double *Lp = at<double>(c, oLp), *Bw = at<double>(c, oBw), *X = at<double>(c, oX), *Di = at<double>(c, oDi);
+    double *S = at<double>(c, oS), *LS = at<double>(c, oLS), *ds = at<double>(c, oDs);
+    int *ps = at<int>(c, oPs);
+    double *Z = at<double>(c, oZ), *H = at<double>(c, oH), *Q = at<double>(c, oQ), *B12 = at<double>(c, oB12);
+    double *U = at<double>(c, oU), *V = at<double>(c, oV), *T = at<double>(c, oT);
+    auto mm = [&](const double *Am, long la, int ta, const double *Bm, long lb, int tb, double *Cm, long lc, int Mr,
+                  int Nc, int Kd, double al, double be, int uplo = GEMM_FULL) -> int {
+        if (Mr <= 0 || Nc <= 0) return GENINV_OK;
+        HIPCHK(launch_dgemm(gemm(Am, la, ta, Bm, lb, tb, Cm, lc, hdim(Mr), hdim(Nc), hdim(Kd), al, be, uplo),
+                            c->stream));
+        return GENINV_OK;
+    };
+
+    // new rows of L: L_P X = B_P, blocked by 64 with inverted diagonal blocks
+    HIPCHK(launch_gather_rows(L, ldl, piv, r0, r0, Lp, r0, c->stream));
+    HIPCHK(launch_gather_cols_t(A, lda, n_old, piv, r0, p, Bw, r0, c->stream));
+    HIPCHK(launch_trinv64(Lp, r0, r0, Di, c->stream));
+    for (int b = 0; b < nbk; ++b) {
+        const int k0 = b * 64, bs = std::min(64, r0 - k0), rest = r0 - k0 - bs;
+        CHK(mm(Di + (long)b * 4096, 64, 0, Bw + k0, r0, 0, X + k0, r0, bs, p, bs, 1.0, 0.0));
+        CHK(mm(Lp + (k0 + bs) + (long)k0 * r0, r0, 0, X + k0, r0, 0, Bw + k0 + bs, r0, rest, p, bs, -1.0, 1.0));
+    }
+    // the new columns' Schur complement and its full-rank Cholesky
+    HIPCHK(launch_copy(A + n_old + (long)n_old * lda, lda, S, p, hdim(p), hdim(p), c->stream));
+    CHK(mm(X, r0, 1, X, r0, 0, S, p, p, p, r0, -1.0, 1.0, GEMM_LOWER));
+    HIPCHK(launch_fill(L + (long)r0 * ldl, ldl, n_old, p, 0.0, c->stream));   // zeros above the new pivots
+    CHK(run_frchol(c, sub, S, p, p, tol_new, LS, p, ps, ds));
+    int rs = 0;
+    HIPCHK(hipMemcpyAsync(c->hpin, at<int>(c, sub.rank) + (p + FR_NB - 1) / FR_NB, sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    rs = *c->hpin;
+    if (rs < 0 || rs > p) return GENINV_EHIP;
+    HIPCHK(launch_transpose(X, r0, L + n_old, ldl, r0, p, c->stream));
+    if (rs > 0) {
+        HIPCHK(launch_copy(LS, p, L + n_old + (long)r0 * ldl, ldl, hdim(p), hdim(rs), c->stream));
+        HIPCHK(launch_offset_int(ps, rs, n_old, piv + r0, c->stream));
+    }
+    HIPCHK(launch_copy(ds, 1, dvals + n_old, 1, hdim(1), hdim(p), c->stream));
+
+    // M = (L'L)^-1 for the extended L = [L_old 0; X' LS]:
+    //   L'L = [B11 B12; B12' LS'LS] with B11 = L_old'L_old + X X', B12 = X LS;
+    //   B11^-1 = M0 - Z (I + X'Z)^-1 Z'  (Z = M0 X, Woodbury);
+    //   with U = B11^-1 B12 and T = LS'LS - B12' U (Schur complement):
+    //   M = [B11^-1 + U T^-1 U', -U T^-1; -T^-1 U', T^-1].
+    CHK(mm(M, ldm, 0, X, r0, 0, Z, r0, r0, p, r0, 1.0, 0.0));
+    HIPCHK(launch_ns_scaled_eye(H, p, p, 1.0, c->stream));
+    CHK(mm(X, r0, 1, Z, r0, 0, H, p, p, p, r0, 1.0, 1.0));
+    CHK(run_spdinv(c, sub, H, p, hdim(p)));
+    CHK(mm(Z, r0, 0, H, p, 0, Q, r0, r0, p, p, 1.0, 0.0));
+    CHK(mm(Q, r0, 0, Z, r0, 1, M, ldm, r0, r0, p, -1.0, 1.0));
+    if (rs > 0) {
+        CHK(mm(X, r0, 0, LS, p, 0, B12, r0, r0, rs, p, 1.0, 0.0));
+        CHK(mm(M, ldm, 0, B12, r0, 0, U, r0, r0, rs, r0, 1.0, 0.0));
+        CHK(mm(LS, p, 1, LS, p, 0, T, p, rs, rs, p, 1.0, 0.0));
+        CHK(mm(B12, r0, 1, U, r0, 0, T, p, rs, rs, r0, -1.0, 1.0));
+        CHK(run_spdinv(c, sub, T, p, hdim(rs)));
+        CHK(mm(U, r0, 0, T, p, 0, V, r0, r0, rs, rs, 1.0, 0.0));
+        CHK(mm(V, r0, 0, U, r0, 1, M, ldm, r0, r0, rs, 1.0, 1.0));                     // + U T^-1 U'
+        CHK(mm(U, r0, 0, T, p, 0, M + (long)r0 * ldm, ldm, r0, rs, rs, -1.0, 0.0));   // -U T^-1
+        CHK(mm(T, p, 0, U, r0, 1, M + r0, ldm, rs, r0, rs, -1.0, 0.0));               // -T^-1 U'
+        HIPCHK(launch_copy(T, p, M + r0 + (long)r0 * ldm, ldm, hdim(rs), hdim(rs), c->stream));
+    }
+    *rank_io = r0 + rs;
+    *tol_io = tol_new;
+    int st = 0;
+    HIPCHK(hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (st != 0) {
+        int zero = 0;
+        HIPCHK(hipMemcpy(c->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+    }
+    return st;
+}
+
+int geninv_factored_lstsq(geninv_ctx *c, int n, int r, int k, const double *L, int ldl, const double *M, int ldm,
+                          const double *B, int ldb, double *W, int ldw) {
+    if (!c || n < 0 || r < 0 || r > n || k < 0) return GENINV_EINVAL;
+    if (n == 0 || k == 0) return GENINV_OK;
+    if (!W || !B || bad_ld(ldw, n) || bad_ld(ldb, n)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    if (r == 0) {
+        HIPCHK(launch_fill(W, ldw, n, k, 0.0, c->stream));
+        return GENINV_OK;
+    }
+    if (!L || !M || bad_ld(ldl, n) || bad_ld(ldm, r)) return GENINV_EINVAL;
+    size_t off = 0;
+    const size_t o1 = off;
+    off += align256(sizeof(double) * r * (size_t)k);
+    const size_t o2 = off;
+    off += align256(sizeof(double) * r * (size_t)k);
+    CHK(ensure_ws(c, off));
+    double *T1 = at<double>(c, o1), *T2 = at<double>(c, o2);
+    // W = L (M (M (L' B)))
+    HIPCHK(launch_dgemm(gemm(L, ldl, 1, B, ldb, 0, T1, r, hdim(r), hdim(k), hdim(n), 1.0, 0.0), c->stream));
+    HIPCHK(launch_dgemm(gemm(M, ldm, 0, T1, r, 0, T2, r, hdim(r), hdim(k), hdim(r), 1.0, 0.0), c->stream));
+    HIPCHK(launch_dgemm(gemm(M, ldm, 0, T2, r, 0, T1, r, hdim(r), hdim(k), hdim(r), 1.0, 0.0), c->stream));
+    HIPCHK(launch_dgemm(gemm(L, ldl, 0, T1, r, 0, W, ldw, hdim(n), hdim(k), hdim(r), 1.0, 0.0), c->stream));
     return GENINV_OK;
 }
 
@@ -1062,48 +1441,147 @@ int geninv_bchain(geninv_ctx *c, int n, int m, int k, const double *P, int ldp, 
     return run_sliced(c, sg, nullptr, 0);
 }
 
-int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double tol, int slices, int chain_slices,
-                 int ns_steps, double *Y, int ldy, int *rank, int *piv) {
-    if (!c || m < 0 || n < 0 || slices < 1 || slices > SG_MAX_S || chain_slices < 0 || chain_slices > SG_MAX_S ||
-        ns_steps < 0)
+// The error estimate of a mixed result (geninv_mixed), from PROBES random
+// sign vectors and float64 products with the caller's G:
+//   resA = ||A_e V - G'(G V)|| / ||G'(G V)||, the engine's Gram matrix A_e
+//          against float64 products (its representation error, measured);
+//   kappa = max_k A_kk / (smallest accepted pivot), the factorization's
+//          amplification of a relative Gram perturbation into P;
+//   resY = ||Y V' - P (G' V')|| / ||P (G' V')||, the engine's chain product
+//          against float64 products on the same P (measured).
+// err_est = kappa resA + resY: a first-order estimate of the relative change
+// the engine makes to Y against the float64 form on the same G (Frobenius
+// norms estimated from the probes, relative spread about 1 / sqrt(2 PROBES)).
+struct MixedProbe {
+    double *blk, *nrm;
+    long L;
+    double *col(int i) const { return blk + (long)i * L * PROBES; }
+};
+
+// resA terms (nrm[0], nrm[1]) right after the Gram matrix, mirrored to full
+// in A (the factorization reads only the lower triangle), and its diagonal
+// into nrm + 8 ..
+int probe_gram(geninv_ctx *c, const Layout &lay, const MixedProbe &pr, int m, int n, const double *G, long ldg,
+               const double *A, long lda, double *diag) {
+    const bool tr = m < n;
+    const int nn = tr ? m : n;
+    const int p = PROBES;
+    const long L = pr.L;
+    double *V = pr.col(0), *W1 = pr.col(1), *W2 = pr.col(2), *U = pr.col(3);
+    auto mm_ = [&](const double *X, long ldx, int tX, const double *Bm, long ldb, double *Cm, int M, int K) {
+        return gemm_splitk(c, lay, gemm(X, ldx, tX, Bm, ldb, 0, Cm, L, hdim(M), hdim(p), hdim(K), 1.0, 0.0));
+    };
+    HIPCHK(launch_fill(pr.nrm, 8, 8, 1, 0.0, c->stream));
+    HIPCHK(launch_copy(A, lda + 1, diag, 1, hdim(1), hdim(nn), c->stream));
+    HIPCHK(launch_probe_fill(V, L, nn, p, 0x5eed0001ULL, c->stream));
+    CHK(mm_(A, lda, 0, V, L, U, nn, nn));
+    if (!tr) {
+        CHK(mm_(G, ldg, 0, V, L, W1, m, n));     // G V   (m x p)
+        CHK(mm_(G, ldg, 1, W1, L, W2, n, m));    // G' W1 (n x p)
+    } else {
+        CHK(mm_(G, ldg, 1, V, L, W1, n, m));     // G' V  (n x p)
+        CHK(mm_(G, ldg, 0, W1, L, W2, m, n));    // G W1  (m x p)
+    }
+    HIPCHK(launch_diff_fro2(U, L, W2, L, nn, p, pr.nrm, c->stream));
+    return GENINV_OK;
+}
+
+// resY terms (nrm[2], nrm[3]) and kappa (nrm[4]) after the chain; one host
+// synchronization for all of them.
+int probe_finish(geninv_ctx *c, const Layout &lay, const MixedProbe &pr, int m, int n, const double *G, long ldg,
+                 const double *P, long ldp, const double *Y, long ldy, const double *diag, const int *rdev,
+                 const int *pv, double *est) {
+    const bool tr = m < n;
+    const int nn = tr ? m : n;
+    const int p = PROBES;
+    const long L = pr.L;
+    double *Oy = pr.col(4), *T = pr.col(5), *Yr = pr.col(6), *Yo = pr.col(7);
+    auto mm_ = [&](const double *X, long ldx, int tX, const double *Bm, long ldb, double *Cm, int M, int K) {
+        return gemm_splitk(c, lay, gemm(X, ldx, tX, Bm, ldb, 0, Cm, L, hdim(M), hdim(p), hdim(K), 1.0, 0.0));
+    };
+    HIPCHK(launch_probe_fill(Oy, L, m, p, 0x5eed0002ULL, c->stream));
+    CHK(mm_(Y, ldy, 0, Oy, L, Yo, n, m));
+    if (!tr) {
+        CHK(mm_(G, ldg, 1, Oy, L, T, n, m));     // G' V'
+        CHK(mm_(P, ldp, 0, T, L, Yr, n, n));     // P (G' V')
+    } else {
+        CHK(mm_(P, ldp, 0, Oy, L, T, m, m));     // P V'
+        CHK(mm_(G, ldg, 1, T, L, Yr, n, m));     // G' (P V')
+    }
+    HIPCHK(launch_diff_fro2(Yo, L, Yr, L, n, p, pr.nrm + 2, c->stream));
+    HIPCHK(launch_kappa(diag, at<double>(c, lay.dvals), pv, rdev, nn, pr.nrm + 4, c->stream));
+    double h[5] = {0, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(h, pr.nrm, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const double resA = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+    const double resY = h[3] > 0.0 ? std::sqrt(h[2] / h[3]) : 0.0;
+    *est = h[4] * resA + resY;
+    if (!std::isfinite(*est)) *est = std::numeric_limits<double>::infinity();
+    return GENINV_OK;
+}
+
+int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double tol, int precision, int gram_digits,
+                 int chain_digits, int ns_steps, double target, double *Y, int ldy, int *rank, int *piv,
+                 double *err_est) {
+    if (!c || m < 0 || n < 0 || ns_steps < 0 || ns_steps > 16) return GENINV_EINVAL;
+    if (precision == GENINV_MIXED_BF16) {
+        if (gram_digits < 1 || gram_digits > SG_MAX_S || chain_digits < 0 || chain_digits > SG_MAX_S)
+            return GENINV_EINVAL;
+    } else if (precision == GENINV_MIXED_INT8) {
+        if (gram_digits < 1 || gram_digits > MOD_MAX || chain_digits < 0 || chain_digits > MOD_MAX)
+            return GENINV_EINVAL;
+    } else {
         return GENINV_EINVAL;
+    }
+    if (err_est) *err_est = 0.0;
     if (m == 0 || n == 0) {
         if (rank) *rank = 0;
         return GENINV_OK;
     }
-    if (m < n) return GENINV_ENOTSUP;
     if (!G || !Y || bad_ld(ldg, m) || bad_ld(ldy, n)) return GENINV_EINVAL;
     DeviceGuard g(c->device);
-    const int nn = n;
-    const Layout lay = make_layout(nn, 0);
-    const MixedLayout ml = make_mixed_layout(lay.total, m, n, slices, chain_slices, ns_steps > 0);
-    CHK(ensure_ws(c, ml.total));
+    const bool tr = m < n;                 // Appendix: factor G G' when m < n
+    const int nn = tr ? m : n, mm = tr ? n : m;
+    const Layout lay = make_layout(nn, PROBES);
+    MixedPlan mp;
+    CHK(make_mixed_plan(lay.total, m, n, precision, gram_digits, chain_digits, ns_steps, mp));
+    CHK(ensure_ws(c, mp.total));
     double *A = at<double>(c, lay.slotA);
     double *L = at<double>(c, lay.slotL);
     double *K = at<double>(c, lay.slotK);
     double *P = at<double>(c, lay.slotP);
     int *pv = piv ? piv : at<int>(c, lay.piv);
-    __bf16 *Gc = at<__bf16>(c, ml.gc);
-    int *ecg = at<int>(c, ml.ecg);
     const long ld = nn;
-    const long mp = pad64(m), np = pad64(n);
 
-    // 1. Gram matrix of the sliced G on the bfloat16 matrix cores (lower triangle)
-    {
-        ProfScope ps(c, PC_SLICE, 0.0);
-        HIPCHK(launch_col_exponents(G, ldg, m, n, ecg, c->stream));
-        HIPCHK(launch_slice_cols(G, ldg, m, n, ecg, slices, Gc, mp, mp * n, c->stream));
+    // 1. Gram matrix (lower triangle) on the engine: G'G, or G G' when m < n
+    if (precision == GENINV_MIXED_BF16) {
+        const int s = gram_digits;
+        __bf16 *Gc = at<__bf16>(c, mp.bf.gc);
+        int *eg = at<int>(c, mp.bf.ecg);
+        const long kp = pad64(mm);
+        {
+            ProfScope ps(c, PC_SLICE, 0.0);
+            if (!tr) {
+                HIPCHK(launch_col_exponents(G, ldg, m, n, eg, c->stream));
+                HIPCHK(launch_slice_cols(G, ldg, m, n, eg, s, Gc, kp, kp * nn, c->stream));
+            } else {
+                HIPCHK(launch_row_exponents(G, ldg, m, n, eg, c->stream));
+                HIPCHK(launch_slice_rows_t(G, ldg, m, n, eg, s, Gc, kp, kp * nn, c->stream));
+            }
+        }
+        ProfScope ps(c, PC_GRAM, (double)mm * nn * (nn + 1.0));
+        CHK(run_sliced(c, sliced(Gc, kp, kp * nn, Gc, kp, kp * nn, s, eg, eg, A, ld, nn, nn, (int)kp, 1),
+                       mp.bf.gpart ? at<double>(c, mp.bf.gpart) : nullptr, mp.bf.gpart_elems));
+    } else {
+        ProfScope ps(c, PC_GRAM, (double)mm * nn * (nn + 1.0));
+        CHK(run_mod_product(c, mp.pg, mp.mg, tr ? 0 : 1, G, ldg, tr ? 1 : 0, G, ldg, A, ld));
     }
-    {
-        ProfScope ps(c, PC_GRAM, (double)m * nn * (nn + 1.0));
-        CHK(run_sliced(c, sliced(Gc, mp, mp * n, Gc, mp, mp * n, slices, ecg, ecg, A, ld, n, n, (int)mp, 1),
-                       ml.gpart ? at<double>(c, ml.gpart) : nullptr, ml.gpart_elems));
-    }
-    double *Gram = nullptr;
-    if (ns_steps > 0) {
-        Gram = at<double>(c, ml.gram);
-        HIPCHK(launch_copy(A, ld, Gram, ld, hdim(nn), hdim(nn), c->stream));
-        HIPCHK(launch_mirror_lower(Gram, ld, hdim(nn), c->stream));
+    const bool estimate = err_est || target > 0.0;
+    const MixedProbe pr{at<double>(c, mp.probe), at<double>(c, mp.norms), mp.pld};
+    double *diag = pr.nrm + 8;
+    if (estimate) {
+        HIPCHK(launch_mirror_lower(A, ld, hdim(nn), c->stream));
+        CHK(probe_gram(c, lay, pr, m, n, G, ldg, A, ld, diag));
     }
     // 2-4. tolerance, full-rank Cholesky, (L'L)^-1 in float64
     CHK(run_frchol(c, lay, A, ld, nn, tol, L, ld, pv, at<double>(c, lay.dvals)));
@@ -1121,40 +1599,103 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
         CHK(gemm_fill(c, lay, gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER)));
         HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
     }
-    // 6. Newton-Schulz steps on P = (G'G)^+ in factored form: P <- 2P - P A P
-    //    (X = P G' follows the iteration X <- 2X - X G X)
+    // 6. Newton-Schulz steps X <- X (2I - G_r X) in the factored form on P
+    //    (X = P G'): P <- 2P - P (L L') P, float64 products.  L L' is the
+    //    Gram matrix of the columns the factorization kept; P = (L L')^+ is
+    //    the method's own fixed point, so the steps correct the rounding of
+    //    (L'L)^-1, K and P.  (Against the full Gram matrix A the step would
+    //    not converge on rank-deficient inputs: A - L L' holds the dropped
+    //    pivots, up to tol, and P (A - L L') P is of the order of P itself
+    //    once accepted pivots come near tol.)  A step is taken only while
+    //    its correction ||P L L' P - P||_F / ||P||_F keeps falling.
+    double prev = std::numeric_limits<double>::infinity();
     for (int it = 0; it < ns_steps; ++it) {
-        ProfScope ps(c, PC_NS, 4.0 * nn * nn * nn);
-        double *T = L;   // L is no longer needed
-        HIPCHK(launch_dgemm(gemm(Gram, ld, 0, P, ld, 0, T, ld, hdim(nn), hdim(nn), hdim(nn), 1.0, 0.0), c->stream));
-        HIPCHK(launch_dgemm(gemm(P, ld, 0, T, ld, 0, K, ld, hdim(nn), hdim(nn), hdim(nn), -1.0, 0.0), c->stream));
-        // K = -P A P;  P <- 2P + K, kept exactly symmetric from its lower half
-        HIPCHK(launch_axpby(K, ld, P, ld, hdim(nn), hdim(nn), 1.0, 2.0, c->stream));
-        HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
+        ProfScope ps(c, PC_NS, 3.0 * nn * (double)nn * r.host);
+        double *T = A;   // M is no longer needed: T = P L (nn x r)
+        CHK(gemm_fill(c, lay, gemm(P, ld, 0, L, ld, 0, T, ld, hdim(nn), r, hdim(nn), 1.0, 0.0)));
+        CHK(gemm_fill(c, lay, gemm(T, ld, 0, T, ld, 1, K, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER)));
+        HIPCHK(launch_mirror_lower(K, ld, hdim(nn), c->stream));
+        HIPCHK(launch_fill(pr.nrm + 6, 2, 2, 1, 0.0, c->stream));
+        HIPCHK(launch_diff_fro2(K, ld, P, ld, nn, nn, pr.nrm + 6, c->stream));
+        double h[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(h, pr.nrm + 6, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        const double corr = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : 0.0;
+        if (!(corr < prev)) break;
+        prev = corr;
+        // K = P L L' P;  P <- 2P - K (both exactly symmetric)
+        HIPCHK(launch_axpby(K, ld, P, ld, hdim(nn), hdim(nn), -1.0, 2.0, c->stream));
     }
-    // 7. Y = P G'
-    if (chain_slices > 0) {
-        __bf16 *Gt = at<__bf16>(c, ml.gt);
-        __bf16 *Pc = at<__bf16>(c, ml.pc);
-        int *erg = at<int>(c, ml.erg);
-        int *ep = at<int>(c, ml.ep);
+    // 7. Y = P G' (G' P in the transpose branch)
+    if (chain_digits == 0) {
+        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * (double)nn);
+        if (!tr) HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
+        else HIPCHK(launch_dgemm(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0), c->stream));
+    } else if (precision == GENINV_MIXED_BF16) {
+        const int s = chain_digits;
+        __bf16 *Gt = at<__bf16>(c, mp.bf.gt);
+        __bf16 *Pc = at<__bf16>(c, mp.bf.pc);
+        int *eg = at<int>(c, mp.bf.erg);
+        int *ep = at<int>(c, mp.bf.ep);
+        const long np = pad64(nn);
         {
             ProfScope ps(c, PC_SLICE, 0.0);
-            HIPCHK(launch_row_exponents(G, ldg, m, n, erg, c->stream));
-            HIPCHK(launch_slice_rows_t(G, ldg, m, n, erg, chain_slices, Gt, np, np * m, c->stream));
             // P is symmetric: its column slices are its row slices
             HIPCHK(launch_col_exponents(P, ld, nn, nn, ep, c->stream));
-            HIPCHK(launch_slice_cols(P, ld, nn, nn, ep, chain_slices, Pc, np, np * nn, c->stream));
+            HIPCHK(launch_slice_cols(P, ld, nn, nn, ep, s, Pc, np, np * nn, c->stream));
+            if (!tr) {   // rows of G (columns of G')
+                HIPCHK(launch_row_exponents(G, ldg, m, n, eg, c->stream));
+                HIPCHK(launch_slice_rows_t(G, ldg, m, n, eg, s, Gt, np, np * m, c->stream));
+            } else {     // columns of G (rows of G')
+                HIPCHK(launch_col_exponents(G, ldg, m, n, eg, c->stream));
+                HIPCHK(launch_slice_cols(G, ldg, m, n, eg, s, Gt, np, np * n, c->stream));
+            }
         }
-        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
-        SlicedGemmArgs sg = sliced(Pc, np, np * nn, Gt, np, np * m, chain_slices, ep, erg, Y, ldy, n, m, (int)np, 0);
-        sg.nclass = sliced_chain_classes(chain_slices);
+        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * (double)nn);
+        SlicedGemmArgs sg = !tr ? sliced(Pc, np, np * nn, Gt, np, np * m, s, ep, eg, Y, ldy, n, m, (int)np, 0)
+                                : sliced(Gt, np, np * n, Pc, np, np * nn, s, eg, ep, Y, ldy, n, m, (int)np, 0);
+        sg.nclass = sliced_chain_classes(s);
         CHK(run_sliced(c, sg, nullptr, 0));
     } else {
-        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
-        HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
+        ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * (double)nn);
+        // P symmetric: op(P) = P' through the column slicer
+        if (!tr) CHK(run_mod_product(c, mp.pch, mp.mch, 1, P, ld, 1, G, ldg, Y, ldy));
+        else CHK(run_mod_product(c, mp.pch, mp.mch, 1, G, ldg, 0, P, ld, Y, ldy));
     }
-    return finish_rank(c, rdev, rank);
+    // 8. error estimate against float64 products with the caller's G
+    double est = 0.0;
+    if (estimate) {
+        CHK(probe_finish(c, lay, pr, m, n, G, ldg, P, ld, Y, ldy, diag, rdev, pv, &est));
+        if (err_est) *err_est = est;
+    }
+    const int st = finish_rank(c, rdev, rank);
+    if (st != GENINV_OK) return st;
+    if (target > 0.0 && !(est <= target)) return GENINV_EACCURACY;
+    return GENINV_OK;
+}
+
+// C = op(A) op(B) (M x N, ldc) on the int8 engine with `moduli` moduli,
+// exactly as geninv_mixed forms its products; lower != 0 writes the lower
+// triangle of a square product only.
+int geninv_mgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, const double *A, int lda,
+                 const double *B, int ldb, int moduli, int lower, double *C, int ldc) {
+    if (!c || M < 0 || N < 0 || K < 0 || moduli < 1 || moduli > MOD_MAX) return GENINV_EINVAL;
+    if (M == 0 || N == 0) return GENINV_OK;
+    if (!C || bad_ld(ldc, M) || (lower && M != N)) return GENINV_EINVAL;
+    DeviceGuard g(c->device);
+    if (K == 0) {
+        HIPCHK(launch_fill(C, ldc, M, N, 0.0, c->stream));
+        return GENINV_OK;
+    }
+    if (!A || !B || bad_ld(lda, transA ? K : M) || bad_ld(ldb, transB ? N : K)) return GENINV_EINVAL;
+    ModConsts mc{};
+    if (!mod_consts(moduli, mc)) return GENINV_EINVAL;
+    const bool same = A == B && lda == ldb && transA && !transB && M == N;
+    const ModPlan P = mod_plan(0, M, N, K, mc, same, lower ? 1 : 0);
+    if (P.beta < 0) return GENINV_EINVAL;
+    CHK(ensure_ws(c, P.total));
+    ProfScope ps(c, PC_GEMM, 2.0 * M * N * (double)K);
+    return run_mod_product(c, P, mc, transA ? 1 : 0, A, lda, transB ? 1 : 0, B, ldb, C, ldc);
 }
 
 }  // extern "C"
@@ -1289,6 +1830,18 @@ int geninv_lstsq_batched(geninv_ctx *c, int batch, const int *m, const int *n, i
     (void)geninv_batch_plan_destroy(p);   // synchronizes the context stream
     if (st != GENINV_OK) return st;
     if (status) *status = geninv_sync_status(c);
+    return GENINV_OK;
+}
+
+int geninv_batch_plan_set_pivots(geninv_batch_plan *p, int *const *piv) {
+    if (!p) return GENINV_EINVAL;
+    if (p->batch == 0) return GENINV_OK;
+    DeviceGuard g(p->c->device);
+    std::vector<char> desc(batched_desc_bytes() * p->batch);
+    HIPCHK(hipStreamSynchronize(p->c->stream));
+    HIPCHK(hipMemcpy(desc.data(), p->desc, desc.size(), hipMemcpyDeviceToHost));
+    for (int b = 0; b < p->batch; ++b) batched_set_piv(desc.data(), b, piv ? piv[b] : nullptr);
+    HIPCHK(hipMemcpy(p->desc, desc.data(), desc.size(), hipMemcpyHostToDevice));
     return GENINV_OK;
 }
 

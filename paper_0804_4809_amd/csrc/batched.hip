@@ -410,6 +410,7 @@ __device__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
 
 struct BatchDesc {
     const float *G; const float *F; double *W;
+    int *piv;            // optional: kept column indices (r of them), or null
     int m, n, ldg, ldf, ldw;
     int pad;
 };
@@ -469,6 +470,8 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
                       : (A == Lg && fr_nb == 4) ? block_frchol_blocked<4>(A, lda, n, tol, cols, &ints[1], big)
                                                 : block_frchol(A, lda, n, tol, cols, &ints[1]);
         if (tid == 0) rank[b] = r;
+        if (d.piv)
+            for (int c = tid; c < r; c += BT_THREADS) d.piv[c] = cols[c];
         if (r == 0) {
             for (int e = tid; e < n * k; e += BT_THREADS) d.W[(e % n) + (long)(e / n) * d.ldw] = 0.0;
             __syncthreads();
@@ -550,8 +553,11 @@ size_t batched_desc_bytes() { return sizeof(BatchDesc); }
 void batched_fill_desc(void *out, const float *G, const float *F, double *W, int m, int n, int ldg, int ldf, int ldw) {
     BatchDesc *d = static_cast<BatchDesc *>(out);
     d->G = G; d->F = F; d->W = W;
+    d->piv = nullptr;
     d->m = m; d->n = n; d->ldg = ldg; d->ldf = ldf; d->ldw = ldw;
     d->pad = 0;
 }
+
+void batched_set_piv(void *desc, int b, int *piv) { static_cast<BatchDesc *>(desc)[b].piv = piv; }
 
 }  // namespace geninv

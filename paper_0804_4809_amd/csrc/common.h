@@ -99,6 +99,11 @@ hipError_t launch_mirror_lower(double *X, long ldx, Dim n, hipStream_t s);
 hipError_t launch_axpby(const double *X, long ldx, double *Yp, long ldy, Dim rows, Dim cols, double a, double b,
                         hipStream_t s);   // Y = a X + b Y
 hipError_t launch_transpose(const double *X, long ldx, double *Yp, long ldy, int rows, int cols, hipStream_t s);
+hipError_t launch_probe_fill(double *X, long ldx, int rows, int cols, unsigned long long seed, hipStream_t s);
+hipError_t launch_diff_fro2(const double *X, long ldx, const double *Yp, long ldy, int rows, int cols, double *out,
+                            hipStream_t s);   // out[0] += ||X - Y||_F^2, out[1] += ||Y||_F^2
+hipError_t launch_kappa(const double *diag, const double *dvals, const int *piv, const int *rank, int n, double *out,
+                        hipStream_t s);  // out[0] = max diag / min accepted pivot
 
 // full-rank Cholesky (frchol.hip)
 constexpr int FR_NB = 64;          // panel width
@@ -127,6 +132,53 @@ long sliced_tiles(int M, int N, int lower);   // workgroups of one sliced-GEMM s
 // weight classes of the chain's truncated pair set (t + u <= S)
 constexpr int sliced_chain_classes(int S) { return S + 1 < 2 * S - 1 ? S + 1 : 2 * S - 1; }
 
+// int8 modular product engine (modular.hip)
+constexpr int MOD_MAX = 16;     // moduli (their product must fit 128 bits)
+struct ModConsts {
+    int n;                      // number of moduli
+    int p[MOD_MAX];             // the moduli, pairwise coprime, <= 255
+    int y[MOD_MAX];             // (M / p_l)^-1 mod p_l
+    double pf[MOD_MAX], invp[MOD_MAX];
+    double w1[MOD_MAX], w2[MOD_MAX], w3[MOD_MAX];   // M / p_l in three exact float64 pieces
+    double m1, m2, m3;                              // M likewise
+    double log2M;
+};
+struct ModGemmArgs {
+    const int8_t *A; long lda; long sa;   // opA(i, k) = A[l sa + k + i lda]  (int8 residue planes)
+    const int8_t *B; long ldb; long sb;   // opB(k, j) = B[l sb + k + j ldb]
+    int M, N, Kpad;                       // Kpad: multiple of 64, zero padded
+    int lower;                            // tiles on or below the diagonal only (M == N)
+    int splitk;                           // K slices (each at most 1024 stages of 64)
+    int8_t *R; long strideR;              // residues: plane (l, z) at R + (l splitk + z) strideR
+    ModConsts mc;
+};
+struct ModRecArgs {
+    const int8_t *R; long strideR;
+    int M, N, lower, splitk, beta;
+    const int *ea; const int *eb;         // row exponents of opA, column exponents of opB
+    double *C; long ldc;
+    ModConsts mc;
+};
+bool mod_consts(int N, ModConsts &mc);
+int mod_beta(const ModConsts &mc, long K);
+long mod_tiles(int M, int N, int lower);
+int mod_min_splits(int Kpad);
+size_t mod_residue_bytes(int M, int N, int lower);   // bytes of one residue plane
+hipError_t launch_mod_slice_cols(const double *X, long ldx, int rows, int cols, const int *e, int beta,
+                                 const ModConsts &mc, int8_t *planes, long ldp, long sp, hipStream_t s);
+hipError_t launch_mod_slice_rows_t(const double *X, long ldx, int rows, int cols, const int *e, int beta,
+                                   const ModConsts &mc, int8_t *planes, long ldp, long sp, hipStream_t s);
+hipError_t launch_mod_gemm(const ModGemmArgs &a, hipStream_t s);
+hipError_t launch_mod_reconstruct(const ModRecArgs &a, hipStream_t s);
+
+// incremental factorization (incremental.hip)
+hipError_t launch_gather_rows(const double *X, long ldx, const int *idx, int r, int cols, double *out, long ldo,
+                              hipStream_t s);
+hipError_t launch_gather_cols_t(const double *X, long ldx, int row0, const int *idx, int r, int p, double *out,
+                                long ldo, hipStream_t s);
+hipError_t launch_offset_int(const int *src, int n, int off, int *dst, hipStream_t s);
+hipError_t launch_trinv64(const double *T, long ldt, int r, double *Dinv, hipStream_t s);
+
 // batched least squares (batched.hip)
 constexpr int BATCH_NMAX = 256;
 constexpr int BATCH_KMAX = 16;
@@ -136,5 +188,6 @@ size_t batched_lds_bytes(int nl, int nmax, int k);
 size_t batched_slab_doubles(int nmax, int k);
 size_t batched_desc_bytes();
 void batched_fill_desc(void *out, const float *G, const float *F, double *W, int m, int n, int ldg, int ldf, int ldw);
+void batched_set_piv(void *desc, int b, int *piv);   // on a host copy of the descriptors
 
 }  // namespace geninv

@@ -24,6 +24,8 @@ transpose-copy them.
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -97,13 +99,28 @@ def rbf_design(m: int, dim: int, n_unique: int, n_dup: int, sigma: float, seed: 
     n = C.shape[0]
     G = np.empty((m, n), dtype=np.float64)
     inv2s2 = 1.0 / (2.0 * sigma * sigma)
-    for r0 in range(0, m, chunk_rows):
+
+    def rows(r0):
         r1 = min(m, r0 + chunk_rows)
         d2 = np.zeros((r1 - r0, n), dtype=np.float64)
+        diff = np.empty_like(d2)
         for t in range(dim):
-            diff = X[r0:r1, t][:, None] - C[:, t][None, :]
-            d2 += diff * diff
-        np.exp(-d2 * inv2s2, out=G[r0:r1])
+            np.subtract(X[r0:r1, t][:, None], C[:, t][None, :], out=diff)
+            np.multiply(diff, diff, out=diff)
+            d2 += diff
+        np.multiply(d2, -inv2s2, out=d2)
+        np.exp(d2, out=G[r0:r1])
+
+    # row blocks are independent and NumPy releases the GIL inside ufuncs;
+    # the values do not depend on the number of threads
+    starts = range(0, m, chunk_rows)
+    workers = max(1, min(16, os.cpu_count() or 1, len(starts)))
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(rows, starts))
+    else:
+        for r0 in starts:
+            rows(r0)
     F = g.standard_normal((m, k)) if k > 0 else None
     return G, F, idx
 

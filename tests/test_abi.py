@@ -68,14 +68,30 @@ def test_create_rejects_null_handle_and_bad_device(lib):
 
 
 def test_workspace_query(lib):
-    assert lib.geninv_workspace_bytes(0, 5, 0) == 0
-    small = lib.geninv_workspace_bytes(200, 50, 3)
-    big = lib.geninv_workspace_bytes(8192, 2048, 8)
+    FP64, BF16, INT8 = 0, 1, 2
+    assert lib.geninv_workspace_bytes(0, 5, 0, FP64, 0, 0, 0) == 0
+    small = lib.geninv_workspace_bytes(200, 50, 3, FP64, 0, 0, 0)
+    big = lib.geninv_workspace_bytes(8192, 2048, 8, FP64, 0, 0, 0)
     assert 0 < small < big
     # four n x n float64 slots dominate
     assert big >= 4 * 2048 * 2048 * 8
     # transposed problems factor the smaller dimension
-    assert lib.geninv_workspace_bytes(50, 200, 0) == lib.geninv_workspace_bytes(200, 50, 0)
+    assert lib.geninv_workspace_bytes(50, 200, 0, FP64, 0, 0, 0) == lib.geninv_workspace_bytes(200, 50, 0, FP64,
+                                                                                                0, 0, 0)
+    # the mixed forms add their operand planes: 4 bfloat16 slices of G (8 bytes
+    # per element), or 16 int8 residues (16 bytes per element)
+    m, n = 32768, 4096
+    base = lib.geninv_workspace_bytes(m, n, 0, FP64, 0, 0, 0)
+    bf = lib.geninv_workspace_bytes(m, n, 0, BF16, 4, 4, 0)
+    i8 = lib.geninv_workspace_bytes(m, n, 0, INT8, 16, 16, 0)
+    assert bf >= base + 2 * 4 * m * n
+    assert i8 >= base + 16 * m * n
+    # the Newton-Schulz steps work in the float64 slots
+    assert lib.geninv_workspace_bytes(m, n, 0, INT8, 16, 16, 2) == i8
+    # invalid digits or precision
+    assert lib.geninv_workspace_bytes(m, n, 0, BF16, 5, 4, 0) == 0
+    assert lib.geninv_workspace_bytes(m, n, 0, INT8, 17, 16, 0) == 0
+    assert lib.geninv_workspace_bytes(m, n, 0, 7, 4, 4, 0) == 0
 
 
 def test_python_api_refuses_cpu_tensors():

@@ -1,0 +1,194 @@
+"""GPU parity of the int8 modular product engine and of the mixed form on it.
+
+* geninv_mgemm against oracle.crt_ref.crt_product (the exact product of the
+  integer representations, rounded once): elementwise within the
+  reconstruction's rounding (3 u |C| plus an absolute term far below the
+  representation error), on ragged shapes, every transposition, several
+  moduli counts, the shared-operand Gram path (lower triangle), and depths
+  that force split-K slices;
+* the whole mixed method with GENINV_MIXED_INT8 against the float64 oracle:
+  at 16 moduli the products are float64-accurate and the float64 tolerance
+  (1e-10) applies; with fewer moduli the mixed tolerance (1e-6); decisions
+  identical to the oracle's; the transpose branch; the error estimate and
+  the EACCURACY refusal on an ill-conditioned RBF design.
+"""
+import numpy as np
+import pytest
+
+from oracle import crt_ref as crt
+from oracle import geninv_ref as o
+from paper_0804_4809_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_0804_4809_amd import api  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+U = np.finfo(np.float64).eps / 2
+
+
+def up(X):
+    return torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(DEV)
+
+
+def down(T):
+    torch.cuda.synchronize()
+    return T.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(label, **kw):
+    print(f"[case] {label} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _bound(C, beta, ea, eb, N):
+    # reconstruction error: 2 u |X| from the two final additions, plus the
+    # rounding of the third float64 piece, below 2^(E - 110) in units of the
+    # integer sum (E = bit length of the moduli's product)
+    E = crt.modulus_product(N).bit_length()
+    unit = np.ldexp(1.0, (np.asarray(ea)[:, None] + np.asarray(eb)[None, :] - 2 * beta))
+    return 3 * U * np.abs(C) + unit * 2.0 ** (E - 110)
+
+
+@pytest.mark.parametrize("M,N,K,tA,tB,nmod", [
+    (200, 150, 300, 0, 0, 16), (200, 150, 300, 1, 0, 16), (200, 150, 300, 0, 1, 16), (200, 150, 300, 1, 1, 16),
+    (129, 257, 65, 1, 0, 12), (1, 1, 1, 0, 0, 8), (300, 5, 2000, 1, 0, 14), (64, 64, 64, 0, 1, 16),
+    (513, 385, 777, 0, 1, 10),
+])
+def test_mgemm_matches_exact_representation_product(M, N, K, tA, tB, nmod):
+    _case("mgemm", M=M, N=N, K=K, tA=tA, tB=tB, moduli=nmod)
+    rng = np.random.default_rng(M + 3 * N + 7 * K + nmod)
+    # rows/columns of very different scales, with zeros and tiny entries
+    A = rng.standard_normal((M, K)) * np.exp(rng.uniform(-8, 8, size=(M, 1)))
+    B = rng.standard_normal((K, N)) * np.exp(rng.uniform(-8, 8, size=(1, N)))
+    A[0, : K // 3] = 0.0
+    B[: K // 2, -1] *= 1e-30
+    ref, beta, ea, eb = crt.crt_product(A, B, nmod)
+    C = down(api.mgemm(up(A.T if tA else A), up(B.T if tB else B), bool(tA), bool(tB), moduli=nmod))
+    bound = _bound(ref, beta, ea, eb, nmod)
+    bad = np.abs(C - ref) > bound
+    assert not bad.any(), (np.argwhere(bad)[:5], C[bad][:5], ref[bad][:5])
+
+
+@pytest.mark.parametrize("m,n,nmod", [(1000, 300, 16), (70000, 96, 16), (2049, 1500, 12)])
+def test_mgemm_gram_lower_triangle(m, n, nmod):
+    """G'G through the shared-operand path (lower triangle only); 70000 rows
+    force split-K slices (at most 65536 products per slice)."""
+    _case("mgemm gram", m=m, n=n, moduli=nmod)
+    rng = np.random.default_rng(m + n)
+    G = rng.standard_normal((m, n)) * np.exp(rng.uniform(-3, 3, size=(1, n)))
+    Gd = up(G)
+    A = down(api.mgemm(Gd, Gd, True, False, moduli=nmod, lower=True))
+    sub = slice(0, min(n, 300))
+    ref, beta, e = crt.crt_gram(G[:, sub] if m <= 2100 else G[:, :64], nmod)
+    k = ref.shape[0]
+    got = A[:k, :k]
+    low = np.tril(np.ones((k, k), bool))
+    bound = _bound(ref, beta, e, e, nmod)
+    assert np.all(np.abs(got - ref)[low] <= bound[low])
+    assert not np.triu(A, 1).any()      # nothing written above the diagonal
+
+
+def test_mgemm_int8_16_moduli_is_float64_accurate():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((300, 500))
+    B = rng.standard_normal((500, 200))
+    C = down(api.mgemm(up(A), up(B), moduli=16))
+    ref = (A.astype(np.longdouble) @ B.astype(np.longdouble)).astype(np.float64)
+    assert np.max(np.abs(C - ref) / (np.abs(A) @ np.abs(B))) <= 4 * U
+
+
+def test_mgemm_rejects_too_few_moduli_for_the_depth():
+    with pytest.raises(api.GeninvError) as e:
+        api.mgemm(up(np.ones((4, 300))), up(np.ones((300, 4))), moduli=1)
+    assert e.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# whole mixed method on the int8 engine
+# ---------------------------------------------------------------------------
+def _mixed(G, **kw):
+    return api.mixed(up(G), engine="int8", return_result=True, **kw)
+
+
+def test_mixed_int8_c1_float64_tolerance():
+    _case("mixed int8", cfg="c1")
+    G, _ = w.c1_problem(0)
+    ref = o.geninv(G)
+    res = _mixed(G, gram_digits=16, chain_digits=16)
+    assert res.rank == ref.rank == 40
+    assert np.array_equal(down(res.piv).astype(np.int64), ref.piv)
+    assert o.rel_fro(down(res.Y), ref.Y) <= 1e-10
+    assert res.err_est <= 1e-10
+
+
+@pytest.mark.parametrize("gd,cd,ns,tol", [(16, 16, 0, 1e-6), (12, 12, 0, 1e-6), (16, 0, 0, 1e-6), (16, 16, 2, 1e-6)])
+def test_mixed_int8_svd_family(gd, cd, ns, tol):
+    """G = P diag(s) Q', 8192 x 1024, rank 768, s in [1e-3, 1]."""
+    _case("mixed int8", cfg="svd 8192x1024 r768", gd=gd, cd=cd, ns=ns)
+    G, _, P, sv, Q = w.svd_family(8192, 1024, 768, 1e-3, seed=2)
+    ref = o.geninv(G)
+    res = _mixed(G, gram_digits=gd, chain_digits=cd, ns_steps=ns)
+    Yg = down(res.Y)
+    err = o.rel_fro(Yg, ref.Y)
+    print(f"  rank {res.rank}; relF(Y) vs oracle {err:.3e}; vs closed form {o.rel_fro(Yg, (Q / sv) @ P.T):.3e}; "
+          f"err_est {res.err_est:.3e}", flush=True)
+    assert res.rank == ref.rank == 768
+    assert np.array_equal(down(res.piv).astype(np.int64), ref.piv)
+    assert err <= tol
+    # the estimate is a first-order bound: not below the error against the
+    # oracle by more than the oracle's own distance from the closed form,
+    # and small enough to accept the result at a 1e-4 target
+    assert res.err_est >= err / 10 - o.rel_fro(ref.Y, (Q / sv) @ P.T)
+    assert res.err_est <= 1e-4
+
+
+@pytest.mark.parametrize("m,n,r", [(3001, 517, 300), (300, 900, 200), (2000, 2000, 1500)])
+def test_mixed_int8_lowrank_shapes(m, n, r):
+    """Ragged, wide (the transpose branch) and square exact-rank inputs at 16 moduli."""
+    _case("mixed int8", m=m, n=n, r=r)
+    G, _ = w.lowrank_uv(m, n, r, seed=m + n)
+    ref = o.geninv(G)
+    res = _mixed(G, gram_digits=16, chain_digits=16)
+    err = o.rel_fro(down(res.Y), ref.Y)
+    print(f"  rank {res.rank}; relF(Y) {err:.3e}; err_est {res.err_est:.3e}", flush=True)
+    assert res.rank == ref.rank == r
+    assert np.array_equal(down(res.piv).astype(np.int64), ref.piv)
+    assert err <= max(1e-10, 10 * o.self_spread(G, base=ref))
+
+
+def test_mixed_ill_conditioned_rbf_meets_float64_quality_or_refuses():
+    """The RBF design of 8192 inputs in [0,1]^4 with 2048 centers (256
+    duplicates, sigma 0.3; smallest accepted pivot about 1e-10 of the largest
+    Gram diagonal): the int8 form at 16 moduli reaches the float64 method's
+    quality (same decisions or a rounding-band replay, least-squares residual
+    within 1 % of the oracle's, Y within 10x the oracle's own rounding
+    spread) and its error estimate stays below 1e-4; the 32-bit bfloat16
+    form's chain product cannot carry this conditioning, its estimate says
+    so and a 1e-4 target is refused."""
+    from parity_rules import decisions_or_replay
+    _case("mixed rbf", m=8192, n=2048)
+    G, F, _ = w.c2_problem()
+    ref0 = o.geninv(G)
+    res = _mixed(G, gram_digits=16, chain_digits=16, target=1e-4)
+    assert res.status == 0
+    ref, amb = decisions_or_replay(G, ref0, down(res.piv).astype(np.int64))
+    forced = np.isin(np.arange(G.shape[1]), down(res.piv)) if amb else None
+    Yg = down(res.Y)
+    spread = o.self_spread(G, base=ref, forced=forced)
+    err = o.rel_fro(Yg, ref.Y)
+    ls_o = np.linalg.norm(G @ (ref.Y @ F) - F) / np.linalg.norm(F)
+    ls_g = np.linalg.norm(G @ (Yg @ F) - F) / np.linalg.norm(F)
+    print(f"  int8: rank {res.rank}; relF(Y) {err:.3e} (oracle spread {spread:.3e}); LS residual {ls_g:.6f} vs "
+          f"oracle {ls_o:.6f}; err_est {res.err_est:.3e}", flush=True)
+    assert err <= 10 * spread
+    assert abs(ls_g - ls_o) <= 0.01 * ls_o
+    bf = api.mixed(up(G), engine="bf16", gram_digits=4, chain_digits=4, target=1e-4, return_result=True)
+    Yb = down(bf.Y)
+    ls_b = np.linalg.norm(G @ (Yb @ F) - F) / np.linalg.norm(F)
+    print(f"  bf16 s=4: status {bf.status}, err_est {bf.err_est:.3e}, relF(Y) {o.rel_fro(Yb, ref0.Y):.3e}, "
+          f"LS residual {ls_b:.6f}", flush=True)
+    assert bf.status == -7 and bf.err_est > 1e-4

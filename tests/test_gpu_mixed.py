@@ -130,7 +130,8 @@ def test_mixed_c1_matches_oracle():
     _case("mixed", cfg="c1")
     G, F = w.c1_problem(0)
     ref = o.geninv(G)
-    Y, r, piv = api.mixed(up(G), return_piv=True)
+    res = api.mixed(up(G), engine="bf16", gram_digits=4, chain_digits=4, return_result=True)
+    Y, r, piv = res.Y, res.rank, res.piv
     assert r == ref.rank
     assert np.array_equal(down(piv).astype(np.int64), ref.piv)
     assert o.rel_fro(down(Y), ref.Y) <= MIXED_TOL
@@ -143,7 +144,8 @@ def test_mixed_svd_family(chain_slices, ns):
     _case("mixed", cfg="svd 8192x1024 r768", chain_slices=chain_slices, ns=ns)
     G, _, P, sv, Q = w.svd_family(8192, 1024, 768, 1e-3, seed=2)
     ref = o.geninv(G)
-    Y, r, piv = api.mixed(up(G), chain_slices=chain_slices, ns_steps=ns, return_piv=True)
+    res = api.mixed(up(G), engine="bf16", gram_digits=4, chain_digits=chain_slices, ns_steps=ns, return_result=True)
+    Y, r, piv = res.Y, res.rank, res.piv
     Yg = down(Y)
     err = o.rel_fro(Yg, ref.Y)
     print(f"  rank gpu {r} oracle {ref.rank}; relF(Y) vs oracle {err:.3e}; "
@@ -169,7 +171,9 @@ def test_mixed_more_shapes(kind, m, n, r, slices, chain_slices, ns):
     else:
         G = w.svd_family(m, n, r, 0.5, seed=m + n)[0]
     ref = o.geninv(G)
-    Y, rg, piv = api.mixed(up(G), slices=slices, chain_slices=chain_slices, ns_steps=ns, return_piv=True)
+    res = api.mixed(up(G), engine="bf16", gram_digits=slices, chain_digits=chain_slices, ns_steps=ns,
+                    return_result=True)
+    Y, rg, piv = res.Y, res.rank, res.piv
     err = o.rel_fro(down(Y), ref.Y)
     # 4 chain slices: the 1e-6 target.  3 chain slices represent P and G with
     # 24 bits: an entry of Y = P G' (n terms of random sign) then carries
@@ -181,8 +185,21 @@ def test_mixed_more_shapes(kind, m, n, r, slices, chain_slices, ns):
     assert err <= tol
 
 
-def test_mixed_rejects_wide_input():
-    G = up(np.ones((3, 5)))
-    with pytest.raises(api.GeninvError) as e:
-        api.mixed(G)
-    assert e.value.status == -6
+def test_mixed_transpose_branch():
+    """m < n: the Appendix's transpose branch, G G' factored and Y = G' P."""
+    _case("mixed", cfg="wide 300 x 900, rank 200", engine="bf16")
+    G, _ = w.lowrank_uv(300, 900, 200, seed=77)
+    ref = o.geninv(G)
+    res = api.mixed(up(G), engine="bf16", gram_digits=4, chain_digits=4, return_result=True)
+    assert res.rank == ref.rank == 200
+    assert np.array_equal(down(res.piv).astype(np.int64), ref.piv)
+    assert o.rel_fro(down(res.Y), ref.Y) <= MIXED_TOL
+
+
+def test_mixed_rejects_bad_digits():
+    G = up(np.ones((5, 3)))
+    for kw in (dict(engine="bf16", gram_digits=5), dict(engine="bf16", gram_digits=0),
+               dict(engine="int8", gram_digits=17), dict(engine="int8", chain_digits=-1)):
+        with pytest.raises(api.GeninvError) as e:
+            api.mixed(G, **kw)
+        assert e.value.status == -1

@@ -22,6 +22,7 @@ import pytest
 
 from oracle import geninv_ref as o
 from paper_0804_4809_amd import workloads as w
+from parity_rules import _mask, decisions_or_replay  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -88,34 +89,6 @@ def test_gram_parity(m, n):
     assert o.rel_fro(A, ref) <= 1e-14 * np.sqrt(m)
     Al = down(api.gram(up(G), full=False))
     assert np.array_equal(np.tril(Al), np.tril(A))
-
-
-def _mask(piv, n):
-    a = np.zeros(n, bool)
-    a[np.asarray(piv, dtype=np.int64)] = True
-    return a
-
-
-def decisions_or_replay(G, ref, piv_gpu, tol=None):
-    """Oracle result to compare with: ref itself when the GPU took the same
-    decisions, else the oracle replayed with the GPU's decisions after
-    checking that every difference is a legitimate rounding-band case.
-    Returns (result, number of ambiguous decisions)."""
-    n = ref.A.shape[0]
-    acc_o = _mask(ref.piv, n)
-    acc_g = _mask(piv_gpu, n)
-    if np.array_equal(acc_o, acc_g):
-        return ref, 0
-    band = o.ambiguity_band(ref.A, ref.tol, acc_o)
-    k = int(np.nonzero(acc_o != acc_g)[0][0])
-    print(f"  ambiguous decision at column {k}: oracle d/tol={ref.d[k] / ref.tol:.6f}, band={band[k]:.3e}",
-          flush=True)
-    assert abs(ref.d[k] / ref.tol - 1.0) <= band[k]
-    rep = o.geninv(G, tol, forced=acc_g)
-    band = np.maximum(band, o.ambiguity_band(rep.A, rep.tol, acc_g))
-    consistent = ((rep.d > rep.tol) == acc_g) | (np.abs(rep.d / rep.tol - 1.0) <= band)
-    assert consistent.all(), np.nonzero(~consistent)[0][:10]
-    return rep, int((acc_o != acc_g).sum())
 
 
 def _frchol_case(G):
@@ -320,7 +293,9 @@ def test_lstsq_c1():
     assert o.rel_fro(down(W), Wr) <= FP64_TOL
 
 
-@pytest.mark.parametrize("m,n,k,r", [(3000, 257, 5, 180), (700, 64, 1, 64), (9000, 130, 16, 100)])
+@pytest.mark.parametrize("m,n,k,r", [(3000, 257, 5, 180), (700, 64, 1, 64), (9000, 130, 16, 100),
+                                     # the transpose branch (m < n): G G' factored, W = G' L M M L' F
+                                     (200, 700, 3, 150), (64, 2000, 8, 64), (333, 334, 2, 333)])
 def test_lstsq_ragged(m, n, k, r):
     _print_case("lstsq", m=m, n=n, k=k, r=r)
     G, F = w.lowrank_uv(m, n, r, seed=m + k, k=k)
