@@ -715,6 +715,9 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle checks of the other forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for hardware byte counters) and exit")
+    ap.add_argument("--only-mixed", metavar="KEY",
+                    help="only run one mixed-form variant (e.g. int8_m16) on the headline workload `steps` "
+                         "times and exit (for hardware counter runs)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -749,6 +752,15 @@ def main():
     m, n, k = step.m, step.n, step.k
     del G, F
     print(f"[bench] {tag} generated in {gen_s:.1f} s, uploaded", file=sys.stderr, flush=True)
+    if args.only_mixed:
+        variant = {v[0]: v for v in MIXED_C5 + MIXED_C3}[args.only_mixed]
+        Ymx = api.empty_colmajor(n, m, dev)
+        for _ in range(args.warmup):
+            _mixed_call(lib, step.ctx, m, n, step.Gd, m, Ymx, variant)
+        t = _timed(lambda: _mixed_call(lib, step.ctx, m, n, step.Gd, m, Ymx, variant), args.steps,
+                   torch.cuda.synchronize)
+        print(json.dumps({"workload": desc, "variant": variant, "ms": round(t, 3), "steps": args.steps}), flush=True)
+        return
     rep, roofline, breakdown, _ = measure_fp64(lib, step, args.steps, args.warmup, torch, tag)
     print(f"[bench] {tag} float64: {rep['ms_per_step']} ms/step", file=sys.stderr, flush=True)
 

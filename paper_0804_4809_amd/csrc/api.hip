@@ -517,7 +517,7 @@ int run_sliced(geninv_ctx *c, SlicedGemmArgs g, double *part, size_t part_elems)
 // depth K): int8 residue planes of both operands (shared for a Gram matrix),
 // their exponents, and the residue planes of the result.
 struct ModPlan {
-    int M = 0, N = 0, K = 0, Kpad = 0, beta = -1, splitk = 1, lower = 0;
+    int M = 0, N = 0, K = 0, Kpad = 0, beta = -1, splitk = 1, lower = 0, cfg = 0;
     bool same = false;
     long sa = 0, sb = 0, strideR = 0;
     size_t pa = 0, pb = 0, ea = 0, eb = 0, res = 0, total = 0;
@@ -532,12 +532,17 @@ ModPlan mod_plan(size_t base, int M, int N, int K, const ModConsts &mc, bool sam
     P.same = same;
     P.Kpad = (int)pad64(std::max(K, 1));
     P.beta = mod_beta(mc, K);
-    // split K when the tiles of all moduli leave the compute units short
-    // (about three workgroups each), keeping at least 16 stages per slice
-    const long tiles = mod_tiles(M, N, lower);
+    // 256 x 256 tiles (one workgroup per compute unit) when they give every
+    // compute unit at least two rounds, else 128 x 128 (three per compute
+    // unit); K split when the tiles of all moduli still leave the compute
+    // units short, keeping at least 16 stages per slice
     const int nst = P.Kpad / 64;
-    int S = mod_min_splits(P.Kpad);
-    while (S < 16 && tiles * mc.n * S < 768 && nst / (S + 1) >= 16) ++S;
+    const int S0 = mod_min_splits(P.Kpad);
+    P.cfg = mod_tiles(M, N, lower, 1) * mc.n * S0 >= 512 ? 1 : 0;
+    const long tiles = mod_tiles(M, N, lower, P.cfg);
+    const long target = P.cfg ? 512 : 768;
+    int S = S0;
+    while (S < 16 && tiles * mc.n * S < target && nst / (S + 1) >= 16) ++S;
     P.splitk = S;
     size_t off = base;
     auto take = [&](size_t bytes) {
@@ -551,7 +556,7 @@ ModPlan mod_plan(size_t base, int M, int N, int K, const ModConsts &mc, bool sam
     P.pb = same ? P.pa : take((size_t)mc.n * P.sb);
     P.ea = take((size_t)std::max(M, 1) * sizeof(int));
     P.eb = same ? P.ea : take((size_t)std::max(N, 1) * sizeof(int));
-    P.strideR = (long)mod_residue_bytes(M, N, lower);
+    P.strideR = (long)mod_residue_bytes(M, N, lower, P.cfg);
     P.res = take((size_t)mc.n * S * P.strideR);
     P.total = off;
     return P;
@@ -589,13 +594,14 @@ int run_mod_product(geninv_ctx *c, const ModPlan &P, const ModConsts &mc, int tr
     g.B = pb; g.ldb = P.Kpad; g.sb = P.sb;
     g.M = P.M; g.N = P.N; g.Kpad = P.Kpad;
     g.lower = P.lower;
+    g.cfg = P.cfg;
     g.splitk = P.splitk;
     g.R = res; g.strideR = P.strideR;
     g.mc = mc;
     HIPCHK(launch_mod_gemm(g, c->stream));
     ModRecArgs r{};
     r.R = res; r.strideR = P.strideR;
-    r.M = P.M; r.N = P.N; r.lower = P.lower; r.splitk = P.splitk; r.beta = P.beta;
+    r.M = P.M; r.N = P.N; r.lower = P.lower; r.cfg = P.cfg; r.splitk = P.splitk; r.beta = P.beta;
     r.ea = ea; r.eb = P.same ? ea : eb;
     r.C = C; r.ldc = ldc;
     r.mc = mc;
@@ -1077,6 +1083,7 @@ int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, 
 }
 
 
+
 // C (M x N, ldc) = op(A) op(B) split over K into `part` when the output is
 // too small to fill the compute units (S partial results, then a reduction)
 static int rows_gemm(geninv_ctx *c, GemmArgs g, double *part, size_t part_elems) {
@@ -1224,7 +1231,7 @@ int geninv_inc_factor(geninv_ctx *c, int n_old, int p, const double *A, int lda,
     const size_t oLp = take(sizeof(double) * r0 * (size_t)r0), oBw = take(sizeof(double) * r0 * (size_t)p),
                  oX = take(sizeof(double) * r0 * (size_t)p), oDi = take(sizeof(double) * 4096 * (size_t)nbk),
                  oS = take(sizeof(double) * p * (size_t)p), oLS = take(sizeof(double) * p * (size_t)p),
-                 oPs = take(sizeof(int) * (size_t)p), oDs = take(sizeof(double) * (size_t)p),
+                 oPs = take(sizeof(int) * (size_t)p), oDs = take(sizeof(double) * 2 * (size_t)p),
                  oZ = take(sizeof(double) * r0 * (size_t)p), oH = take(sizeof(double) * p * (size_t)p),
                  oQ = take(sizeof(double) * r0 * (size_t)p), oB12 = take(sizeof(double) * r0 * (size_t)p),
                  oU = take(sizeof(double) * r0 * (size_t)p), oV = take(sizeof(double) * r0 * (size_t)p),
@@ -1258,12 +1265,20 @@ int geninv_inc_factor(geninv_ctx *c, int n_old, int p, const double *A, int lda,
     CHK(mm(X, r0, 1, X, r0, 0, S, p, p, p, r0, -1.0, 1.0, GEMM_LOWER));
     HIPCHK(launch_fill(L + (long)r0 * ldl, ldl, n_old, p, 0.0, c->stream));   // zeros above the new pivots
     CHK(run_frchol(c, sub, S, p, p, tol_new, LS, p, ps, ds));
-    int rs = 0;
+    // Woodbury's H = I + X' M0 X (Z = M0 X), read back with the new rank
+    CHK(mm(M, ldm, 0, X, r0, 0, Z, r0, r0, p, r0, 1.0, 0.0));
+    HIPCHK(launch_ns_scaled_eye(H, p, p, 1.0, c->stream));
+    CHK(mm(X, r0, 1, Z, r0, 0, H, p, p, p, r0, 1.0, 1.0));
+    std::vector<double> hdiag(p);
+    HIPCHK(launch_copy(H, p + 1, ds + p, 1, hdim(1), hdim(p), c->stream));   // diag(H) behind ds
+    HIPCHK(hipMemcpyAsync(hdiag.data(), ds + p, sizeof(double) * p, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(c->hpin, at<int>(c, sub.rank) + (p + FR_NB - 1) / FR_NB, sizeof(int), hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
-    rs = *c->hpin;
+    const int rs = *c->hpin;
     if (rs < 0 || rs > p) return GENINV_EHIP;
+    double htrace = 0.0;
+    for (double v : hdiag) htrace += v;
     HIPCHK(launch_transpose(X, r0, L + n_old, ldl, r0, p, c->stream));
     if (rs > 0) {
         HIPCHK(launch_copy(LS, p, L + n_old + (long)r0 * ldl, ldl, hdim(p), hdim(rs), c->stream));
@@ -1276,9 +1291,18 @@ int geninv_inc_factor(geninv_ctx *c, int n_old, int p, const double *A, int lda,
     //   B11^-1 = M0 - Z (I + X'Z)^-1 Z'  (Z = M0 X, Woodbury);
     //   with U = B11^-1 B12 and T = LS'LS - B12' U (Schur complement):
     //   M = [B11^-1 + U T^-1 U', -U T^-1; -T^-1 U', T^-1].
-    CHK(mm(M, ldm, 0, X, r0, 0, Z, r0, r0, p, r0, 1.0, 0.0));
-    HIPCHK(launch_ns_scaled_eye(H, p, p, 1.0, c->stream));
-    CHK(mm(X, r0, 1, Z, r0, 0, H, p, p, p, r0, 1.0, 1.0));
+    // Woodbury's subtraction loses about u ||H|| relative: when the new rows
+    // dominate (trace(H) above 2 p + 64, e.g. appended columns that are
+    // combinations of many earlier ones), M is formed from the extended L
+    // directly instead (L'L on the matrix cores and its Gauss-Jordan
+    // inverse, O(r^3)).
+    if (htrace > 2.0 * p + 64.0) {
+        const int r = r0 + rs;
+        CHK(run_factor_inverse(c, full, L, ldl, n, hdim(r), M, ldm));
+        *rank_io = r;
+        *tol_io = tol_new;
+        return geninv_sync_status(c);
+    }
     CHK(run_spdinv(c, sub, H, p, hdim(p)));
     CHK(mm(Z, r0, 0, H, p, 0, Q, r0, r0, p, p, 1.0, 0.0));
     CHK(mm(Q, r0, 0, Z, r0, 1, M, ldm, r0, r0, p, -1.0, 1.0));

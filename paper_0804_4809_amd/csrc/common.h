@@ -148,22 +148,23 @@ struct ModGemmArgs {
     const int8_t *B; long ldb; long sb;   // opB(k, j) = B[l sb + k + j ldb]
     int M, N, Kpad;                       // Kpad: multiple of 64, zero padded
     int lower;                            // tiles on or below the diagonal only (M == N)
+    int cfg;                              // 0: 128 x 128 tiles, 1: 256 x 256 tiles
     int splitk;                           // K slices (each at most 1024 stages of 64)
     int8_t *R; long strideR;              // residues: plane (l, z) at R + (l splitk + z) strideR
     ModConsts mc;
 };
 struct ModRecArgs {
     const int8_t *R; long strideR;
-    int M, N, lower, splitk, beta;
+    int M, N, lower, cfg, splitk, beta;
     const int *ea; const int *eb;         // row exponents of opA, column exponents of opB
     double *C; long ldc;
     ModConsts mc;
 };
 bool mod_consts(int N, ModConsts &mc);
 int mod_beta(const ModConsts &mc, long K);
-long mod_tiles(int M, int N, int lower);
+long mod_tiles(int M, int N, int lower, int cfg);     // workgroups of one modulus and K slice
 int mod_min_splits(int Kpad);
-size_t mod_residue_bytes(int M, int N, int lower);   // bytes of one residue plane
+size_t mod_residue_bytes(int M, int N, int lower, int cfg);   // bytes of one residue plane
 hipError_t launch_mod_slice_cols(const double *X, long ldx, int rows, int cols, const int *e, int beta,
                                  const ModConsts &mc, int8_t *planes, long ldp, long sp, hipStream_t s);
 hipError_t launch_mod_slice_rows_t(const double *X, long ldx, int rows, int cols, const int *e, int beta,

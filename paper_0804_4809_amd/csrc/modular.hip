@@ -25,8 +25,8 @@
 // The GEMM writes each modulus's residues (int8, summed over split-K slices
 // by the reconstruction) in a tile-blocked layout that makes both the GEMM's
 // stores and the reconstruction's loads 256-byte contiguous per wavefront:
-// byte ((t * 16 + g) * 256 + thread) * 4 + v for tile t, block g = 4a + b of
-// the thread's 4 x 4 MFMA blocks and accumulator slot v.
+// byte ((t NG + g) NT + thread) 4 + v for tile t, MFMA block g of the
+// thread's NG blocks, accumulator slot v, NT threads per workgroup.
 #include "common.h"
 
 #include <cmath>
@@ -112,20 +112,25 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 // ---------------------------------------------------------------------------
 // int8 GEMM per modulus
 //
-// A workgroup (4 wavefronts, 2 x 2) owns a 128 x 128 tile of C for one
-// modulus; a wavefront owns 64 x 64 (4 x 4 MFMA blocks of 16 x 16, two
-// matrix-core operations per 16-byte fragment read from LDS).  K is taken
-// 64 at a time: the stage's 256 rows of 64 bytes (A rows, then B rows) go
-// straight from global memory into LDS (global_load_lds_dwordx4, three
-// buffers, loads two stages ahead).  A wavefront's direct load fills a 1 KiB
-// chunk of 16 rows; the four 16-byte granules of row r sit XOR-permuted by
-// (r / 4) mod 4 so that the fragment reads (16 rows, one granule) meet
-// distinct banks.  Every fragment address is "buffer + opaque lane offset +
-// constant", so the compiler keeps the three buffers apart in its wait
-// counts.  The grid is one-dimensional over the tiles (lower triangle only
-// for the Gram matrix), each XCD taking a contiguous run of an order that
-// walks groups of MG_GM tile rows column by column; blockIdx.y is the
-// split-K slice and blockIdx.z the modulus.
+// A workgroup of WM x WN wavefronts owns a TILE x TILE tile of C for one
+// modulus; a wavefront owns (TILE / WM) x (TILE / WN), FA x FB MFMA blocks of
+// 16 x 16 (FA A fragments and FB B fragments per 64-deep stage feed FA FB
+// matrix-core operations).  Two shapes: 128 x 128 with 2 x 2 wavefronts of
+// 64 x 64 (three workgroups per compute unit), and 256 x 256 with 2 x 4
+// wavefronts of 128 x 64 (one per compute unit), which halves the operand
+// bytes each tile pulls from L2 per product (an int8 GEMM at the matrix
+// cores' rate with 128 x 128 tiles would need about 39 TB/s of operands).
+// K is taken 64 at a time: the stage's rows of 64 bytes (TILE A rows, then
+// TILE B rows) go straight from global memory into LDS
+// (global_load_lds_dwordx4, three buffers, loads two stages ahead).  A
+// wavefront's direct load fills a 1 KiB chunk of 16 rows; the four 16-byte
+// granules of row r sit XOR-permuted by (r / 4) mod 4 so that the fragment
+// reads (16 rows, one granule) meet distinct banks.  Every fragment address
+// is "buffer + opaque lane offset + constant", so the compiler keeps the
+// three buffers apart in its wait counts.  The grid is one-dimensional over
+// the tiles (lower triangle only for the Gram matrix), each XCD taking a
+// contiguous run of an order that walks groups of MG_GM tile rows column by
+// column; blockIdx.y is the split-K slice and blockIdx.z the modulus.
 //
 // Operand layout of v_mfma_i32_16x16x64_i8: lane l holds 16 int8 of row
 // l % 16 (A) or column l % 16 (B), the same 16 k for A and B in both, so a
@@ -133,13 +138,25 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 // the stage.  The roles are swapped (the instruction gets the B rows as its
 // A operand), so lane l holds C(row l % 16, column 4 (l / 16) + v).
 // ---------------------------------------------------------------------------
-constexpr int MG_BM = 128, MG_BK = 64, MG_NT = 256, MG_GM = 8;
-constexpr int MG_ROWS = 2 * MG_BM;              // LDS rows per stage: A rows then B rows
-constexpr int MG_STAGE_BYTES = MG_ROWS * MG_BK;  // 16 KiB
+constexpr int MG_BK = 64, MG_GM = 8;
 constexpr int MG_MAX_STAGES = 1024;              // stages per split: sums of 65536 products
 
-__host__ __device__ inline long mg_tiles(int M, int N, int lower) {
-    const long tm = (M + MG_BM - 1) / MG_BM, tn = (N + MG_BM - 1) / MG_BM;
+template <int TILE_, int WM_, int WN_>
+struct MgCfg {
+    static constexpr int TILE = TILE_, WM = WM_, WN = WN_;
+    static constexpr int NT = 64 * WM * WN;
+    static constexpr int FA = TILE / WM / 16, FB = TILE / WN / 16;
+    static constexpr int CHUNKS = 2 * TILE / 16;          // 1 KiB direct-load chunks per stage
+    static constexpr int CPW = CHUNKS / (WM * WN);        // chunks per wavefront
+    static constexpr int STAGE = 2 * TILE * MG_BK;        // LDS bytes per stage
+    static constexpr int NG = FA * FB;                    // groups of 4 outputs per thread
+    static_assert(CHUNKS % (WM * WN) == 0, "chunks per wavefront");
+};
+using MgSmall = MgCfg<128, 2, 2>;
+using MgLarge = MgCfg<256, 2, 4>;
+
+__host__ __device__ inline long mg_tiles(int M, int N, int lower, int tile) {
+    const long tm = (M + tile - 1) / tile, tn = (N + tile - 1) / tile;
     if (!lower) return tm * tn;
     long t = 0;
     for (long r = 0; r < tm; ++r) t += r + 1 < tn ? r + 1 : tn;
@@ -170,12 +187,14 @@ __device__ inline void mg_tile(long t, int tm, int tn, int lower, int &bx, int &
     }
 }
 
-__global__ __launch_bounds__(MG_NT) void mod_gemm_kernel(ModGemmArgs p) {
-    __shared__ __align__(1024) char Ls0[MG_STAGE_BYTES];
-    __shared__ __align__(1024) char Ls1[MG_STAGE_BYTES];
-    __shared__ __align__(1024) char Ls2[MG_STAGE_BYTES];
+template <class CF>
+__global__ __launch_bounds__(CF::NT) void mod_gemm_kernel(ModGemmArgs p) {
+    constexpr int TILE = CF::TILE, NT = CF::NT, FA = CF::FA, FB = CF::FB, CPW = CF::CPW, NWV = CF::WM * CF::WN;
+    __shared__ __align__(1024) char Ls0[CF::STAGE];
+    __shared__ __align__(1024) char Ls1[CF::STAGE];
+    __shared__ __align__(1024) char Ls2[CF::STAGE];
 
-    const int tm = (p.M + MG_BM - 1) / MG_BM, tn = (p.N + MG_BM - 1) / MG_BM;
+    const int tm = (p.M + TILE - 1) / TILE, tn = (p.N + TILE - 1) / TILE;
     long tile;
     {
         // the hardware deals workgroups to the 8 XCDs in turn: give XCD x a
@@ -186,7 +205,7 @@ __global__ __launch_bounds__(MG_NT) void mod_gemm_kernel(ModGemmArgs p) {
     }
     int bx = 0, by = 0;
     mg_tile(tile, tm, tn, p.lower, bx, by);
-    const int row0 = bx * MG_BM, col0 = by * MG_BM;
+    const int row0 = bx * TILE, col0 = by * TILE;
     const int l = blockIdx.z;   // modulus
     const int nst_all = p.Kpad / MG_BK;
     const int per = (nst_all + p.splitk - 1) / p.splitk;
@@ -195,61 +214,63 @@ __global__ __launch_bounds__(MG_NT) void mod_gemm_kernel(ModGemmArgs p) {
     const int8_t *Bb = p.B + (long)l * p.sb;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % CF::WM, wn = wave / CF::WM;
 
-    // Direct loads: chunk q (16 rows; A rows for q < 8, B rows for q >= 8) is
-    // loaded by wavefront q % 4.  Lane l fills row l / 4 of its chunk, slot
-    // l % 4, with granule (l % 4) ^ (l / 16).  Rows past M (N) are read
+    // Direct loads: chunk q (16 rows; A rows for q < TILE / 16, B rows after)
+    // is loaded by wavefront q % NWV.  Lane l fills row l / 4 of its chunk,
+    // slot l % 4, with granule (l % 4) ^ (l / 16).  Rows past M (N) are read
     // clamped: they only reach outputs that are never stored.
-    unsigned srcoff[4];
+    constexpr int ACH = TILE / 16;
+    unsigned srcoff[CPW];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int q = wave + 4 * i;
-        const int r = (q % 8) * 16 + (lane >> 2);
+    for (int i = 0; i < CPW; ++i) {
+        const int q = wave + NWV * i;
+        const int r = (q % ACH) * 16 + (lane >> 2);
         const int g = (lane & 3) ^ (lane >> 4);
-        srcoff[i] = q < 8 ? (unsigned)((long)min(row0 + r, p.M - 1) * p.lda + 16 * g)
-                          : (unsigned)((long)min(col0 + r, p.N - 1) * p.ldb + 16 * g);
+        srcoff[i] = q < ACH ? (unsigned)((long)min(row0 + r, p.M - 1) * p.lda + 16 * g)
+                            : (unsigned)((long)min(col0 + r, p.N - 1) * p.ldb + 16 * g);
     }
     auto dma = [&](int st, char *buf) {
         const long k0 = (long)st * MG_BK;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int q = wave + 4 * i;
-            lds_load16((q < 8 ? Ab : Bb) + k0 + srcoff[i], buf + q * 1024);
+        for (int i = 0; i < CPW; ++i) {
+            const int q = wave + NWV * i;
+            lds_load16((q < ACH ? Ab : Bb) + k0 + srcoff[i], buf + q * 1024);
         }
     };
 
-    i4 acc[4][4];
+    i4 acc[FA][FB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = i4{0, 0, 0, 0};
+        for (int b = 0; b < FB; ++b) acc[a][b] = i4{0, 0, 0, 0};
 
     // lane read offsets: row l % 16 of a 16-row block, granule l / 16
-    int rda = (wm * 64 + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ ((lane >> 2) & 3));
-    int rdb = rda + (MG_BM + wn * 64 - wm * 64) * 64;
+    constexpr int WTM = TILE / CF::WM, WTN = TILE / CF::WN;
+    int rda = (wm * WTM + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ ((lane >> 2) & 3));
+    int rdb = rda + (TILE + wn * WTN - wm * WTM) * 64;
     asm volatile("" : "+v"(rda), "+v"(rdb));
     auto compute = [&](const char *buf) {
-        i4 bf[4];
+        i4 bf[FB];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = *reinterpret_cast<const i4 *>(buf + rdb + b * 16 * 64);
+        for (int b = 0; b < FB; ++b) bf[b] = *reinterpret_cast<const i4 *>(buf + rdb + b * 16 * 64);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a < FA; ++a) {
             const i4 af = *reinterpret_cast<const i4 *>(buf + rda + a * 16 * 64);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[b], af, acc[a][b], 0, 0, 0);
+            for (int b = 0; b < FB; ++b) acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(bf[b], af, acc[a][b], 0, 0, 0);
         }
     };
     auto stage = [&](int st, char *next, const char *cur) {
         dma(min(st + 2, st1 - 1), next);
         compute(cur);
-        wait_vm<4>();    // this wavefront's loads of stage st + 1 landed
+        wait_vm<CPW>();    // this wavefront's loads of stage st + 1 landed
         stage_barrier();
     };
     if (st1 > st0) {
         dma(st0, Ls0);
         dma(min(st0 + 1, st1 - 1), Ls1);
-        wait_vm<4>();
+        wait_vm<CPW>();
         stage_barrier();
         int st = st0;
         for (; st + 3 <= st1; st += 3) {
@@ -263,14 +284,14 @@ __global__ __launch_bounds__(MG_NT) void mod_gemm_kernel(ModGemmArgs p) {
     }
 
     // residues, balanced: |acc| < 2^31 is exact in float64
-    const double pf = p.mc.pf[l], invp = p.mc.invp[l];
+    const double invp = p.mc.invp[l];
     const int pi = p.mc.p[l];
     unsigned *out = reinterpret_cast<unsigned *>(p.R + ((long)l * p.splitk + blockIdx.y) * p.strideR) +
-                    (tile * 16) * MG_NT + tid;
+                    (tile * CF::NG) * NT + tid;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FA; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < FB; ++b) {
             unsigned w = 0;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -281,9 +302,8 @@ __global__ __launch_bounds__(MG_NT) void mod_gemm_kernel(ModGemmArgs p) {
                 r = r < -(pi >> 1) ? r + pi : r;
                 w |= (unsigned)(r & 0xff) << (8 * v);
             }
-            out[(a * 4 + b) * MG_NT] = w;
+            out[(a * FB + b) * NT] = w;
         }
-    (void)pf;
 }
 
 // ---------------------------------------------------------------------------
@@ -297,31 +317,35 @@ __global__ __launch_bounds__(MG_NT) void mod_gemm_kernel(ModGemmArgs p) {
 // 2^(E-80) and below (E = bit length of M): each piece has at most 40 (44)
 // significant bits, so s_l times a piece is exact and so are the sums of the
 // first two pieces over 16 moduli and the subtraction of q M; only the two
-// final additions round (error about 2 u |X|).
+// final additions round (error about 2 u |X|).  Same tile and thread layout
+// as the GEMM that wrote the residues.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(MG_NT) void mod_reconstruct_kernel(ModRecArgs a) {
+template <class CF>
+__global__ __launch_bounds__(CF::NT) void mod_reconstruct_kernel(ModRecArgs a) {
+    constexpr int TILE = CF::TILE, NT = CF::NT, FB = CF::FB;
+    constexpr int WTM = TILE / CF::WM, WTN = TILE / CF::WN;
     const long tile = blockIdx.x;
-    const int tm = (a.M + MG_BM - 1) / MG_BM, tn = (a.N + MG_BM - 1) / MG_BM;
+    const int tm = (a.M + TILE - 1) / TILE, tn = (a.N + TILE - 1) / TILE;
     int bx = 0, by = 0;
     mg_tile(tile, tm, tn, a.lower, bx, by);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % CF::WM, wn = wave / CF::WM;
     const int n = a.mc.n;
-    for (int g = 0; g < 16; ++g) {
-        const int ba = g >> 2, bb = g & 3;
-        const int r = bx * MG_BM + wm * 64 + ba * 16 + (lane & 15);
-        const int c0 = by * MG_BM + wn * 64 + bb * 16 + 4 * (lane >> 4);
+    for (int g = 0; g < CF::NG; ++g) {
+        const int ba = g / FB, bb = g % FB;
+        const int r = bx * TILE + wm * WTM + ba * 16 + (lane & 15);
+        const int c0 = by * TILE + wn * WTN + bb * 16 + 4 * (lane >> 4);
         if (r >= a.M || c0 >= a.N || (a.lower && r < c0)) continue;
         double t[4] = {0, 0, 0, 0}, T1[4] = {0, 0, 0, 0}, T2[4] = {0, 0, 0, 0}, T3[4] = {0, 0, 0, 0};
         for (int l = 0; l < n; ++l) {
             int R[4] = {0, 0, 0, 0};
             for (int z = 0; z < a.splitk; ++z) {
                 const unsigned w = reinterpret_cast<const unsigned *>(a.R + ((long)l * a.splitk + z) * a.strideR)
-                    [(tile * 16 + g) * MG_NT + tid];
+                    [(tile * CF::NG + g) * NT + tid];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) R[v] += (int)(signed char)((w >> (8 * v)) & 0xff);
             }
-            const int pi = a.mc.p[l], y = a.mc.y[l];
+            const int y = a.mc.y[l];
             const double pf = a.mc.pf[l], invp = a.mc.invp[l];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -334,7 +358,6 @@ __global__ __launch_bounds__(MG_NT) void mod_reconstruct_kernel(ModRecArgs a) {
                 T2[v] = fma(s, a.mc.w2[l], T2[v]);
                 T3[v] = fma(s, a.mc.w3[l], T3[v]);
             }
-            (void)pi;
         }
         const int er = a.ea[r];
 #pragma unroll
@@ -371,9 +394,16 @@ hipError_t launch_mod_slice_rows_t(const double *X, long ldx, int rows, int cols
     return hipGetLastError();
 }
 
-long mod_tiles(int M, int N, int lower) { return mg_tiles(M, N, lower); }
+static int mg_tile_of(int cfg) { return cfg ? MgLarge::TILE : MgSmall::TILE; }
+
+long mod_tiles(int M, int N, int lower, int cfg) { return mg_tiles(M, N, lower, mg_tile_of(cfg)); }
 
 int mod_min_splits(int Kpad) { return (Kpad / MG_BK + MG_MAX_STAGES - 1) / MG_MAX_STAGES; }
+
+size_t mod_residue_bytes(int M, int N, int lower, int cfg) {
+    const long t = mg_tile_of(cfg);
+    return (size_t)mg_tiles(M, N, lower, (int)t) * t * t;
+}
 
 hipError_t launch_mod_gemm(const ModGemmArgs &a, hipStream_t s) {
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
@@ -383,18 +413,22 @@ hipError_t launch_mod_gemm(const ModGemmArgs &a, hipStream_t s) {
     // lane offsets into a plane are 32-bit byte counts
     if ((double)(a.M - 1) * a.lda + a.Kpad >= 4294967296.0 || (double)(a.N - 1) * a.ldb + a.Kpad >= 4294967296.0)
         return hipErrorInvalidValue;
-    const long T = mg_tiles(a.M, a.N, a.lower);
-    if (a.strideR < T * MG_STAGE_BYTES) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(mod_gemm_kernel, dim3((unsigned)T, a.splitk, a.mc.n), dim3(MG_NT), 0, s, a);
+    if ((size_t)a.strideR < mod_residue_bytes(a.M, a.N, a.lower, a.cfg)) return hipErrorInvalidValue;
+    const long T = mod_tiles(a.M, a.N, a.lower, a.cfg);
+    if (a.cfg)
+        hipLaunchKernelGGL(mod_gemm_kernel<MgLarge>, dim3((unsigned)T, a.splitk, a.mc.n), dim3(MgLarge::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(mod_gemm_kernel<MgSmall>, dim3((unsigned)T, a.splitk, a.mc.n), dim3(MgSmall::NT), 0, s, a);
     return hipGetLastError();
 }
 
-size_t mod_residue_bytes(int M, int N, int lower) { return (size_t)mg_tiles(M, N, lower) * MG_STAGE_BYTES; }
-
 hipError_t launch_mod_reconstruct(const ModRecArgs &a, hipStream_t s) {
     if (a.M <= 0 || a.N <= 0) return hipSuccess;
-    const long T = mg_tiles(a.M, a.N, a.lower);
-    hipLaunchKernelGGL(mod_reconstruct_kernel, dim3((unsigned)T), dim3(MG_NT), 0, s, a);
+    const long T = mod_tiles(a.M, a.N, a.lower, a.cfg);
+    if (a.cfg)
+        hipLaunchKernelGGL(mod_reconstruct_kernel<MgLarge>, dim3((unsigned)T), dim3(MgLarge::NT), 0, s, a);
+    else
+        hipLaunchKernelGGL(mod_reconstruct_kernel<MgSmall>, dim3((unsigned)T), dim3(MgSmall::NT), 0, s, a);
     return hipGetLastError();
 }
 

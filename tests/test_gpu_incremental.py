@@ -60,7 +60,10 @@ def test_appended_gram_rows_equal_the_gram_matrix(m, steps, k):
 
 @pytest.mark.parametrize("refactor", [False, True])
 @pytest.mark.parametrize("m,n,r,k,steps", [(2000, 300, 200, 4, [100, 120, 80]), (1500, 129, 129, 2, [64, 65]),
-                                           (900, 200, 60, 3, [50, 50, 50, 50]), (3000, 700, 500, 2, [300, 1, 399])])
+                                           (900, 200, 60, 3, [50, 50, 50, 50]), (3000, 700, 500, 2, [300, 1, 399]),
+                                           # 128 appended columns all combinations of the 896 before them: the
+                                           # new rows of L dominate L'L (the direct inverse, not Woodbury)
+                                           (20000, 1024, 896, 2, [896, 128])])
 def test_incremental_lstsq_matches_oracle_after_every_append(m, n, r, k, steps, refactor):
     """W from the appended Gram rows equals the oracle's W = G^+ F on the
     columns seen so far (same pivot columns, relF within the float64 bound)."""

@@ -57,6 +57,7 @@ def _bound(C, beta, ea, eb, N):
     (200, 150, 300, 0, 0, 16), (200, 150, 300, 1, 0, 16), (200, 150, 300, 0, 1, 16), (200, 150, 300, 1, 1, 16),
     (129, 257, 65, 1, 0, 12), (1, 1, 1, 0, 0, 8), (300, 5, 2000, 1, 0, 14), (64, 64, 64, 0, 1, 16),
     (513, 385, 777, 0, 1, 10),
+    (1600, 1300, 130, 1, 1, 16),   # enough 256 x 256 tiles for the large workgroup shape
 ])
 def test_mgemm_matches_exact_representation_product(M, N, K, tA, tB, nmod):
     _case("mgemm", M=M, N=N, K=K, tA=tA, tB=tB, moduli=nmod)
