@@ -54,7 +54,8 @@ typedef enum {
     GENINV_ENONFINITE = -4,  /* G (or its Gram matrix) holds Inf/NaN; r is set to 0 */
     GENINV_ENOTSPD = -5,     /* L'L lost positive definiteness in the inverse */
     GENINV_ENOTSUP = -6,     /* valid request that the library does not support */
-    GENINV_EACCURACY = -7    /* mixed form: outputs written, but the error estimate exceeds the target */
+    GENINV_EACCURACY = -7,   /* mixed form: outputs written, but the error estimate exceeds the target */
+    GENINV_ESCRATCH = -8     /* allocation-free call: the problem needs more than the fixed scratch area */
 } geninv_status;
 
 /* Arithmetic of a whole-method call (geninv_mixed, geninv_workspace_bytes). */
@@ -130,6 +131,25 @@ int geninv_dgeninv(geninv_ctx *ctx, int m, int n, const double *G, int ldg, doub
  * W = G' (L (M (M (L' F)))).  k <= 4096 (ENOTSUP above). */
 int geninv_dlstsq(geninv_ctx *ctx, int m, int n, int k, const double *G, int ldg,
                   const double *F, int ldf, double tol, double *W, int ldw, int *rank);
+
+/* The same least-squares solve for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops): every scratch
+ * buffer of the call (Gram matrix, factor, inverse, split-K partials, rank
+ * and pivots) lives in a fixed device array of geninv_noalloc_capacity()
+ * bytes (256 MiB) that the library holds on each device until the process
+ * ends; the call makes no hipMalloc, hipFree or other allocation (its event
+ * timers are off for the call).  Problems whose workspace
+ * (geninv_workspace_bytes(m, n, k, GENINV_FP64, 0, 0, 0)) exceeds it return
+ * GENINV_ESCRATCH before anything is enqueued: in float64 with k <= 64 that
+ * is about n = min(m, n) <= 1400.  Arguments, results and synchronization
+ * as geninv_dlstsq (the rank read-back by default; see
+ * geninv_set_host_sync).  Every call on one device uses the same array and
+ * keeps the last call's contents: calls that overlap on one device (on
+ * different streams or host threads, with any context) race.  Nothing in
+ * the array needs to start at zero: each call writes every part it reads. */
+int geninv_dlstsq_noalloc(geninv_ctx *ctx, int m, int n, int k, const double *G, int ldg, const double *F, int ldf,
+                          double tol, double *W, int ldw, int *rank);
+size_t geninv_noalloc_capacity(void);
 
 /* ---- individual steps, float64 (same kernels as the whole method) ------- */
 

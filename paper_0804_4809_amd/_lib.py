@@ -21,7 +21,7 @@ _lock = threading.Lock()
 
 GENINV_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONFINITE", -5: "ENOTSPD", -6: "ENOTSUP",
-                -7: "EACCURACY"}
+                -7: "EACCURACY", -8: "ESCRATCH"}
 GENINV_EACCURACY = -7
 # geninv_precision
 GENINV_FP64, GENINV_MIXED_BF16, GENINV_MIXED_INT8 = 0, 1, 2
@@ -50,6 +50,9 @@ _SIGS = [
                                       _VP, ctypes.c_int, _c_int_p, _VP]),
     ("geninv_dlstsq", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
                                      ctypes.c_int, ctypes.c_double, _VP, ctypes.c_int, _c_int_p]),
+    ("geninv_dlstsq_noalloc", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP,
+                                             ctypes.c_int, ctypes.c_double, _VP, ctypes.c_int, _c_int_p]),
+    ("geninv_noalloc_capacity", ctypes.c_size_t, []),
     ("geninv_dgram", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_int, _VP, ctypes.c_int,
                                     ctypes.c_int]),
     ("geninv_dfrchol", ctypes.c_int, [_VP, ctypes.c_int, _VP, ctypes.c_int, ctypes.c_double, _VP, ctypes.c_int,

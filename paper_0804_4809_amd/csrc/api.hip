@@ -4,6 +4,7 @@
 #include <cmath>
 #include <limits>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -41,6 +42,17 @@ hipError_t launch_skinny_gemm(const double *A, long lda, const double *B, long l
                               hipStream_t s);
 }  // namespace geninv
 
+// Fixed device scratch area of geninv_dlstsq_noalloc, for callers that
+// cannot allocate.  Each device holds its own copy from module load until the
+// process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (kept per device in
+// g_scratch and in each context), never through the array's name.
+constexpr size_t NOALLOC_BYTES = size_t(256) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static char *g_scratch[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
 struct geninv_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -49,6 +61,7 @@ struct geninv_ctx {
     int *status = nullptr;     // device status word (separate from the workspace: survives regrowth)
     int host_sync = 1;         // read the rank back after the factorization (geninv_set_host_sync)
     int *hpin = nullptr;       // pinned host word for that read-back
+    char *scratch = nullptr;   // this device's address of the fixed scratch area
     ProfState prof;
 };
 
@@ -421,6 +434,7 @@ int finish_rank(geninv_ctx *c, const int *rdev, int *rank) {
 
 bool bad_ld(long ld, int rows) { return ld < std::max(1, rows); }
 
+
 // ---- mixed precision (sliced bfloat16 products) --------------------------
 
 inline long pad64(long x) { return (x + 63) / 64 * 64; }
@@ -704,6 +718,7 @@ const char *geninv_strerror(int s) {
         case GENINV_ENOTSPD: return "L'L is not positive definite in floating point";
         case GENINV_ENOTSUP: return "not supported by the library";
         case GENINV_EACCURACY: return "result written, but its error estimate exceeds the requested accuracy";
+        case GENINV_ESCRATCH: return "problem needs more device memory than the fixed scratch area holds";
         default: return "unknown status";
     }
 }
@@ -736,6 +751,21 @@ int geninv_create(geninv_ctx **ctx, int device, void *hip_stream) {
         return GENINV_ENOMEM;
     }
     c->hpin = static_cast<int *>(h);
+    if (device < NOALLOC_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[device]) {
+            void *sp = nullptr;
+            if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
+                (void)hipGetLastError();
+                (void)hipHostFree(h);
+                (void)hipFree(p);
+                delete c;
+                return GENINV_EHIP;
+            }
+            g_scratch[device] = static_cast<char *>(sp);
+        }
+        c->scratch = g_scratch[device];
+    }
     *ctx = c;
     return GENINV_OK;
 }
@@ -1020,6 +1050,25 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
 
 namespace {
 
+// Points the context's workspace at the fixed scratch area (and switches
+// the event timers off, which would create events) for one call.
+struct ScratchWorkspace {
+    geninv_ctx *c;
+    char *ws;
+    size_t bytes;
+    unsigned mask;
+    explicit ScratchWorkspace(geninv_ctx *ctx) : c(ctx), ws(ctx->ws), bytes(ctx->ws_bytes), mask(ctx->prof.mask) {
+        c->ws = c->scratch;
+        c->ws_bytes = NOALLOC_BYTES;
+        c->prof.mask = 0;
+    }
+    ~ScratchWorkspace() {
+        c->ws = ws;
+        c->ws_bytes = bytes;
+        c->prof.mask = mask;
+    }
+};
+
 int dlstsq_run(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf, double tol,
                double *W, int ldw, int *rank, bool noalloc) {
     if (!c || m < 0 || n < 0 || k < 0) return GENINV_EINVAL;
@@ -1039,7 +1088,12 @@ int dlstsq_run(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, con
     const bool tr = m < n;              // Appendix: factor G G' when m < n
     const int nn = tr ? m : n;
     const Layout lay = make_layout(nn, k, tr ? n : m);
-    if (!noalloc) CHK(ensure_ws(c, lay.total));
+    if (noalloc) {
+        if (!c->scratch) return GENINV_EHIP;
+        if (lay.total > NOALLOC_BYTES) return GENINV_ESCRATCH;
+    } else {
+        CHK(ensure_ws(c, lay.total));
+    }
     double *A = at<double>(c, lay.slotA);
     double *L = at<double>(c, lay.slotL);
     double *T0 = at<double>(c, lay.t0);
@@ -1080,6 +1134,15 @@ extern "C" {
 int geninv_dlstsq(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf,
                   double tol, double *W, int ldw, int *rank) {
     return dlstsq_run(c, m, n, k, G, ldg, F, ldf, tol, W, ldw, rank, false);
+}
+
+size_t geninv_noalloc_capacity(void) { return NOALLOC_BYTES; }
+
+int geninv_dlstsq_noalloc(geninv_ctx *c, int m, int n, int k, const double *G, int ldg, const double *F, int ldf,
+                          double tol, double *W, int ldw, int *rank) {
+    if (!c) return GENINV_EINVAL;
+    ScratchWorkspace sw(c);
+    return dlstsq_run(c, m, n, k, G, ldg, F, ldf, tol, W, ldw, rank, true);
 }
 
 
