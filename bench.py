@@ -400,13 +400,17 @@ def bench_batched(api, workloads, torch, np, steps, keep_host):
     out["relF_vs_fp64_form_same_rank"] = {"median": float(np.median(rel[same])), "max": float(rel[same].max()),
                                           "above_1e-6": int((rel[same] > 1e-6).sum())}
 
-    del Gs, Fs, Ws
     host = None
     if keep_host:
         rng = np.random.default_rng(0)
         sample = [int(b) for b in rng.choice(len(B.G), size=16, replace=False)]
+        # same-rank problems where the two GPU forms differ by more than
+        # 1e-6: both against the oracle in the oracle leg
+        outl = [int(b) for b in np.nonzero(same & (rel > 1e-6))[0][:16]]
         host = {"B": B, "sample": {b: plan.W(b).cpu().numpy() for b in sample},
+                "outliers": {b: (plan.W(b).cpu().numpy(), Ws[b].cpu().numpy()) for b in outl},
                 "rank_batched": ranks.copy(), "rank_fp64": r64, "differs": [int(b) for b in np.nonzero(~same)[0]]}
+    del Gs, Fs, Ws
     plan.close()
     return out, host
 
@@ -681,6 +685,23 @@ def cpu_oracle_leg(workloads, np, headline_key, flops_fn, c2_host, mixed_host, b
                           "rank_fp64": int(batched_host["rank_fp64"][b]), "rank_oracle": o.geninv(Gb).rank,
                           "rank_oracle_extended_gram": o.geninv(Gb, A=o.gram_extended(Gb)).rank})
         bo["rank_differs_from_fp64_form"] = diffs
+        # same-rank problems where the batched and float64 forms disagree by
+        # more than 1e-6: both forms against the oracle, its own rounding
+        # spread, and the least-squares residuals
+        outl = []
+        for b, (Wg, W64) in batched_host["outliers"].items():
+            Gb = B.G[b].astype(np.float64)
+            Fb = B.F[b].astype(np.float64)
+            ref = o.geninv(Gb)
+            Wr = ref.Y @ Fb
+            nf = float(np.linalg.norm(Fb))
+            outl.append({"problem": b, "m": int(Gb.shape[0]), "n": int(Gb.shape[1]), "rank_oracle": ref.rank,
+                         "relF_batched_vs_oracle": relf(Wg, Wr), "relF_fp64_form_vs_oracle": relf(W64, Wr),
+                         "oracle_self_spread_Y": o.self_spread(Gb, base=ref),
+                         "ls_residual": {"batched": float(np.linalg.norm(Gb @ Wg - Fb)) / nf,
+                                         "fp64_form": float(np.linalg.norm(Gb @ W64 - Fb)) / nf,
+                                         "oracle": float(np.linalg.norm(Gb @ Wr - Fb)) / nf}})
+        bo["same_rank_outliers_vs_oracle"] = outl
     return cpu
 
 
@@ -715,6 +736,9 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle checks of the other forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for hardware byte counters) and exit")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only run the 4096-problem batch `steps` times (direct launches, fixed configuration) "
+                         "and exit (for hardware counter runs)")
     ap.add_argument("--only-mixed", metavar="KEY",
                     help="only run one mixed-form variant (e.g. int8_m16) on the headline workload `steps` "
                          "times and exit (for hardware counter runs)")
@@ -744,6 +768,17 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     tag, desc = WORKLOADS[args.workload]
+    if args.only_batched:
+        B = workloads.c4_problem()
+        plan = api.BatchPlan(B.G, B.F)
+        plan.config(48, 512)
+        for _ in range(args.warmup):
+            plan.run(use_graph=False)
+        t = _timed(lambda: plan.run(use_graph=False), args.steps, torch.cuda.synchronize)
+        print(json.dumps({"workload": "4096 batched problems (C4)", "config": plan.config(), "ms": round(t, 3),
+                          "steps": args.steps}), flush=True)
+        plan.close()
+        return
 
     c0 = time.perf_counter()
     G, F = _generate(workloads, args.workload)

@@ -78,6 +78,27 @@ int geninv_destroy(geninv_ctx *ctx);
 /* Switch the stream later calls enqueue on (same device). */
 int geninv_set_stream(geninv_ctx *ctx, void *hip_stream);
 
+/* Cap on the context's workspace in bytes (0, the default, means none; the
+ * environment variable GENINV_WORKSPACE_LIMIT sets it when the context is
+ * created).  A call that needs a larger workspace returns GENINV_ENOMEM
+ * before anything is enqueued and leaves its outputs untouched; the context
+ * stays usable.  This is the hook through which tests force an allocation
+ * failure; callers can also use it to bound the library's device memory.
+ * EINVAL for a null ctx. */
+int geninv_set_workspace_limit(geninv_ctx *ctx, size_t bytes);
+
+/* Debug aids.  GENINV_DEBUG_POISON: every workspace the context allocates
+ * from then on is filled with a quiet-NaN pattern before its first use (the
+ * environment variable GENINV_DEBUG=1 sets it when the context is created),
+ * so a step that reads memory no earlier step of its call wrote shows up as
+ * NaN in the results.  geninv_debug_poison fills the current workspace with
+ * that pattern now (on the context's stream), e.g. between two calls to
+ * check that a call does not depend on what an earlier one left behind.
+ * EINVAL for a null ctx or unknown flags. */
+enum { GENINV_DEBUG_POISON = 1 };
+int geninv_set_debug(geninv_ctx *ctx, int flags);
+int geninv_debug_poison(geninv_ctx *ctx);
+
 /* Whether a call reads the rank back to the host once its full-rank Cholesky
  * factorization is done (enable != 0, the default) or not (enable == 0).
  * On: one stream synchronization inside geninv_dgeninv, geninv_dlstsq and
@@ -251,7 +272,10 @@ int geninv_dlstsq_gram(geninv_ctx *ctx, int n, int k, const double *A, int lda, 
  * products); the full-rank Cholesky of the new columns' Schur complement
  * A_new - X'X with the same strict test; and M by a block update
  * (Woodbury for L_old'L_old + X X', then the Schur complement of the new
- * kept columns), O(r^2 p) instead of O(r^3).  When the default threshold
+ * kept columns), O(r^2 p) instead of O(r^3); when the appended rows
+ * dominate (trace of I + X' M_old X above 2 p + 64, where the update would
+ * lose accuracy) M is formed directly from the extended L instead.  When
+ * the default threshold
  * falls (a new column with a smaller diagonal) so far that an earlier
  * decision would change, the call refactors all n_old + p columns instead.
  * n_old = 0 factors from scratch.  Synchronizes (reads the new rank). */
@@ -294,24 +318,29 @@ int geninv_factored_lstsq(geninv_ctx *ctx, int n, int r, int k, const double *L,
  *   gram_digits   slices or moduli of the Gram matrix
  *   chain_digits  slices or moduli of Y = P G'; 0 evaluates it in float64
  *   ns_steps   0..16 Newton-Schulz steps X <- X (2I - G X), in the factored
- *              form P <- 2P - P A P (X = P G') with the engine's Gram matrix
- *              A and float64 products; a step is taken only while its
- *              correction ||P A P - P||_F / ||P||_F falls (each step reads
- *              one number back to the host).
+ *              form P <- 2P - P (L L') P (X = P G') with float64 products:
+ *              L L' is the Gram matrix of the columns the factorization
+ *              kept, whose pseudoinverse P is the method's fixed point, so
+ *              the steps remove the rounding of (L'L)^-1, K and P; a step is
+ *              taken only while its correction ||P L L' P - P||_F / ||P||_F
+ *              falls (each step reads one number back to the host).
  *   target     > 0: return GENINV_EACCURACY (outputs still written) when the
  *              error estimate exceeds it; <= 0: no check
  *   err_est    HOST double* or NULL.  When non-NULL or target > 0 the call
- *              estimates the relative error of the result with 16 random
- *              sign probes and float64 products that use the caller's G
- *              (one host synchronization): ||P A P w - P w|| / ||P w|| with
- *              A = G'G applied through G (it sees the engine's
- *              representation error of the Gram matrix and the
- *              factorization's rounding), plus ||Y v - P G' v|| / ||P G' v||
- *              (the chain product's own error).  The estimate is of the
- *              error against the exact pseudoinverse of G restricted to the
- *              accepted columns; on inputs where float64 itself is
- *              ill-conditioned (cond(L'L) u not small) it reports that
- *              floor too.
+ *              estimates the relative change the engine makes to Y against
+ *              the float64 form on the same G, from 16 random sign probes V
+ *              and float64 products that use the caller's G (one host
+ *              synchronization):
+ *                resA  = ||A_e V - G'(G V)|| / ||G'(G V)||, the engine's
+ *                        Gram matrix A_e against float64 products;
+ *                kappa = max_k A_kk / (smallest accepted pivot), how much
+ *                        the factorization amplifies a relative Gram error;
+ *                resY  = ||Y V' - P (G' V')|| / ||P (G' V')||, the engine's
+ *                        chain product against float64 products on the
+ *                        same P (0 for a float64 chain);
+ *              err_est = kappa resA + resY (a first-order estimate; the
+ *              Frobenius norms come from the probes, relative spread about
+ *              1 / sqrt(32)).
  * Other arguments as in geninv_dgeninv. */
 int geninv_mixed(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double tol, int precision,
                  int gram_digits, int chain_digits, int ns_steps, double target, double *Y, int ldy, int *rank,
@@ -375,8 +404,14 @@ int geninv_batch_plan_destroy(geninv_batch_plan *plan);
 
 /* Enqueue one solve of every problem on the context stream.  use_graph != 0
  * captures the launch into a HIP graph on first use (on a non-default
- * stream) and replays it afterwards. */
+ * stream) and replays it afterwards.  When the stream is already being
+ * captured by the caller, or the plan's own capture or instantiation fails,
+ * the run launches directly instead (same work; inside a caller's capture
+ * the launches join the caller's graph) and the plan counts it:
+ * geninv_batch_plan_graph_fallbacks returns that count (EINVAL for a null
+ * plan). */
 int geninv_batch_plan_run(geninv_batch_plan *plan, int use_graph);
+int geninv_batch_plan_graph_fallbacks(const geninv_batch_plan *plan);
 
 /* Autotuner: times each launch configuration (LDS threshold below which a
  * problem's Gram matrix and L'L live in LDS, and workgroups per compute unit)

@@ -41,6 +41,9 @@ _SIGS = [
     ("geninv_destroy", ctypes.c_int, [_VP]),
     ("geninv_set_stream", ctypes.c_int, [_VP, _VP]),
     ("geninv_set_host_sync", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("geninv_set_workspace_limit", ctypes.c_int, [_VP, ctypes.c_size_t]),
+    ("geninv_set_debug", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("geninv_debug_poison", ctypes.c_int, [_VP]),
     ("geninv_sync_status", ctypes.c_int, [_VP]),
     ("geninv_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("geninv_version", ctypes.c_int, []),
@@ -91,6 +94,7 @@ _SIGS = [
                                             ctypes.POINTER(_VP), _c_int_p, ctypes.POINTER(_VP), _c_int_p,
                                             ctypes.c_double, ctypes.POINTER(_VP), _c_int_p, _VP, _c_int_p]),
     ("geninv_batch_plan_run", ctypes.c_int, [_VP, ctypes.c_int]),
+    ("geninv_batch_plan_graph_fallbacks", ctypes.c_int, [_VP]),
     ("geninv_batch_plan_autotune", ctypes.c_int, [_VP, ctypes.c_int, _c_int_p, _c_int_p,
                                                   ctypes.POINTER(ctypes.c_double)]),
     ("geninv_batch_plan_set_pivots", ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),

@@ -37,9 +37,27 @@ def _ctx(device: torch.device):
 
 def set_host_sync(enable: bool, device=None):
     """geninv_set_host_sync on the context of `device` (default: current)."""
-    dev = torch.device("cuda", device if isinstance(device, int) else torch.cuda.current_device()) \
+    _check(load().geninv_set_host_sync(_ctx(_ctx_of(device)), 1 if enable else 0), "geninv_set_host_sync")
+
+
+def _ctx_of(device):
+    return torch.device("cuda", device if isinstance(device, int) else torch.cuda.current_device()) \
         if not isinstance(device, torch.device) else device
-    _check(load().geninv_set_host_sync(_ctx(dev), 1 if enable else 0), "geninv_set_host_sync")
+
+
+def set_workspace_limit(nbytes: int, device=None):
+    """geninv_set_workspace_limit (0 = no cap) on the context of `device`."""
+    _check(load().geninv_set_workspace_limit(_ctx(_ctx_of(device)), int(nbytes)), "geninv_set_workspace_limit")
+
+
+def set_debug(flags: int, device=None):
+    """geninv_set_debug (GENINV_DEBUG_POISON = 1) on the context of `device`."""
+    _check(load().geninv_set_debug(_ctx(_ctx_of(device)), int(flags)), "geninv_set_debug")
+
+
+def debug_poison(device=None):
+    """geninv_debug_poison: NaN-fill the context's current workspace."""
+    _check(load().geninv_debug_poison(_ctx(_ctx_of(device))), "geninv_debug_poison")
 
 
 def _check(st: int, where: str):
@@ -477,6 +495,11 @@ class BatchPlan(_PackedBatch):
     def run(self, use_graph: bool = True):
         _ctx(self.device)   # follow torch's current stream
         _check(self._lib.geninv_batch_plan_run(self._plan, int(use_graph)), "geninv_batch_plan_run")
+
+    def graph_fallbacks(self) -> int:
+        """Runs that asked for the graph and launched directly
+        (geninv_batch_plan_graph_fallbacks)."""
+        return int(self._lib.geninv_batch_plan_graph_fallbacks(self._plan))
 
     def autotune(self, reps: int = 3):
         _ctx(self.device)

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -35,6 +36,8 @@ struct ProfState {
 struct geninv_batch_plan;
 
 namespace geninv {
+// debug.hip
+hipError_t launch_poison(void *p, size_t bytes, hipStream_t s);
 // skinny.hip
 int skinny_padded_width(int N);
 hipError_t launch_skinny_gemm(const double *A, long lda, const double *B, long ldb, int transB, int M, int N, int K,
@@ -62,6 +65,8 @@ struct geninv_ctx {
     int host_sync = 1;         // read the rank back after the factorization (geninv_set_host_sync)
     int *hpin = nullptr;       // pinned host word for that read-back
     char *scratch = nullptr;   // this device's address of the fixed scratch area
+    size_t ws_limit = 0;       // workspace cap in bytes, 0 = none (geninv_set_workspace_limit)
+    int debug = 0;             // GENINV_DEBUG_POISON: NaN-fill every new workspace
     ProfState prof;
 };
 
@@ -204,6 +209,7 @@ Layout make_layout(int nn, int k, int kdim = 0) {
 }
 
 int ensure_ws(geninv_ctx *c, size_t bytes) {
+    if (c->ws_limit && bytes > c->ws_limit) return GENINV_ENOMEM;
     if (bytes <= c->ws_bytes) return GENINV_OK;
     if (c->ws) {
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -218,6 +224,7 @@ int ensure_ws(geninv_ctx *c, size_t bytes) {
     }
     c->ws = static_cast<char *>(p);
     c->ws_bytes = bytes;
+    if (c->debug & GENINV_DEBUG_POISON) HIPCHK(launch_poison(c->ws, c->ws_bytes, c->stream));
     return GENINV_OK;
 }
 
@@ -235,6 +242,15 @@ GemmArgs gemm(const double *A, long lda, int tA, const double *B, long ldb, int 
     g.uplo = uplo;
     g.splitk = 1;
     g.strideC = 0;
+    g.onelevel = 0;
+    return g;
+}
+
+// The chain's products (K = L M, P = K K', Y = P G'): their rounding is not
+// amplified by a later inversion, so one running sum over K suffices (the
+// Gram matrix and L'L keep the two-level sum).
+GemmArgs chain(GemmArgs g) {
+    g.onelevel = 1;
     return g;
 }
 
@@ -434,6 +450,37 @@ int finish_rank(geninv_ctx *c, const int *rdev, int *rank) {
 
 bool bad_ld(long ld, int rows) { return ld < std::max(1, rows); }
 
+// Step 5's last product for a rank under half the order (rank known on the
+// host): Y = K (K' G'), or (G' K) K' in the transpose branch, 4 nn r m flops
+// instead of the nn(nn+1) r + 2 nn^2 m of forming P = K K' first; equal to
+// L M M L' G' in exact arithmetic (Theorem 1).  The r-row intermediate goes
+// through the P slot (nn x nn elements) in blocks of Y's columns (rows in the
+// transpose branch).
+bool lowrank_chain(int nn, Dim r) { return !r.dev && r.host > 0 && 2 * r.host < nn; }
+
+int run_chain_lowrank(geninv_ctx *c, const Layout &lay, const double *K, long ld, int nn, int r, const double *G,
+                      long ldg, bool tr, int n, int m, double *Y, long ldy) {
+    double *Z = at<double>(c, lay.slotP);
+    const long cap = (long)nn * nn;
+    const int other = tr ? n : m;            // Y's long dimension
+    long blk = std::min<long>(other, cap / r);
+    if (blk > 128) blk -= blk % 128;
+    for (long j0 = 0; j0 < other; j0 += blk) {
+        const int w = (int)std::min<long>(blk, other - j0);
+        if (!tr) {
+            // Z (r x w) = K' G(j0:j0+w, :)', then Y(:, j0:j0+w) = K Z
+            CHK(gemm_fill(c, lay, chain(gemm(K, ld, 1, G + j0, ldg, 1, Z, r, hdim(r), hdim(w), hdim(nn), 1.0, 0.0))));
+            CHK(gemm_fill(c, lay,
+                          chain(gemm(K, ld, 0, Z, r, 0, Y + j0 * ldy, ldy, hdim(nn), hdim(w), hdim(r), 1.0, 0.0))));
+        } else {
+            // Z (w x r) = G(:, j0:j0+w)' K, then Y(j0:j0+w, :) = Z K'
+            CHK(gemm_fill(c, lay,
+                          chain(gemm(G + j0 * ldg, ldg, 1, K, ld, 0, Z, w, hdim(w), hdim(r), hdim(nn), 1.0, 0.0))));
+            CHK(gemm_fill(c, lay, chain(gemm(Z, w, 0, K, ld, 1, Y + j0, ldy, hdim(w), hdim(nn), hdim(r), 1.0, 0.0))));
+        }
+    }
+    return GENINV_OK;
+}
 
 // ---- mixed precision (sliced bfloat16 products) --------------------------
 
@@ -766,6 +813,8 @@ int geninv_create(geninv_ctx **ctx, int device, void *hip_stream) {
         }
         c->scratch = g_scratch[device];
     }
+    if (const char *e = getenv("GENINV_DEBUG")) c->debug = atoi(e);
+    if (const char *e = getenv("GENINV_WORKSPACE_LIMIT")) c->ws_limit = strtoull(e, nullptr, 10);
     *ctx = c;
     return GENINV_OK;
 }
@@ -786,6 +835,26 @@ int geninv_destroy(geninv_ctx *c) {
 int geninv_set_host_sync(geninv_ctx *c, int enable) {
     if (!c) return GENINV_EINVAL;
     c->host_sync = enable ? 1 : 0;
+    return GENINV_OK;
+}
+
+int geninv_set_workspace_limit(geninv_ctx *c, size_t bytes) {
+    if (!c) return GENINV_EINVAL;
+    c->ws_limit = bytes;
+    return GENINV_OK;
+}
+
+int geninv_set_debug(geninv_ctx *c, int flags) {
+    if (!c || (flags & ~GENINV_DEBUG_POISON)) return GENINV_EINVAL;
+    c->debug = flags;
+    return GENINV_OK;
+}
+
+int geninv_debug_poison(geninv_ctx *c) {
+    if (!c) return GENINV_EINVAL;
+    if (!c->ws) return GENINV_OK;
+    DeviceGuard g(c->device);
+    HIPCHK(launch_poison(c->ws, c->ws_bytes, c->stream));
     return GENINV_OK;
 }
 
@@ -989,10 +1058,11 @@ int geninv_dchain(geninv_ctx *c, int m, int n, int r, const double *L, int ldl, 
     CHK(ensure_ws(c, lay.total));
     double *K = at<double>(c, lay.slotK);
     double *P = at<double>(c, lay.slotP);
-    CHK(gemm_fill(c, lay, gemm(L, ldl, 0, M, ldm, 0, K, n, hdim(n), hdim(r), hdim(r), 1.0, 0.0)));
-    CHK(gemm_fill(c, lay, gemm(K, n, 0, K, n, 1, P, n, hdim(n), hdim(n), hdim(r), 1.0, 0.0, GEMM_LOWER)));
+    CHK(gemm_fill(c, lay, chain(gemm(L, ldl, 0, M, ldm, 0, K, n, hdim(n), hdim(r), hdim(r), 1.0, 0.0))));
+    if (lowrank_chain(n, hdim(r))) return run_chain_lowrank(c, lay, K, n, n, r, G, ldg, false, n, m, Y, ldy);
+    CHK(gemm_fill(c, lay, chain(gemm(K, n, 0, K, n, 1, P, n, hdim(n), hdim(n), hdim(r), 1.0, 0.0, GEMM_LOWER))));
     HIPCHK(launch_mirror_lower(P, n, hdim(n), c->stream));
-    HIPCHK(launch_dgemm(gemm(P, n, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
+    HIPCHK(launch_dgemm(chain(gemm(P, n, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0)), c->stream));
     return GENINV_OK;
 }
 
@@ -1025,14 +1095,20 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     CHK(rank_dim(c, nn, rdev, &r));
     // 4. M = (L'L)^-1 into the Gram's slot
     CHK(run_factor_inverse(c, lay, L, ld, nn, r, A, ld));
-    // 5. K = L M, P = K K' (= (G'G)^+), then Y = P G' or Y = G' P
+    // 5. K = L M, P = K K' (= (G'G)^+), then Y = P G' or Y = G' P; for a rank
+    //    under half the order Y = K (K' G') or (G' K) K' instead
     {
         ProfScope ps(c, PC_CHAIN_K, 0.0);
-        CHK(gemm_fill(c, lay, gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0)));
+        CHK(gemm_fill(c, lay, chain(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0))));
+    }
+    if (lowrank_chain(nn, r)) {
+        ProfScope ps(c, PC_CHAIN_Y, 4.0 * n * m * r.host);
+        CHK(run_chain_lowrank(c, lay, K, ld, nn, r.host, G, ldg, tr, n, m, Y, ldy));
+        return finish_rank(c, rdev, rank);
     }
     {
         ProfScope ps(c, PC_CHAIN_P, 0.0);
-        CHK(gemm_fill(c, lay, gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER)));
+        CHK(gemm_fill(c, lay, chain(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER))));
     }
     {
         ProfScope ps(c, PC_MIRROR, 0.0);
@@ -1040,8 +1116,10 @@ int geninv_dgeninv(geninv_ctx *c, int m, int n, const double *G, int ldg, double
     }
     {
         ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * nn);
-        if (!tr) HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
-        else HIPCHK(launch_dgemm(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0), c->stream));
+        if (!tr) HIPCHK(launch_dgemm(chain(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0)),
+                                     c->stream));
+        else HIPCHK(launch_dgemm(chain(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0)),
+                                 c->stream));
     }
     return finish_rank(c, rdev, rank);
 }
@@ -1679,11 +1757,11 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
     // 5. K = L M, P = K K' (float64)
     {
         ProfScope ps(c, PC_CHAIN_K, 0.0);
-        CHK(gemm_fill(c, lay, gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0)));
+        CHK(gemm_fill(c, lay, chain(gemm(L, ld, 0, A, ld, 0, K, ld, hdim(nn), r, r, 1.0, 0.0))));
     }
     {
         ProfScope ps(c, PC_CHAIN_P, 0.0);
-        CHK(gemm_fill(c, lay, gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER)));
+        CHK(gemm_fill(c, lay, chain(gemm(K, ld, 0, K, ld, 1, P, ld, hdim(nn), hdim(nn), r, 1.0, 0.0, GEMM_LOWER))));
         HIPCHK(launch_mirror_lower(P, ld, hdim(nn), c->stream));
     }
     // 6. Newton-Schulz steps X <- X (2I - G_r X) in the factored form on P
@@ -1716,8 +1794,10 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
     // 7. Y = P G' (G' P in the transpose branch)
     if (chain_digits == 0) {
         ProfScope ps(c, PC_CHAIN_Y, 2.0 * n * m * (double)nn);
-        if (!tr) HIPCHK(launch_dgemm(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0), c->stream));
-        else HIPCHK(launch_dgemm(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0), c->stream));
+        if (!tr) HIPCHK(launch_dgemm(chain(gemm(P, ld, 0, G, ldg, 1, Y, ldy, hdim(n), hdim(m), hdim(n), 1.0, 0.0)),
+                                     c->stream));
+        else HIPCHK(launch_dgemm(chain(gemm(G, ldg, 1, P, ld, 0, Y, ldy, hdim(n), hdim(m), hdim(m), 1.0, 0.0)),
+                                 c->stream));
     } else if (precision == GENINV_MIXED_BF16) {
         const int s = chain_digits;
         __bf16 *Gt = at<__bf16>(c, mp.bf.gt);
@@ -1803,6 +1883,7 @@ struct geninv_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
+    int graph_fallbacks = 0;     // runs that asked for the graph and launched directly
 };
 
 namespace {
@@ -1955,26 +2036,45 @@ int geninv_batch_plan_run(geninv_batch_plan *p, int use_graph) {
     DeviceGuard g(c->device);
     ProfScope ps(c, PC_BATCHED, 0.0);
     if (!use_graph || c->stream == nullptr) return plan_launch(p, c->stream);
+    // A stream that the caller is already capturing gets the direct launches
+    // (they become part of the caller's graph); so does any run whose own
+    // capture or instantiation fails.  Either way the run's work is the
+    // same, and graph_fallbacks counts it.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(c->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+        ++p->graph_fallbacks;
+        return plan_launch(p, c->stream);
+    }
     if (p->exec && p->graph_stream != c->stream) plan_drop_graph(p);
     if (!p->exec) {
-        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        const int st = plan_launch(p, c->stream);
-        hipGraph_t graph = nullptr;
-        const hipError_t e = hipStreamEndCapture(c->stream, &graph);
-        if (st != GENINV_OK || e != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return st != GENINV_OK ? st : GENINV_EHIP;
+        bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const int st = plan_launch(p, c->stream);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+            if (st != GENINV_OK || e != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                if (st != GENINV_OK) return st;   // an argument or launch error, not a capture failure
+                ok = false;
+            } else {
+                p->graph = graph;
+                ok = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (!ok) plan_drop_graph(p);
+            }
         }
-        p->graph = graph;
-        if (hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-            plan_drop_graph(p);
-            return GENINV_EHIP;
+        if (!ok) {
+            (void)hipGetLastError();
+            ++p->graph_fallbacks;
+            return plan_launch(p, c->stream);
         }
         p->graph_stream = c->stream;
     }
     HIPCHK(hipGraphLaunch(p->exec, c->stream));
     return GENINV_OK;
 }
+
+int geninv_batch_plan_graph_fallbacks(const geninv_batch_plan *p) { return p ? p->graph_fallbacks : GENINV_EINVAL; }
 
 // Times every (LDS threshold, workgroups per CU) candidate `reps` times with
 // events on the context stream and keeps the fastest.

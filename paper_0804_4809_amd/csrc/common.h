@@ -64,6 +64,7 @@ struct GemmArgs {
     int uplo;          // GemmUplo; GEMM_LOWER skips tiles above the diagonal and elements with row < col
     int splitk;        // > 1: gridDim.z slices of K, raw partial sums written to C + z*strideC
     long strideC;
+    int onelevel;      // 128-tile kernel: one running sum over K instead of the two-level sum
 };
 
 // Sliced (error-free split) GEMM on bfloat16 matrix cores, ozaki.hip.

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
 // constant, so the compiler keeps reads of one buffer independent of the
 // direct loads into the other.
 // ---------------------------------------------------------------------------
-constexpr int DM_T = 128, DM_BK = 32, DM_NT = 512;
+constexpr int DM_T = 128, DM_BK = 32;
 constexpr int DM_LD = DM_T + 4;   // MN-major LDS row pitch (doubles)
 
 template <bool KMAJ>
@@ -335,12 +335,17 @@ struct DmOp {
     }
 };
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
+template <bool TA, bool TB, int NW, bool FL>
+__global__ __launch_bounds__(64 * NW) void dgemm_dma_kernel(GemmArgs p) {
     constexpr bool AK = TA, BK_ = !TB;   // K-major operands
     using OA = DmOp<AK>;
     using OB = DmOp<BK_>;
-    constexpr int TM = 32, TN = 64, FM = 2, FN = 4;
+    // NW = 8: 4 x 2 wavefronts of 32 x 64; NW = 4: 2 x 2 wavefronts of 64 x 64
+    static_assert(NW == 4 || NW == 8, "wavefronts per workgroup");
+    constexpr int NT = 64 * NW, TM = NW == 8 ? 32 : 64, TN = 64, FM = TM / 16, FN = TN / 16;
+    constexpr int WMW = DM_T / TM;                 // wavefronts along M
+    constexpr int PIECES = 32 / NW;                // direct loads per operand per wavefront and chunk
+    constexpr int PAIRS = DM_T * DM_BK / 2 / NT;   // staged pairs per operand per thread
     __shared__ __align__(1024) char As0[OA::BYTES];
     __shared__ __align__(1024) char As1[OA::BYTES];
     __shared__ __align__(1024) char Bs0[OB::BYTES];
@@ -363,7 +368,7 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wm = wave & 3, wn = wave >> 2;
+    const int wm = wave % WMW, wn = wave / WMW;
     const double *__restrict__ A = p.A;
     const double *__restrict__ B = p.B;
     const long lda = p.lda, ldb = p.ldb;
@@ -375,11 +380,12 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
     const bool small_off = 4L * (lda + ldb) + 64L * (lda + ldb) < (1L << 30);
     const bool interior = aligned && small_off && row0 + DM_T <= M && col0 + DM_T <= N;
 
-    // ---- direct loads: per-lane element offsets (the same for the four
+    // ---- direct loads: per-lane element offsets (the same for the PIECES
     // loads of each operand a wavefront issues per chunk)
-    //   MN-major: load q of wavefront w is k row w + 8q, lane l its granule l
-    //   K-major: load q is rows 4 (w + 8q) .. +3, lane l row + l / 16, slot
-    //            l % 16 holding granule (l % 16) ^ (row % 16)
+    //   MN-major: load q of wavefront w is k row w + NW q, lane l its granule l
+    //   K-major: load q is rows 4 (w + NW q) .. +3, lane l row + l / 16, slot
+    //            l % 16 holding granule (l % 16) ^ (row % 16) (4 NW q is a
+    //            multiple of 16, so the row's residue is 4 (w % 4) + l / 16)
     auto dma_lane_off = [&](bool kmaj, long ld) -> int {
         if (!kmaj) return 2 * lane;
         const int r = lane >> 4;
@@ -387,9 +393,9 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
         return 2 * g + (int)(r * ld);
     };
     const int adl = dma_lane_off(AK, lda), bdl = dma_lane_off(BK_, ldb);
-    // load q (0..3) of each operand for the chunk at kc
+    // load q (0..PIECES-1) of each operand for the chunk at kc
     auto dma_piece = [&](int q, int kc, char *as, char *bs) {
-        const int u = wave + 8 * q;   // k row (MN-major) or row group (K-major)
+        const int u = wave + NW * q;   // k row (MN-major) or row group (K-major)
         const double *ga = AK ? A + kc + (long)(row0 + 4 * u) * lda : A + row0 + (long)(kc + u) * lda;
         const double *gb = BK_ ? B + kc + (long)(col0 + 4 * u) * ldb : B + col0 + (long)(kc + u) * ldb;
         lds_load16(ga + adl, as + (AK ? u * 1024 : u * DM_LD * 8));
@@ -397,20 +403,20 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
     };
     auto dma = [&](int kc, char *as, char *bs) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dma_piece(q, kc, as, bs);
+        for (int q = 0; q < PIECES; ++q) dma_piece(q, kc, as, bs);
     };
 
     // ---- staged fill (edge tiles, partial chunks), after the current chunk's
-    // products so that it holds no registers across them: 4 pairs per operand
-    // per thread, zero outside the operand, written to the same layouts
+    // products so that it holds no registers across them: PAIRS pairs per
+    // operand per thread, zero outside the operand, written to the same layouts
     auto pair_of = [&](bool kmaj, int q, int &i, int &k) {
-        const int c = tid + DM_NT * q;
+        const int c = tid + NT * q;
         if (kmaj) { i = c / (DM_BK / 2); k = 2 * (c % (DM_BK / 2)); }
         else      { i = 2 * (c % (DM_T / 2)); k = c / (DM_T / 2); }
     };
     auto staged_fill = [&](int kc, char *as, char *bs) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < PAIRS; ++q) {
             int i, k;
             d2 v;
             pair_of(AK, q, i, k);
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
         }
     };
 
-    // ---- matrix-core reads: fragment a of the wavefront's rows wm*32 + 16a
+    // ---- matrix-core reads: fragment a of the wavefront's rows wm*TM + 16a
     // + (lane % 16) at k = kk + lane / 16.  MN-major: one per-lane offset;
     // K-major: one per-lane offset for each of the 8 k steps of a chunk.
     int aro[DM_BK / 4], bro[DM_BK / 4];
@@ -457,20 +463,22 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
     auto rconst = [&](bool kmaj, int r, int s) { return kmaj ? 8 * r * DM_BK : 8 * (4 * s * DM_LD + r); };
 
     constexpr int FLUSH_CHUNKS = KFLUSH / DM_BK;
-    d4 acc[FM][FN], tot[FM][FN];
+    // FL: two-level sums (acc restarted every KFLUSH of K, totals in tot);
+    // otherwise acc holds the whole sum
+    d4 acc[FM][FN], tot[FL ? FM : 1][FL ? FN : 1];
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
             acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-            tot[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+            if constexpr (FL) tot[a][b] = d4{0.0, 0.0, 0.0, 0.0};
         }
     // the products of one chunk; with `pf`, the direct loads of the next
     // chunk (at kn, into na / nb) are spread over its first k steps
     auto compute = [&](const char *as, const char *bs, bool pf, int kn, char *na, char *nb) {
 #pragma unroll
         for (int s = 0; s < DM_BK / 4; ++s) {
-            if (s < 4 && pf) dma_piece(s, kn, na, nb);
+            if (s < PIECES && pf) dma_piece(s, kn, na, nb);
             double af[FM], bf[FN];
 #pragma unroll
             for (int a = 0; a < FM; ++a)
@@ -495,14 +503,16 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
         const bool more = c + 1 < nchunks;
         const bool dnext = more && direct(c + 1);
         compute(xa, xb, dnext, kbeg + (c + 1) * DM_BK, ya, yb);
-        if ((c + 1) % FLUSH_CHUNKS == 0) {
+        if constexpr (FL) {
+            if ((c + 1) % FLUSH_CHUNKS == 0) {
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+                for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < FN; ++b) {
-                    tot[a][b] += acc[a][b];
-                    acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-                }
+                    for (int b = 0; b < FN; ++b) {
+                        tot[a][b] += acc[a][b];
+                        acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+                    }
+            }
         }
         if (more && !dnext) staged_fill(kbeg + (c + 1) * DM_BK, ya, yb);
         wait_vm<0>();
@@ -520,10 +530,12 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
         }
         if (c < nchunks) step(c, As0, Bs0, As1, Bs1);
     }
+    if constexpr (FL) {
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) tot[a][b] += acc[a][b];
+            for (int b = 0; b < FN; ++b) acc[a][b] += tot[a][b];
+    }
 
     const bool lower = p.uplo == GEMM_LOWER;
     const long ldc = p.ldc;
@@ -551,7 +563,7 @@ __global__ __launch_bounds__(DM_NT) void dgemm_dma_kernel(GemmArgs p) {
             for (int v = 0; v < 4; ++v) {
                 const int c = col0 + wn * TN + b * 16 + (lane >> 4) + 4 * v;
                 if (r < M && c < N && (!lower || r >= c)) {
-                    const double val = tot[a][b][v];
+                    const double val = acc[a][b][v];
                     C[r + (long)c * ldc] = raw ? val : (with_c ? alpha * val + beta * cold[a][b][v] : alpha * val);
                 }
             }
@@ -564,7 +576,8 @@ static hipError_t launch_dma_t(const GemmArgs &a, hipStream_t s) {
     const int S = a.splitk > 1 ? a.splitk : 1;
     const long T = tiles_of<DM_T, DM_T>(a);
     if (T <= 0) return hipSuccess;
-    hipLaunchKernelGGL((dgemm_dma_kernel<TA, TB>), dim3((unsigned)T, S), dim3(DM_NT), 0, s, a);
+    if (a.onelevel) hipLaunchKernelGGL((dgemm_dma_kernel<TA, TB, 8, false>), dim3((unsigned)T, S), dim3(512), 0, s, a);
+    else hipLaunchKernelGGL((dgemm_dma_kernel<TA, TB, 8, true>), dim3((unsigned)T, S), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 

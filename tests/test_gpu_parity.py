@@ -80,12 +80,17 @@ def test_dgemm_parity(M, N, K, tA, tB):
 # ---------------------------------------------------------------------------
 # individual steps on identical inputs
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("m,n", [(200, 50), (1000, 300), (513, 129), (4096, 1000)])
+@pytest.mark.parametrize("m,n", [(200, 50), (1000, 300), (513, 129), (4096, 1000), (70001, 130)])
 def test_gram_parity(m, n):
+    """Elementwise: both sides are sums of m products, each within
+    m u (|G|'|G|) of the exact Gram matrix; 70001 rows take the split over K."""
     _print_case("gram", m=m, n=n)
-    G = np.random.default_rng(m + n).standard_normal((m, n))
+    rng = np.random.default_rng(m + n)
+    G = rng.standard_normal((m, n)) * np.exp(rng.uniform(-4, 4, size=(1, n)))
     ref = o.gram(G)
     A = down(api.gram(up(G), full=True))
+    bound = 2 * m * 2.2e-16 * (np.abs(G).T @ np.abs(G))
+    assert np.all(np.abs(A - ref) <= bound)
     assert o.rel_fro(A, ref) <= 1e-14 * np.sqrt(m)
     Al = down(api.gram(up(G), full=False))
     assert np.array_equal(np.tril(Al), np.tril(A))
@@ -165,6 +170,32 @@ def test_spdinv_parity():
         assert o.rel_fro(M, ref) <= 50 * cond * 2.2e-16 * r, r
 
 
+@pytest.mark.parametrize("r,smin", [(1153, 1e-3), (3072, 1e-3), (1153, 1e-4)])
+def test_spdinv_parity_path_sizes(r, smin):
+    """The orders the whole method inverts on the RBF and SVD workloads:
+    B = X'X with X's singular values log-spaced from 1 to smin (cond(B) =
+    smin^-2).  Forward error against the oracle within the normwise bound
+    c r cond(B) u, and the residual ||I - B M|| / sqrt(r) within c r cond u
+    (a backward-type check that does not go through the oracle)."""
+    _print_case("spdinv", r=r, smin=smin)
+    rng = np.random.default_rng(r)
+    Q1, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((r, r)))
+    X = (Q1 * np.logspace(0, np.log10(smin), r)) @ Q2.T
+    B = X.T @ X
+    B = (B + B.T) / 2
+    cond = smin ** -2.0
+    ref = o.spd_inverse(B)
+    M = down(api.spd_inverse(up(B)))
+    assert np.array_equal(M, M.T)
+    u = 2.2e-16
+    err = o.rel_fro(M, ref)
+    res = np.linalg.norm(np.eye(r) - B @ M) / np.sqrt(r)
+    print(f"  relF vs oracle {err:.3e}; residual {res:.3e}; cond {cond:.1e}", flush=True)
+    assert err <= 50 * cond * u * r
+    assert res <= 50 * cond * u * r
+
+
 @pytest.mark.parametrize("r,smin", [(1, 1.0), (64, 1e-2), (200, 1e-3), (513, 1e-1), (1000, 1e-3)])
 def test_spdinv_newton_schulz_parity(r, smin):
     """Newton-Schulz inverse of B = X'X (X with singular values log-spaced from
@@ -185,9 +216,12 @@ def test_spdinv_newton_schulz_parity(r, smin):
     assert o.rel_fro(M, ref) <= 50 * cond * 2.2e-16 * r
 
 
-def test_chain_parity_same_factors():
-    _print_case("chain")
-    G, _ = w.lowrank_uv(900, 260, 170, seed=31)
+@pytest.mark.parametrize("m,n,r", [(900, 260, 170), (3000, 400, 90)])
+def test_chain_parity_same_factors(m, n, r):
+    """P = K K' then Y = P G' (rank 170 of 260), and Y = K (K' G') in two
+    column blocks (rank 90 of 400)."""
+    _print_case("chain", m=m, n=n, r=r)
+    G, _ = w.lowrank_uv(m, n, r, seed=31)
     res = o.geninv(G)
     Y = down(api.chain(up(res.L), up(res.M), up(G)))
     assert o.rel_fro(Y, res.Y) <= 1e-11
@@ -222,7 +256,11 @@ def test_geninv_c1():
 
 
 @pytest.mark.parametrize("m,n,r,seed", [(1000, 300, 200, 1), (777, 129, 129, 2), (65, 64, 63, 3),
-                                        (130, 1, 1, 4), (1, 1, 1, 5), (300, 700, 120, 6), (64, 200, 64, 7)])
+                                        (130, 1, 1, 4), (1, 1, 1, 5), (300, 700, 120, 6), (64, 200, 64, 7),
+                                        # rank under half the order: Y = K (K' G') in column blocks of Y
+                                        # (5000 x 300: six blocks, the last ragged), and (G' K) K' in the
+                                        # transpose branch (250 x 3000: three row blocks)
+                                        (5000, 300, 100, 8), (250, 3000, 60, 9), (2000, 700, 150, 10)])
 def test_geninv_lowrank_ragged(m, n, r, seed):
     _print_case("geninv", m=m, n=n, r=r, seed=seed)
     G, _ = w.lowrank_uv(m, n, r, seed)
