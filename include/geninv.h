@@ -386,7 +386,9 @@ int geninv_bchain(geninv_ctx *ctx, int n, int m, int k, const double *P, int ldp
  * queue, largest first, and runs the whole method on one problem (Gram matrix
  * and G'F with float64 accumulation, tol, full-rank Cholesky, (L'L)^-1,
  * W = L M M L' G'F).
- *   m, n, ldg, ldf, ldw   HOST int[batch]; 1 <= n_b <= 256, m_b >= n_b
+ *   m, n, ldg, ldf, ldw   HOST int[batch]; 1 <= min(m_b, n_b) <= 256 (m_b < n_b
+ *                         takes the Appendix's transpose branch: G_b G_b' is
+ *                         factored and W_b = G_b' L M M L' F_b)
  *   G, F                  HOST arrays of DEVICE pointers: G_b m_b x n_b and
  *                         F_b m_b x k, float32, column-major
  *   W                     HOST array of DEVICE pointers: W_b n_b x k, float64
@@ -413,11 +415,19 @@ int geninv_batch_plan_destroy(geninv_batch_plan *plan);
 int geninv_batch_plan_run(geninv_batch_plan *plan, int use_graph);
 int geninv_batch_plan_graph_fallbacks(const geninv_batch_plan *plan);
 
-/* Autotuner: times each launch configuration (LDS threshold below which a
- * problem's Gram matrix and L'L live in LDS, and workgroups per compute unit)
- * `reps` times and keeps the fastest; outputs may be NULL.  Synchronizes. */
-int geninv_batch_plan_autotune(geninv_batch_plan *plan, int reps, int *best_nl, int *best_grid,
-                               double *best_ms);
+/* Autotuner: times each launch configuration (tile class: 4 or 8 Gram tiles
+ * of 16 x 16 per wavefront and pass; LDS threshold below which a problem's
+ * Gram matrix and L'L live in LDS; workgroups per compute unit) `reps` times
+ * and keeps the fastest.  cache_path (or NULL): a text file of tuned
+ * configurations keyed by the library version, the device and the batch's
+ * shapes; an entry for this batch is applied without timing (*from_cache =
+ * 1), otherwise the result is stored there (through a temporary file and a
+ * rename).  Unparsable or inapplicable lines are ignored and a missing,
+ * unreadable or unwritable file only means tuning (the plan keeps working
+ * with the tuned or default configuration).  Outputs may be NULL.
+ * Synchronizes. */
+int geninv_batch_plan_autotune(geninv_batch_plan *plan, int reps, const char *cache_path, int *best_nl,
+                               int *best_grid, int *best_tiles, double *best_ms, int *from_cache);
 
 /* One-shot form of the batched solve, with the arguments of
  * geninv_batch_plan_create: builds a plan with the default launch
@@ -432,15 +442,18 @@ int geninv_lstsq_batched(geninv_ctx *ctx, int batch, const int *m, const int *n,
                          int *status);
 
 /* Optional per-problem pivot output: piv is a HOST array of `batch` DEVICE
- * pointers (int[n_b] each, or NULL entries), or NULL to switch the output
- * off.  Each run then writes the 0-based indices of the r_b columns problem
- * b kept, increasing (as geninv_dgeninv's piv).  Synchronizes the stream;
+ * pointers (int[min(m_b, n_b)] each, or NULL entries), or NULL to switch
+ * the output off.  Each run then writes the 0-based indices of the r_b
+ * columns problem b kept (rows of G_b in the transpose branch), increasing
+ * (as geninv_dgeninv's piv).  Synchronizes the stream;
  * a graph captured earlier keeps reading the descriptors, so it follows. */
 int geninv_batch_plan_set_pivots(geninv_batch_plan *plan, int *const *piv);
 
-/* Set or read the launch configuration directly (e.g. from a cached tuning). */
-int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid);
-int geninv_batch_plan_get_config(geninv_batch_plan *plan, int *nl, int *grid);
+/* Set or read the launch configuration directly: LDS threshold nl, grid
+ * workgroups (<= 1024), tile class (4 or 8).  EINVAL for a configuration
+ * whose LDS does not fit a compute unit. */
+int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid, int tiles);
+int geninv_batch_plan_get_config(geninv_batch_plan *plan, int *nl, int *grid, int *tiles);
 
 /* ---- event timers ------------------------------------------------------- */
 

@@ -10,6 +10,8 @@ runs in libgeninv's HIP kernels.
 from __future__ import annotations
 
 import ctypes
+import os
+from typing import NamedTuple
 from dataclasses import dataclass
 
 import torch
@@ -458,6 +460,14 @@ class _PackedBatch:
         return self.Wbuf[o:o + n * self.k].view(self.k, n).t()
 
 
+class AutotuneResult(NamedTuple):
+    nl: int
+    grid: int
+    tiles: int
+    ms: float
+    from_cache: bool
+
+
 class BatchPlan(_PackedBatch):
     """Batched least squares W_b = G_b^+ F_b (geninv_batch_plan_*).
 
@@ -501,20 +511,29 @@ class BatchPlan(_PackedBatch):
         (geninv_batch_plan_graph_fallbacks)."""
         return int(self._lib.geninv_batch_plan_graph_fallbacks(self._plan))
 
-    def autotune(self, reps: int = 3):
+    def autotune(self, reps: int = 3, cache: str | None = None):
+        """geninv_batch_plan_autotune: (nl, grid, tiles, ms, from_cache)."""
         _ctx(self.device)
-        nl, grid, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
-        _check(self._lib.geninv_batch_plan_autotune(self._plan, reps, ctypes.byref(nl), ctypes.byref(grid),
-                                                    ctypes.byref(ms)), "geninv_batch_plan_autotune")
-        return nl.value, grid.value, ms.value
+        nl, grid, tiles, fc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        ms = ctypes.c_double(0.0)
+        path = None if cache is None else os.fsencode(cache)
+        _check(self._lib.geninv_batch_plan_autotune(self._plan, reps, path, ctypes.byref(nl), ctypes.byref(grid),
+                                                    ctypes.byref(tiles), ctypes.byref(ms), ctypes.byref(fc)),
+               "geninv_batch_plan_autotune")
+        return AutotuneResult(nl.value, grid.value, tiles.value, ms.value, bool(fc.value))
 
-    def config(self, nl: int | None = None, grid: int | None = None):
+    def config(self, nl: int | None = None, grid: int | None = None, tiles: int | None = None):
+        """Set (when nl and grid are given; tiles defaults to the current
+        class) and return the launch configuration (nl, grid, tiles)."""
         if nl is not None and grid is not None:
-            _check(self._lib.geninv_batch_plan_config(self._plan, int(nl), int(grid)), "geninv_batch_plan_config")
-        a, b = ctypes.c_int(0), ctypes.c_int(0)
-        _check(self._lib.geninv_batch_plan_get_config(self._plan, ctypes.byref(a), ctypes.byref(b)),
+            if tiles is None:
+                tiles = self.config()[2]
+            _check(self._lib.geninv_batch_plan_config(self._plan, int(nl), int(grid), int(tiles)),
+                   "geninv_batch_plan_config")
+        a, b, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.geninv_batch_plan_get_config(self._plan, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)),
                "geninv_batch_plan_get_config")
-        return a.value, b.value
+        return a.value, b.value, t.value
 
     def close(self):
         if getattr(self, "_plan", None):

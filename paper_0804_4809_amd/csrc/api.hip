@@ -4,7 +4,9 @@
 #include <cmath>
 #include <limits>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <mutex>
 #include <numeric>
 #include <vector>
@@ -1880,6 +1882,8 @@ struct geninv_batch_plan {
     int max_grid = 0;
     int *rank = nullptr;         // caller's device int[batch]
     int nl = 0, grid = 0;        // LDS threshold and workgroups (autotuned)
+    int tiles = 8;               // Gram tiles per wavefront and pass (tile class, autotuned)
+    unsigned long long shape_hash = 0;   // FNV-1a of k and every (m_b, n_b): the autotune cache key
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
@@ -1898,6 +1902,7 @@ void plan_drop_graph(geninv_batch_plan *p) {
 
 int plan_launch(geninv_batch_plan *p, hipStream_t s) {
     HIPCHK(launch_batched(p->desc, p->order, p->batch, p->k, p->tol, p->nl, p->queue, p->slabs, p->grid, p->nmax,
+                          p->tiles,
                           p->rank, p->c->status, s));
     return GENINV_OK;
 }
@@ -1923,9 +1928,10 @@ int geninv_batch_plan_create(geninv_ctx *c, geninv_batch_plan **plan, int batch,
     if (batch > 0 && (!m || !n || !G || !ldg || !F || !ldf || !W || !ldw || !rank)) return GENINV_EINVAL;
     int nmax = 1;
     for (int b = 0; b < batch; ++b) {
-        if (n[b] < 1 || n[b] > BATCH_NMAX || m[b] < n[b] || !G[b] || !F[b] || !W[b]) return GENINV_EINVAL;
+        const int nn = std::min(m[b], n[b]);   // order of the factored matrix (G'G, or G G' when m < n)
+        if (nn < 1 || nn > BATCH_NMAX || !G[b] || !F[b] || !W[b]) return GENINV_EINVAL;
         if (ldg[b] < m[b] || ldf[b] < m[b] || ldw[b] < n[b]) return GENINV_EINVAL;
-        nmax = std::max(nmax, n[b]);
+        nmax = std::max(nmax, nn);
     }
     DeviceGuard g(c->device);
     geninv_batch_plan *p = new geninv_batch_plan();
@@ -1935,14 +1941,30 @@ int geninv_batch_plan_create(geninv_ctx *c, geninv_batch_plan **plan, int batch,
     p->nmax = nmax;
     p->tol = tol;
     p->rank = rank;
-    // largest-first order: estimated work m n^2 + n^3 (Gram, then factorization and inverse)
+    {
+        unsigned long long h = 1469598103934665603ull;
+        auto mix = [&](unsigned v) {
+            for (int q = 0; q < 4; ++q) {
+                h ^= (v >> (8 * q)) & 0xffu;
+                h *= 1099511628211ull;
+            }
+        };
+        mix((unsigned)k);
+        for (int b = 0; b < batch; ++b) {
+            mix((unsigned)m[b]);
+            mix((unsigned)n[b]);
+        }
+        p->shape_hash = h;
+    }
+    // largest-first order: estimated work max(m, n) nn^2 + nn^3 with nn =
+    // min(m, n) (Gram, then factorization and inverse)
     std::vector<int> order(batch);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const double wa = (double)m[a] * n[a] * n[a] + (double)n[a] * n[a] * n[a];
-        const double wb = (double)m[b] * n[b] * n[b] + (double)n[b] * n[b] * n[b];
-        return wa > wb;
-    });
+    auto work = [&](int q) {
+        const double a = std::max(m[q], n[q]), o = std::min(m[q], n[q]);
+        return a * o * o + o * o * o;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
     std::vector<char> desc(batched_desc_bytes() * std::max(batch, 1));
     for (int b = 0; b < batch; ++b)
         batched_fill_desc(desc.data() + b * batched_desc_bytes(), G[b], F[b], W[b], m[b], n[b], ldg[b], ldf[b], ldw[b]);
@@ -2013,19 +2035,21 @@ int geninv_batch_plan_set_pivots(geninv_batch_plan *p, int *const *piv) {
     return GENINV_OK;
 }
 
-int geninv_batch_plan_config(geninv_batch_plan *p, int nl, int grid) {
-    if (!p || nl < 0 || grid < 1 || grid > p->max_grid) return GENINV_EINVAL;
+int geninv_batch_plan_config(geninv_batch_plan *p, int nl, int grid, int tiles) {
+    if (!p || nl < 0 || grid < 1 || grid > p->max_grid || (tiles != 4 && tiles != 8)) return GENINV_EINVAL;
     if (batched_lds_bytes(nl, p->nmax, p->k) > 160 * 1024) return GENINV_EINVAL;
-    if (nl != p->nl || grid != p->grid) plan_drop_graph(p);
+    if (nl != p->nl || grid != p->grid || tiles != p->tiles) plan_drop_graph(p);
     p->nl = nl;
     p->grid = grid;
+    p->tiles = tiles;
     return GENINV_OK;
 }
 
-int geninv_batch_plan_get_config(geninv_batch_plan *p, int *nl, int *grid) {
+int geninv_batch_plan_get_config(geninv_batch_plan *p, int *nl, int *grid, int *tiles) {
     if (!p) return GENINV_EINVAL;
     if (nl) *nl = p->nl;
     if (grid) *grid = p->grid;
+    if (tiles) *tiles = p->tiles;
     return GENINV_OK;
 }
 
@@ -2076,45 +2100,146 @@ int geninv_batch_plan_run(geninv_batch_plan *p, int use_graph) {
 
 int geninv_batch_plan_graph_fallbacks(const geninv_batch_plan *p) { return p ? p->graph_fallbacks : GENINV_EINVAL; }
 
-// Times every (LDS threshold, workgroups per CU) candidate `reps` times with
-// events on the context stream and keeps the fastest.
-int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, int *best_nl, int *best_grid, double *best_ms) {
+}  // extern "C"
+
+// The autotune cache: a text file of lines "key nl grid tiles ms", the key
+// naming the library version, the device (architecture and compute units)
+// and the batch's shapes (k and every (m_b, n_b), hashed).  Lines that do not
+// parse, or whose configuration this plan cannot launch, are ignored; a
+// missing or unreadable file means "not cached".
+namespace {
+
+std::string cache_key(const geninv_batch_plan *p) {
+    hipDeviceProp_t prop{};
+    const bool ok = hipGetDeviceProperties(&prop, p->c->device) == hipSuccess;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "geninv%d:%s:%dcu:k%d:b%d:%016llx", geninv_version(), ok ? prop.gcnArchName : "?",
+                  ok ? prop.multiProcessorCount : 0, p->k, p->batch, p->shape_hash);
+    for (char *q = buf; *q; ++q)
+        if (*q == ' ' || *q == '\n') *q = '_';
+    return buf;
+}
+
+bool plan_config_ok(const geninv_batch_plan *p, int nl, int grid, int tiles) {
+    return nl >= 0 && grid >= 1 && grid <= p->max_grid && (tiles == 4 || tiles == 8) && (nl == 0 || nl <= p->nmax) &&
+           batched_lds_bytes(nl, p->nmax, p->k) <= 160 * 1024;
+}
+
+// the cached entry for key, if any (the last valid one wins)
+bool cache_lookup(const char *path, const std::string &key, const geninv_batch_plan *p, int *nl, int *grid,
+                  int *tiles, double *ms) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512], kbuf[300];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        int a = 0, b = 0, t = 0;
+        double x = 0.0;
+        if (std::sscanf(line, "%299s %d %d %d %lf", kbuf, &a, &b, &t, &x) != 5) continue;
+        if (key != kbuf || !plan_config_ok(p, a, b, t) || !(x > 0.0)) continue;
+        *nl = a;
+        *grid = b;
+        *tiles = t;
+        *ms = x;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+// rewrite the file with every other parsable line kept and this key's entry
+// replaced; through a temporary file and a rename, so readers never see a
+// half-written cache.  Failure to write is not an error of the tuning.
+void cache_store(const char *path, const std::string &key, int nl, int grid, int tiles, double ms) {
+    std::vector<std::string> keep;
+    if (FILE *f = std::fopen(path, "r")) {
+        char line[512], kbuf[300];
+        while (std::fgets(line, sizeof line, f)) {
+            int a = 0, b = 0, t = 0;
+            double x = 0.0;
+            if (std::sscanf(line, "%299s %d %d %d %lf", kbuf, &a, &b, &t, &x) != 5 || key == kbuf) continue;
+            std::string l(line);
+            if (l.empty() || l.back() != '\n') l += '\n';
+            keep.push_back(l);
+        }
+        std::fclose(f);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    bool ok = true;
+    for (const auto &l : keep) ok = ok && std::fputs(l.c_str(), f) >= 0;
+    ok = ok && std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), nl, grid, tiles, ms) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
+}
+
+}  // namespace
+
+extern "C" {
+
+// Times every (tile class, LDS threshold, workgroups per CU) candidate `reps`
+// times with events on the context stream and keeps the fastest; with a
+// cache path, a cached entry for this batch is taken instead of timing, and
+// a new result is stored.
+int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, const char *cache_path, int *best_nl, int *best_grid,
+                               int *best_tiles, double *best_ms, int *from_cache) {
     if (!p || reps < 1) return GENINV_EINVAL;
     geninv_ctx *c = p->c;
     DeviceGuard g(c->device);
+    if (from_cache) *from_cache = 0;
+    std::string key;
+    if (cache_path) {
+        key = cache_key(p);
+        int nl = 0, grid = 0, tiles = 0;
+        double ms = 0.0;
+        if (cache_lookup(cache_path, key, p, &nl, &grid, &tiles, &ms)) {
+            CHK(geninv_batch_plan_config(p, nl, grid, tiles));
+            if (best_nl) *best_nl = nl;
+            if (best_grid) *best_grid = grid;
+            if (best_tiles) *best_tiles = tiles;
+            if (best_ms) *best_ms = ms;
+            if (from_cache) *from_cache = 1;
+            return GENINV_OK;
+        }
+    }
     const int cand_nl[] = {128, 96, 64, 48, 32, 0};
     hipEvent_t a = nullptr, b = nullptr;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     double best = 1e300;
-    int bnl = p->nl, bgrid = p->grid;
-    for (int nl : cand_nl) {
-        if (nl > p->nmax && nl != 128) continue;
-        const int nlc = std::min(nl, p->nmax);
-        if (batched_lds_bytes(nlc, p->nmax, p->k) > 160 * 1024) continue;
-        const int w = wgs_per_cu(nlc, p->nmax, p->k);
-        for (int ww = 1; ww <= w; ww *= 2) {
-            const int grid = 256 * ww;
-            plan_drop_graph(p);
-            p->nl = nlc;
-            p->grid = grid;
-            CHK(plan_launch(p, c->stream));   // warm-up
-            std::vector<float> t;
-            for (int r = 0; r < reps; ++r) {
-                HIPCHK(hipEventRecord(a, c->stream));
-                CHK(plan_launch(p, c->stream));
-                HIPCHK(hipEventRecord(b, c->stream));
-                HIPCHK(hipEventSynchronize(b));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, a, b));
-                t.push_back(ms);
-            }
-            std::sort(t.begin(), t.end());
-            const double med = t[t.size() / 2];
-            if (med < best) {
-                best = med;
-                bnl = nlc;
-                bgrid = grid;
+    int bnl = p->nl, bgrid = p->grid, btiles = p->tiles;
+    for (int tiles : {8, 4}) {
+        for (int nl : cand_nl) {
+            if (nl > p->nmax && nl != 128) continue;
+            const int nlc = std::min(nl, p->nmax);
+            if (batched_lds_bytes(nlc, p->nmax, p->k) > 160 * 1024) continue;
+            const int w = wgs_per_cu(nlc, p->nmax, p->k);
+            for (int ww = 1; ww <= w; ww *= 2) {
+                const int grid = 256 * ww;
+                plan_drop_graph(p);
+                p->nl = nlc;
+                p->grid = grid;
+                p->tiles = tiles;
+                CHK(plan_launch(p, c->stream));   // warm-up
+                std::vector<float> t;
+                for (int r = 0; r < reps; ++r) {
+                    HIPCHK(hipEventRecord(a, c->stream));
+                    CHK(plan_launch(p, c->stream));
+                    HIPCHK(hipEventRecord(b, c->stream));
+                    HIPCHK(hipEventSynchronize(b));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, a, b));
+                    t.push_back(ms);
+                }
+                std::sort(t.begin(), t.end());
+                const double med = t[t.size() / 2];
+                if (med < best) {
+                    best = med;
+                    bnl = nlc;
+                    bgrid = grid;
+                    btiles = tiles;
+                }
             }
         }
     }
@@ -2123,8 +2248,11 @@ int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, int *best_nl, int
     plan_drop_graph(p);
     p->nl = bnl;
     p->grid = bgrid;
+    p->tiles = btiles;
+    if (cache_path) cache_store(cache_path, key, bnl, bgrid, btiles, best);
     if (best_nl) *best_nl = bnl;
     if (best_grid) *best_grid = bgrid;
+    if (best_tiles) *best_tiles = btiles;
     if (best_ms) *best_ms = best;
     return GENINV_OK;
 }

@@ -1,5 +1,6 @@
 // Batched least squares W_b = G_b^+ F_b for thousands of small, unevenly sized
-// problems in one persistent launch (Section 1's least-squares use of the
+// problems (either orientation: m_b < n_b takes the Appendix's transpose
+// branch) in one persistent launch (Section 1's least-squares use of the
 // method, Section 4's many small fits; the method itself is the Appendix's).
 //
 // Every workgroup (256 threads) takes problems from a device work queue (an
@@ -7,9 +8,9 @@
 // is empty; all workgroups reach that exit.  One problem runs entirely inside
 // one workgroup:
 //
-//   1. A = G'G and B = G'F, float32 inputs accumulated in float64 (register
-//      tiles of 8 x 4 outputs per thread, G staged through LDS 16 rows at a
-//      time)
+//   1. A = G'G and B = G'F, float32 inputs accumulated in float64 on the
+//      FP64 matrix cores (16 x 16 output tiles, G staged through LDS 16 rows
+//      at a time, the next stage prefetched into registers)
 //   2. tol = 1e-9 min{A_kk > 0} (or the caller's), then the full-rank Cholesky
 //      of A in place, column by column with the paper's strict test
 //   3. C = L'L and T = L'B, as a second Gram product over the kept columns
@@ -29,93 +30,136 @@ constexpr int BT_STAGE_ROWS = 16;
 __device__ __forceinline__ double ldv(const float *p) { return (double)*p; }
 __device__ __forceinline__ double ldv(const double *p) { return *p; }
 
+typedef double bd4 __attribute__((ext_vector_type(4)));
+
 // Lower triangle of X(:, cols)' X(:, cols) into Aout (nc x nc, lda) and
 // X(:, cols)' F into Bout (nc x k, ldb).  cols[c] selects the source column of
 // output column c (identity when cols == nullptr); with `tri`, the source is
-// taken as zero above row cols[c] (a lower trapezoidal factor).
-template <typename T>
+// taken as zero above row cols[c] (a lower trapezoidal factor).  With
+// TRANS, X(row, c) is read as X[c + row ldx] (the Gram matrix of the rows:
+// X X' for a matrix stored nc x rows).
+//
+// On the FP64 matrix cores: the outputs are 16 x 16 tiles (the lower
+// triangle's T(T+1)/2 tiles, T = ceil(nc / 16), then T tiles of X'F), each a
+// chain of v_mfma_f64_16x16x4f64 over the rows; a wavefront owns TPW tiles
+// per pass over the rows (the launch's tile class, 4 or 8: more tiles per
+// pass mean fewer passes over G and more registers).  The rows are staged through LDS 16 at a time as
+// float64 (one row of the stage holds every column of X, then F); each
+// thread loads its share of the next stage into registers while the current
+// one is multiplied.
+constexpr int BG_PF = (BATCH_NMAX + BATCH_KMAX) * BT_STAGE_ROWS / BT_THREADS + 1;   // stage loads per thread
+
+template <int TPW, typename T, bool TRANS>
 __device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *cols, bool tri, const T *F, long ldf,
                            int k, double *Aout, long lda, double *Bout, long ldb, double *stage) {
-    // a thread owns 8 output rows x 4 output columns: tiles (ti, tj) with
-    // 4 tj <= 8 ti + 7 cover the lower triangle of X'X (2 ti + 2 of them in
-    // row block ti), then the blocks of X'F
-    const int tid = threadIdx.x;
-    const int nt = (nc + 7) / 8, kt = (k + 3) / 4;
-    const int tri_tiles = nt * (nt + 1);
-    const int ntiles = tri_tiles + nt * kt;
-    const int sw = nc + k;                 // stage width (columns)
-    for (int base = 0; base < ntiles; base += BT_THREADS) {
-        const int t = base + tid;
-        int ti = 0, tj = 0;
-        bool fcol = false, active = t < ntiles;
-        if (active) {
-            if (t < tri_tiles) {
-                ti = (int)((sqrtf(4.0f * t + 1.0f) - 1.0f) * 0.5f);
-                while (ti * (ti + 1) > t) --ti;
-                while ((ti + 1) * (ti + 2) <= t) ++ti;
-                tj = t - ti * (ti + 1);
+    constexpr int NWV = BT_THREADS / 64;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nt = (nc + 15) >> 4;
+    const int ntri = nt * (nt + 1) / 2;
+    const int ntiles = ntri + (k > 0 ? nt : 0);
+    const int sw = nc + k;                   // stage row length
+    const int li = lane & 15, lk = lane >> 4;
+
+    // stage loads: element q of this thread is row tid % 16 of stage column
+    // tid / 16 + 16 q (16 consecutive rows of a column go to 16 consecutive
+    // lanes: one 64-byte segment per 16 lanes), zero outside X, F or the
+    // trapezoid
+    const int sr = tid % BT_STAGE_ROWS, sc0 = tid / BT_STAGE_ROWS;
+    T px[BG_PF];
+    auto fetch = [&](int k0) {
+        const int row = k0 + sr;
+#pragma unroll
+        for (int q = 0; q < BG_PF; ++q) {
+            const int c = sc0 + (BT_THREADS / BT_STAGE_ROWS) * q;
+            long off = 0;
+            bool ok = row < rows && c < sw;
+            const T *base = X;
+            if (c < nc) {
+                const int src = cols ? cols[c] : c;
+                ok = ok && (!tri || row >= src);
+                off = TRANS ? src + (long)row * ldx : row + (long)src * ldx;
             } else {
-                const int u = t - tri_tiles;
-                ti = u / kt;
-                tj = u % kt;
-                fcol = true;
+                base = F;
+                off = row + (long)(c - nc) * ldf;
+            }
+            const T v = ok ? base[off] : T(0);
+            px[q] = v;
+        }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int q = 0; q < BG_PF; ++q) {
+            const int c = sc0 + (BT_THREADS / BT_STAGE_ROWS) * q;
+            if (c < sw) stage[sr * sw + c] = (double)px[q];
+        }
+    };
+
+    for (int base = 0; base < ntiles; base += NWV * TPW) {
+        // tile coordinates of this wavefront's tiles (uniform): row block ti,
+        // column block tj (-1: the X'F tile of row block ti)
+        int ti[TPW], tj[TPW];
+#pragma unroll
+        for (int j = 0; j < TPW; ++j) {
+            const int t = base + wave + NWV * j;
+            if (t < ntri) {
+                int a = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+                while (a * (a + 1) / 2 > t) --a;
+                while ((a + 1) * (a + 2) / 2 <= t) ++a;
+                ti[j] = a;
+                tj[j] = t - a * (a + 1) / 2;
+            } else {
+                ti[j] = t < ntiles ? t - ntri : -1;
+                tj[j] = -1;
             }
         }
-        double acc[8][4];
+        bd4 acc[TPW];
 #pragma unroll
-        for (int a = 0; a < 8; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int j = 0; j < TPW; ++j) acc[j] = bd4{0.0, 0.0, 0.0, 0.0};
+        fetch(0);
         for (int k0 = 0; k0 < rows; k0 += BT_STAGE_ROWS) {
+            __syncthreads();   // the previous stage's readers are done
+            put();
             __syncthreads();
-            // branch-free loads (clamped address, then select) so that a
-            // thread's loads of the stage issue back to back
-            for (int e = tid; e < BT_STAGE_ROWS * sw; e += BT_THREADS) {
-                const int r = e % BT_STAGE_ROWS, c = e / BT_STAGE_ROWS;
-                const int row = k0 + r;
-                const bool inx = c < nc;
-                const int src = inx ? (cols ? cols[c] : c) : 0;
-                const bool ok = row < rows && (!inx || !tri || row >= src);
-                const T *p = inx ? X + row + (long)src * ldx : F + row + (long)(c - nc) * ldf;
-                const double v = ldv(ok ? p : X);
-                stage[r * sw + c] = ok ? v : 0.0;
-            }
-            __syncthreads();
-            if (active) {
-#pragma unroll 4
-                for (int r = 0; r < BT_STAGE_ROWS; ++r) {
-                    double av[8], bv[4];
-                    const double *srow = stage + r * sw;
+            if (k0 + BT_STAGE_ROWS < rows) fetch(k0 + BT_STAGE_ROWS);   // in flight during the products
+#pragma unroll 1
+            for (int ks = 0; ks < BT_STAGE_ROWS / 4; ++ks) {
+                const double *srow = stage + (4 * ks + lk) * sw;
 #pragma unroll
-                    for (int a = 0; a < 8; ++a) {
-                        const int ci = ti * 8 + a;
-                        av[a] = ci < nc ? srow[ci] : 0.0;
+                for (int j = 0; j < TPW; ++j) {
+                    if (ti[j] < 0) continue;
+                    const int ci = ti[j] * 16 + li;
+                    const double av = srow[min(ci, sw - 1)];
+                    const double a = ci < nc ? av : 0.0;
+                    double b;
+                    if (tj[j] >= 0) {
+                        const int cj = tj[j] * 16 + li;
+                        const double bv = srow[min(cj, sw - 1)];
+                        b = cj < nc ? bv : 0.0;
+                    } else {
+                        const double bv = srow[min(nc + li, sw - 1)];
+                        b = li < k ? bv : 0.0;
                     }
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int cj = fcol ? nc + tj * 4 + b : tj * 4 + b;
-                        bv[b] = (fcol ? (tj * 4 + b < k) : (cj < nc)) ? srow[cj] : 0.0;
-                    }
-#pragma unroll
-                    for (int a = 0; a < 8; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc[j], 0, 0, 0);
                 }
             }
         }
-        if (active) {
+        // lane holds output (row 16 ti + l % 16, column 16 tj + l / 16 + 4 v)
 #pragma unroll
-            for (int a = 0; a < 8; ++a)
+        for (int j = 0; j < TPW; ++j) {
+            if (ti[j] < 0) continue;
+            const int i = ti[j] * 16 + li;
+            if (i >= nc) continue;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int i = ti * 8 + a, j = tj * 4 + b;
-                    if (i >= nc) continue;
-                    if (fcol) {
-                        if (j < k) Bout[i + (long)j * ldb] = acc[a][b];
-                    } else if (j <= i) {
-                        Aout[i + (long)j * lda] = acc[a][b];
-                    }
+            for (int v = 0; v < 4; ++v) {
+                const int q = lk + 4 * v;
+                if (tj[j] >= 0) {
+                    const int c = tj[j] * 16 + q;
+                    if (c <= i) Aout[i + (long)c * lda] = acc[j][v];
+                } else if (q < k) {
+                    Bout[i + (long)q * ldb] = acc[j][v];
                 }
+            }
         }
     }
     __syncthreads();
@@ -415,7 +459,8 @@ struct BatchDesc {
     int pad;
 };
 
-__global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
+template <int TPW>
+__global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
                                                                    int k, double user_tol, int nl, int *queue,
                                                                    double *slabs, long slab_stride, int nmax,
                                                                    int *rank, int *status) {
@@ -456,13 +501,23 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
         if (slot >= batch) break;
         const int b = order[slot];
         const BatchDesc d = desc[b];
-        const int m = d.m, n = d.n;
+        const int m = d.m, nfull = d.n;
+        // the Appendix's transpose branch for m < n: factor G G' (m x m), B = F,
+        // and W = G' (L M M L' F); n below is the order of the factored matrix
+        const bool tr = m < nfull;
+        const int n = tr ? m : nfull;
         if (tid == 0) ints[2] = 0;
 
-        // 1. A = G'G, B = G'F
+        // 1. A = G'G, B = G'F (transpose branch: A = G G', B = F)
         double *A = (n <= nl) ? big : Lg;
         const long lda = n;
-        block_gram<float>(d.G, d.ldg, m, n, nullptr, false, d.F, d.ldf, k, A, lda, Bv, n, stage);
+        if (!tr) {
+            block_gram<TPW, float, false>(d.G, d.ldg, m, n, nullptr, false, d.F, d.ldf, k, A, lda, Bv, n, stage);
+        } else {
+            block_gram<TPW, float, true>(d.G, d.ldg, nfull, n, nullptr, false, d.F, d.ldf, 0, A, lda, Bv, n, stage);
+            for (int e = tid; e < n * k; e += BT_THREADS) Bv[e] = (double)d.F[(e % n) + (long)(e / n) * d.ldf];
+            __syncthreads();
+        }
         // 2. tolerance and full-rank Cholesky in place
         const double tol = block_tol(A, lda, n, user_tol, red, &ints[2]);
         if (ints[2] && tid == 0) *status = ST_NONFINITE;
@@ -473,7 +528,7 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
         if (d.piv)
             for (int c = tid; c < r; c += BT_THREADS) d.piv[c] = cols[c];
         if (r == 0) {
-            for (int e = tid; e < n * k; e += BT_THREADS) d.W[(e % n) + (long)(e / n) * d.ldw] = 0.0;
+            for (int e = tid; e < nfull * k; e += BT_THREADS) d.W[(e % nfull) + (long)(e / nfull) * d.ldw] = 0.0;
             __syncthreads();
             continue;
         }
@@ -485,7 +540,7 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
         // 3. C = L'L (kept columns), T = L'B
         double *C = (r <= nl) ? big : Cg;
         const long ldc = r;
-        block_gram<double>(Lg, n, n, r, cols, true, Bv, n, k, C, ldc, Tv, r, stage);
+        block_gram<TPW, double, false>(Lg, n, n, r, cols, true, Bv, n, k, C, ldc, Tv, r, stage);
         // full symmetric C from its lower triangle
         for (long e = tid; e < (long)r * r; e += BT_THREADS) {
             const int i = (int)(e % r), j = (int)(e / r);
@@ -513,13 +568,26 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
             Tv[i + (long)q * r] = s;
         }
         __syncthreads();
+        // V = L T: W itself, or (transpose branch) V in Xv and W = G' V
+        double *V = tr ? Xv : nullptr;
         for (int e = tid; e < n * k; e += BT_THREADS) {
             const int i = e % n, q = e / n;
             double s = 0.0;
             for (int c = 0; c < r && cols[c] <= i; ++c) s = fma(Lg[i + (long)cols[c] * n], Tv[c + (long)q * r], s);
-            d.W[i + (long)q * d.ldw] = s;
+            if (tr) V[i + (long)q * n] = s;
+            else d.W[i + (long)q * d.ldw] = s;
         }
         __syncthreads();
+        if (tr) {
+            for (int e = tid; e < nfull * k; e += BT_THREADS) {
+                const int j = e % nfull, q = e / nfull;
+                const float *gj = d.G + (long)j * d.ldg;
+                double s = 0.0;
+                for (int i = 0; i < m; ++i) s = fma((double)gj[i], V[i + (long)q * n], s);
+                d.W[j + (long)q * d.ldw] = s;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -537,14 +605,20 @@ size_t batched_slab_doubles(int nmax, int k) {
 }
 
 hipError_t launch_batched(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
-                          double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s) {
+                          double *slabs, int grid, int nmax, int tiles, int *rank, int *status, hipStream_t s) {
+    if (tiles != 4 && tiles != 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = batched_lds_bytes(nl, nmax, k);
-    hipLaunchKernelGGL(batched_lstsq_kernel, dim3(grid), dim3(BT_THREADS), lds, s,
-                       static_cast<const BatchDesc *>(desc), order, batch, k, tol, nl, queue, slabs,
-                       (long)batched_slab_doubles(nmax, k), nmax, rank, status);
+    const long slab = (long)batched_slab_doubles(nmax, k);
+    const BatchDesc *d = static_cast<const BatchDesc *>(desc);
+    if (tiles == 8)
+        hipLaunchKernelGGL(batched_lstsq_kernel<8>, dim3(grid), dim3(BT_THREADS), lds, s, d, order, batch, k, tol, nl,
+                           queue, slabs, slab, nmax, rank, status);
+    else
+        hipLaunchKernelGGL(batched_lstsq_kernel<4>, dim3(grid), dim3(BT_THREADS), lds, s, d, order, batch, k, tol, nl,
+                           queue, slabs, slab, nmax, rank, status);
     return hipGetLastError();
 }
 

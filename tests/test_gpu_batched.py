@@ -86,17 +86,49 @@ def test_one_shot_batched_call_matches_a_plan():
     plan.close()
 
 
-def test_batched_random_uneven_sizes_all_lds_thresholds():
-    print("[case] batched 96 problems", flush=True)
-    B = w.batch_lowrank(96, seed=11, m_hi=600, n_hi=200)
-    plan = api.BatchPlan(B.G, B.F)
-    for nl, grid in [(0, 256), (64, 512), (128, 256)]:
+def test_batched_wide_problems_take_the_transpose_branch():
+    """m_b < n_b (the Appendix's transpose branch: G G' factored, W = G' L M
+    M L' F) mixed with tall problems in one batch, under two launch
+    configurations (G G' in LDS and in the slab); n_b up to 600 with
+    min(m_b, n_b) up to 200, plus wide edge cases (one row, zero, duplicated
+    rows)."""
+    print("[case] batched wide problems", flush=True)
+    rng = np.random.default_rng(23)
+    Gs, Fs = [], []
+    for q in range(40):
+        if q % 2:
+            m = int(rng.integers(16, 200)); n = int(rng.integers(m + 1, 600))
+        else:
+            n = int(rng.integers(16, 200)); m = int(rng.integers(n, 600))
+        r = int(rng.integers(max(1, min(m, n) // 2), min(m, n) + 1))
+        Gs.append((rng.standard_normal((m, r)) @ rng.standard_normal((r, n))).astype(np.float32))
+        Fs.append(rng.standard_normal((m, 4)).astype(np.float32))
+    Gs.append(rng.standard_normal((1, 50)).astype(np.float32)); Fs.append(rng.standard_normal((1, 4)).astype(np.float32))
+    Gs.append(np.zeros((5, 30), np.float32)); Fs.append(rng.standard_normal((5, 4)).astype(np.float32))
+    R = rng.standard_normal((6, 90)).astype(np.float32)
+    Gs.append(np.concatenate([R, R[:2]], axis=0)); Fs.append(rng.standard_normal((8, 4)).astype(np.float32))
+    plan = api.BatchPlan(Gs, Fs)
+    for nl, grid in [(0, 256), (128, 256)]:
         plan.config(nl, grid)
         plan.Wbuf.zero_()
         plan.run(use_graph=False)
         torch.cuda.synchronize()
-        worst = _check(plan, B.G, B.F)
+        worst = _check(plan, Gs, Fs)
         print(f"  nl={nl} grid={grid} worst relF(W)={worst:.2e}", flush=True)
+    plan.close()
+
+
+def test_batched_random_uneven_sizes_all_lds_thresholds():
+    print("[case] batched 96 problems", flush=True)
+    B = w.batch_lowrank(96, seed=11, m_hi=600, n_hi=200)
+    plan = api.BatchPlan(B.G, B.F)
+    for nl, grid, tiles in [(0, 256, 8), (64, 512, 4), (128, 256, 8), (32, 1024, 4)]:
+        plan.config(nl, grid, tiles)
+        plan.Wbuf.zero_()
+        plan.run(use_graph=False)
+        torch.cuda.synchronize()
+        worst = _check(plan, B.G, B.F)
+        print(f"  nl={nl} grid={grid} tiles={tiles} worst relF(W)={worst:.2e}", flush=True)
     plan.close()
 
 
@@ -131,12 +163,49 @@ def test_batched_autotune_picks_a_valid_config():
     print("[case] batched autotune", flush=True)
     B = w.batch_lowrank(128, seed=13, m_hi=500, n_hi=160)
     plan = api.BatchPlan(B.G, B.F)
-    nl, grid, ms = plan.autotune(reps=2)
-    assert grid in (256, 512, 768, 1024) and 0 <= nl <= 128 and ms > 0
+    t = plan.autotune(reps=2)
+    assert t.grid in (256, 512, 768, 1024) and 0 <= t.nl <= 128 and t.tiles in (4, 8) and t.ms > 0
+    assert not t.from_cache and plan.config() == (t.nl, t.grid, t.tiles)
     plan.run(use_graph=False)
     torch.cuda.synchronize()
     _check(plan, B.G, B.F)
     plan.close()
+
+
+def test_batched_autotune_cache(tmp_path):
+    """The tuned configuration is stored under a key of the batch's shapes
+    and taken from the file by a later plan of the same shapes without
+    timing; another batch gets its own entry; a corrupt file (garbage, a
+    line whose configuration cannot launch) is ignored and rewritten."""
+    print("[case] batched autotune cache", flush=True)
+    path = str(tmp_path / "tune.txt")
+    B = w.batch_lowrank(64, seed=17, m_hi=400, n_hi=120)
+    p1 = api.BatchPlan(B.G, B.F)
+    t1 = p1.autotune(reps=1, cache=path)
+    assert not t1.from_cache
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:4] == [str(t1.nl), str(t1.grid), str(t1.tiles)]
+    p2 = api.BatchPlan(B.G, B.F)
+    p2.config(0, 256, 4 if t1.tiles == 8 else 8)
+    t2 = p2.autotune(reps=1, cache=path)
+    assert t2.from_cache and (t2.nl, t2.grid, t2.tiles) == (t1.nl, t1.grid, t1.tiles)
+    assert p2.config() == (t1.nl, t1.grid, t1.tiles)
+    C = w.batch_lowrank(32, seed=19, m_hi=300, n_hi=100)
+    p3 = api.BatchPlan(C.G, C.F)
+    assert not p3.autotune(reps=1, cache=path).from_cache
+    assert len(open(path).read().splitlines()) == 2
+    key = lines[0].split()[0]
+    with open(path, "w") as f:
+        f.write("garbage line\n" + key + " 0 99999 8 1.0\n" + key + " 0 256 5 1.0\n\x00\x01\n")
+    p4 = api.BatchPlan(B.G, B.F)
+    t4 = p4.autotune(reps=1, cache=path)
+    assert not t4.from_cache
+    assert [l.split()[0] for l in open(path).read().splitlines()] == [key]
+    p4.run(use_graph=False)
+    torch.cuda.synchronize()
+    _check(p4, B.G, B.F)
+    for p in (p1, p2, p3, p4):
+        p.close()
 
 
 def test_batched_c4_distribution_against_the_oracle():
