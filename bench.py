@@ -346,8 +346,7 @@ def bench_batched(api, workloads, torch, np, steps, keep_host):
     out = {"workload": "4096 problems, m ~ U[64,1024], n ~ U[16, min(256, m/2)], rank ~ U[n/2, n], G = U V and "
                        "F (m x 4) stored in float32, float64 accumulation and pivots",
            "ms": round(t, 3), "solves_per_s": round(len(B.G) / (t * 1e-3), 1), "tflops": round(flops / t / 1e9, 3),
-           "autotuned": {"lds_threshold": tuned.nl, "workgroups": tuned.grid, "tiles_per_wavefront": tuned.tiles,
-                         "ms": round(tuned.ms, 3)},
+           "autotuned": {"lds_threshold": tuned.nl, "workgroups": tuned.grid, "ms": round(tuned.ms, 3)},
            "rank_equals_construction": int((ranks == B.rank).sum())}
     # the same 4096 problems through the plain float64 form, one geninv_dlstsq
     # call per problem on the library's stream (float32 inputs widened exactly)
@@ -739,7 +738,7 @@ def main():
                     help="only run a plain 1 GiB device copy (reference for hardware byte counters) and exit")
     ap.add_argument("--only-batched", action="store_true",
                     help="only run the 4096-problem batch `steps` times (direct launches, LDS threshold 48, 512 "
-                         "workgroups, 8 tiles per wavefront) "
+                         "workgroups) "
                          "and exit (for hardware counter runs)")
     ap.add_argument("--only-mixed", metavar="KEY",
                     help="only run one mixed-form variant (e.g. int8_m16) on the headline workload `steps` "
@@ -773,7 +772,7 @@ def main():
     if args.only_batched:
         B = workloads.c4_problem()
         plan = api.BatchPlan(B.G, B.F)
-        plan.config(48, 512, 8)
+        plan.config(48, 512)
         for _ in range(args.warmup):
             plan.run(use_graph=False)
         t = _timed(lambda: plan.run(use_graph=False), args.steps, torch.cuda.synchronize)

@@ -387,8 +387,9 @@ int geninv_bchain(geninv_ctx *ctx, int n, int m, int k, const double *P, int ldp
  * and G'F with float64 accumulation, tol, full-rank Cholesky, (L'L)^-1,
  * W = L M M L' G'F).
  *   m, n, ldg, ldf, ldw   HOST int[batch]; 1 <= min(m_b, n_b) <= 256 (m_b < n_b
- *                         takes the Appendix's transpose branch: G_b G_b' is
- *                         factored and W_b = G_b' L M M L' F_b)
+ *                         takes the Appendix's transpose branch, in a second
+ *                         persistent launch after the tall problems': G_b G_b'
+ *                         is factored and W_b = G_b' L M M L' F_b)
  *   G, F                  HOST arrays of DEVICE pointers: G_b m_b x n_b and
  *                         F_b m_b x k, float32, column-major
  *   W                     HOST array of DEVICE pointers: W_b n_b x k, float64
@@ -415,19 +416,18 @@ int geninv_batch_plan_destroy(geninv_batch_plan *plan);
 int geninv_batch_plan_run(geninv_batch_plan *plan, int use_graph);
 int geninv_batch_plan_graph_fallbacks(const geninv_batch_plan *plan);
 
-/* Autotuner: times each launch configuration (tile class: 4 or 8 Gram tiles
- * of 16 x 16 per wavefront and pass; LDS threshold below which a problem's
- * Gram matrix and L'L live in LDS; workgroups per compute unit) `reps` times
- * and keeps the fastest.  cache_path (or NULL): a text file of tuned
- * configurations keyed by the library version, the device and the batch's
- * shapes; an entry for this batch is applied without timing (*from_cache =
- * 1), otherwise the result is stored there (through a temporary file and a
- * rename).  Unparsable or inapplicable lines are ignored and a missing,
- * unreadable or unwritable file only means tuning (the plan keeps working
- * with the tuned or default configuration).  Outputs may be NULL.
- * Synchronizes. */
+/* Autotuner: times each launch configuration (LDS threshold below which a
+ * problem's Gram matrix and L'L live in LDS; workgroups per compute unit)
+ * `reps` times and keeps the fastest.  cache_path (or NULL): a text file of
+ * tuned configurations, one line "key nl grid ms" per batch, the key naming
+ * the library version, the device and the batch's shapes; an entry for this
+ * batch is applied without timing (*from_cache = 1), otherwise the result is
+ * stored there (through a temporary file and a rename).  Unparsable or
+ * inapplicable lines are ignored and a missing, unreadable or unwritable file
+ * only means tuning (the plan keeps working with the tuned or default
+ * configuration).  Outputs may be NULL.  Synchronizes. */
 int geninv_batch_plan_autotune(geninv_batch_plan *plan, int reps, const char *cache_path, int *best_nl,
-                               int *best_grid, int *best_tiles, double *best_ms, int *from_cache);
+                               int *best_grid, double *best_ms, int *from_cache);
 
 /* One-shot form of the batched solve, with the arguments of
  * geninv_batch_plan_create: builds a plan with the default launch
@@ -450,10 +450,10 @@ int geninv_lstsq_batched(geninv_ctx *ctx, int batch, const int *m, const int *n,
 int geninv_batch_plan_set_pivots(geninv_batch_plan *plan, int *const *piv);
 
 /* Set or read the launch configuration directly: LDS threshold nl, grid
- * workgroups (<= 1024), tile class (4 or 8).  EINVAL for a configuration
- * whose LDS does not fit a compute unit. */
-int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid, int tiles);
-int geninv_batch_plan_get_config(geninv_batch_plan *plan, int *nl, int *grid, int *tiles);
+ * workgroups (<= 1024).  EINVAL for a configuration whose LDS does not fit
+ * a compute unit. */
+int geninv_batch_plan_config(geninv_batch_plan *plan, int nl, int grid);
+int geninv_batch_plan_get_config(geninv_batch_plan *plan, int *nl, int *grid);
 
 /* ---- event timers ------------------------------------------------------- */
 

@@ -95,11 +95,11 @@ _SIGS = [
                                             ctypes.c_double, ctypes.POINTER(_VP), _c_int_p, _VP, _c_int_p]),
     ("geninv_batch_plan_run", ctypes.c_int, [_VP, ctypes.c_int]),
     ("geninv_batch_plan_graph_fallbacks", ctypes.c_int, [_VP]),
-    ("geninv_batch_plan_autotune", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_char_p, _c_int_p, _c_int_p, _c_int_p,
+    ("geninv_batch_plan_autotune", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_char_p, _c_int_p, _c_int_p,
                                                   ctypes.POINTER(ctypes.c_double), _c_int_p]),
     ("geninv_batch_plan_set_pivots", ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
-    ("geninv_batch_plan_config", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
-    ("geninv_batch_plan_get_config", ctypes.c_int, [_VP, _c_int_p, _c_int_p, _c_int_p]),
+    ("geninv_batch_plan_config", ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int]),
+    ("geninv_batch_plan_get_config", ctypes.c_int, [_VP, _c_int_p, _c_int_p]),
     ("geninv_prof_classes", ctypes.c_int, []),
     ("geninv_prof_name", ctypes.c_char_p, [ctypes.c_int]),
     ("geninv_prof_enable", ctypes.c_int, [_VP, ctypes.c_uint]),

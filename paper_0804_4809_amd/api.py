@@ -463,7 +463,6 @@ class _PackedBatch:
 class AutotuneResult(NamedTuple):
     nl: int
     grid: int
-    tiles: int
     ms: float
     from_cache: bool
 
@@ -512,28 +511,24 @@ class BatchPlan(_PackedBatch):
         return int(self._lib.geninv_batch_plan_graph_fallbacks(self._plan))
 
     def autotune(self, reps: int = 3, cache: str | None = None):
-        """geninv_batch_plan_autotune: (nl, grid, tiles, ms, from_cache)."""
+        """geninv_batch_plan_autotune: (nl, grid, ms, from_cache)."""
         _ctx(self.device)
-        nl, grid, tiles, fc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        nl, grid, fc = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
         ms = ctypes.c_double(0.0)
         path = None if cache is None else os.fsencode(cache)
         _check(self._lib.geninv_batch_plan_autotune(self._plan, reps, path, ctypes.byref(nl), ctypes.byref(grid),
-                                                    ctypes.byref(tiles), ctypes.byref(ms), ctypes.byref(fc)),
-               "geninv_batch_plan_autotune")
-        return AutotuneResult(nl.value, grid.value, tiles.value, ms.value, bool(fc.value))
+                                                    ctypes.byref(ms), ctypes.byref(fc)), "geninv_batch_plan_autotune")
+        return AutotuneResult(nl.value, grid.value, ms.value, bool(fc.value))
 
-    def config(self, nl: int | None = None, grid: int | None = None, tiles: int | None = None):
-        """Set (when nl and grid are given; tiles defaults to the current
-        class) and return the launch configuration (nl, grid, tiles)."""
+    def config(self, nl: int | None = None, grid: int | None = None):
+        """Set (when nl and grid are given) and return the launch
+        configuration (nl, grid)."""
         if nl is not None and grid is not None:
-            if tiles is None:
-                tiles = self.config()[2]
-            _check(self._lib.geninv_batch_plan_config(self._plan, int(nl), int(grid), int(tiles)),
-                   "geninv_batch_plan_config")
-        a, b, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-        _check(self._lib.geninv_batch_plan_get_config(self._plan, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)),
+            _check(self._lib.geninv_batch_plan_config(self._plan, int(nl), int(grid)), "geninv_batch_plan_config")
+        a, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check(self._lib.geninv_batch_plan_get_config(self._plan, ctypes.byref(a), ctypes.byref(b)),
                "geninv_batch_plan_get_config")
-        return a.value, b.value, t.value
+        return a.value, b.value
 
     def close(self):
         if getattr(self, "_plan", None):

@@ -1882,7 +1882,7 @@ struct geninv_batch_plan {
     int max_grid = 0;
     int *rank = nullptr;         // caller's device int[batch]
     int nl = 0, grid = 0;        // LDS threshold and workgroups (autotuned)
-    int tiles = 8;               // Gram tiles per wavefront and pass (tile class, autotuned)
+    int ntall = 0;               // order[0 .. ntall): tall problems (m >= n); the rest wide (m < n)
     unsigned long long shape_hash = 0;   // FNV-1a of k and every (m_b, n_b): the autotune cache key
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1900,10 +1900,15 @@ void plan_drop_graph(geninv_batch_plan *p) {
     p->graph_stream = nullptr;
 }
 
+// tall problems, then (same slabs, same stream) the wide ones; each launch
+// has its own queue counter
 int plan_launch(geninv_batch_plan *p, hipStream_t s) {
-    HIPCHK(launch_batched(p->desc, p->order, p->batch, p->k, p->tol, p->nl, p->queue, p->slabs, p->grid, p->nmax,
-                          p->tiles,
-                          p->rank, p->c->status, s));
+    if (p->ntall > 0)
+        HIPCHK(launch_batched(p->desc, p->order, p->ntall, p->k, p->tol, p->nl, p->queue, p->slabs, p->grid, p->nmax,
+                              p->rank, p->c->status, s));
+    if (p->batch > p->ntall)
+        HIPCHK(launch_batched_wide(p->desc, p->order + p->ntall, p->batch - p->ntall, p->k, p->tol, p->nl,
+                                   p->queue + 16, p->slabs, p->grid, p->nmax, p->rank, p->c->status, s));
     return GENINV_OK;
 }
 
@@ -1956,15 +1961,21 @@ int geninv_batch_plan_create(geninv_ctx *c, geninv_batch_plan **plan, int batch,
         }
         p->shape_hash = h;
     }
-    // largest-first order: estimated work max(m, n) nn^2 + nn^3 with nn =
-    // min(m, n) (Gram, then factorization and inverse)
+    // the tall problems, then the wide ones (two launches), each largest
+    // first: estimated work max(m, n) nn^2 + nn^3 with nn = min(m, n) (Gram,
+    // then factorization and inverse)
     std::vector<int> order(batch);
     std::iota(order.begin(), order.end(), 0);
     auto work = [&](int q) {
         const double a = std::max(m[q], n[q]), o = std::min(m[q], n[q]);
         return a * o * o + o * o * o;
     };
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const bool ta = m[a] >= n[a], tb = m[b] >= n[b];
+        return ta != tb ? ta : work(a) > work(b);
+    });
+    p->ntall = 0;
+    for (int b = 0; b < batch; ++b) p->ntall += m[b] >= n[b] ? 1 : 0;
     std::vector<char> desc(batched_desc_bytes() * std::max(batch, 1));
     for (int b = 0; b < batch; ++b)
         batched_fill_desc(desc.data() + b * batched_desc_bytes(), G[b], F[b], W[b], m[b], n[b], ldg[b], ldf[b], ldw[b]);
@@ -2035,21 +2046,19 @@ int geninv_batch_plan_set_pivots(geninv_batch_plan *p, int *const *piv) {
     return GENINV_OK;
 }
 
-int geninv_batch_plan_config(geninv_batch_plan *p, int nl, int grid, int tiles) {
-    if (!p || nl < 0 || grid < 1 || grid > p->max_grid || (tiles != 4 && tiles != 8)) return GENINV_EINVAL;
+int geninv_batch_plan_config(geninv_batch_plan *p, int nl, int grid) {
+    if (!p || nl < 0 || grid < 1 || grid > p->max_grid) return GENINV_EINVAL;
     if (batched_lds_bytes(nl, p->nmax, p->k) > 160 * 1024) return GENINV_EINVAL;
-    if (nl != p->nl || grid != p->grid || tiles != p->tiles) plan_drop_graph(p);
+    if (nl != p->nl || grid != p->grid) plan_drop_graph(p);
     p->nl = nl;
     p->grid = grid;
-    p->tiles = tiles;
     return GENINV_OK;
 }
 
-int geninv_batch_plan_get_config(geninv_batch_plan *p, int *nl, int *grid, int *tiles) {
+int geninv_batch_plan_get_config(geninv_batch_plan *p, int *nl, int *grid) {
     if (!p) return GENINV_EINVAL;
     if (nl) *nl = p->nl;
     if (grid) *grid = p->grid;
-    if (tiles) *tiles = p->tiles;
     return GENINV_OK;
 }
 
@@ -2102,7 +2111,7 @@ int geninv_batch_plan_graph_fallbacks(const geninv_batch_plan *p) { return p ? p
 
 }  // extern "C"
 
-// The autotune cache: a text file of lines "key nl grid tiles ms", the key
+// The autotune cache: a text file of lines "key nl grid ms", the key
 // naming the library version, the device (architecture and compute units)
 // and the batch's shapes (k and every (m_b, n_b), hashed).  Lines that do not
 // parse, or whose configuration this plan cannot launch, are ignored; a
@@ -2120,26 +2129,32 @@ std::string cache_key(const geninv_batch_plan *p) {
     return buf;
 }
 
-bool plan_config_ok(const geninv_batch_plan *p, int nl, int grid, int tiles) {
-    return nl >= 0 && grid >= 1 && grid <= p->max_grid && (tiles == 4 || tiles == 8) && (nl == 0 || nl <= p->nmax) &&
+bool plan_config_ok(const geninv_batch_plan *p, int nl, int grid) {
+    return nl >= 0 && grid >= 1 && grid <= p->max_grid && (nl == 0 || nl <= p->nmax) &&
            batched_lds_bytes(nl, p->nmax, p->k) <= 160 * 1024;
 }
 
 // the cached entry for key, if any (the last valid one wins)
+// one cache line "key nl grid ms" (exactly four fields)
+bool cache_parse(const char *line, char *kbuf, int *nl, int *grid, double *ms) {
+    int pos = -1;
+    if (std::sscanf(line, "%299s %d %d %lf %n", kbuf, nl, grid, ms, &pos) != 4 || pos < 0) return false;
+    return line[pos] == '\0';
+}
+
 bool cache_lookup(const char *path, const std::string &key, const geninv_batch_plan *p, int *nl, int *grid,
-                  int *tiles, double *ms) {
+                  double *ms) {
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
     char line[512], kbuf[300];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
-        int a = 0, b = 0, t = 0;
+        int a = 0, b = 0;
         double x = 0.0;
-        if (std::sscanf(line, "%299s %d %d %d %lf", kbuf, &a, &b, &t, &x) != 5) continue;
-        if (key != kbuf || !plan_config_ok(p, a, b, t) || !(x > 0.0)) continue;
+        if (!cache_parse(line, kbuf, &a, &b, &x)) continue;
+        if (key != kbuf || !plan_config_ok(p, a, b) || !(x > 0.0)) continue;
         *nl = a;
         *grid = b;
-        *tiles = t;
         *ms = x;
         found = true;
     }
@@ -2150,14 +2165,14 @@ bool cache_lookup(const char *path, const std::string &key, const geninv_batch_p
 // rewrite the file with every other parsable line kept and this key's entry
 // replaced; through a temporary file and a rename, so readers never see a
 // half-written cache.  Failure to write is not an error of the tuning.
-void cache_store(const char *path, const std::string &key, int nl, int grid, int tiles, double ms) {
+void cache_store(const char *path, const std::string &key, int nl, int grid, double ms) {
     std::vector<std::string> keep;
     if (FILE *f = std::fopen(path, "r")) {
         char line[512], kbuf[300];
         while (std::fgets(line, sizeof line, f)) {
-            int a = 0, b = 0, t = 0;
+            int a = 0, b = 0;
             double x = 0.0;
-            if (std::sscanf(line, "%299s %d %d %d %lf", kbuf, &a, &b, &t, &x) != 5 || key == kbuf) continue;
+            if (!cache_parse(line, kbuf, &a, &b, &x) || key == kbuf) continue;
             std::string l(line);
             if (l.empty() || l.back() != '\n') l += '\n';
             keep.push_back(l);
@@ -2169,7 +2184,7 @@ void cache_store(const char *path, const std::string &key, int nl, int grid, int
     if (!f) return;
     bool ok = true;
     for (const auto &l : keep) ok = ok && std::fputs(l.c_str(), f) >= 0;
-    ok = ok && std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), nl, grid, tiles, ms) > 0;
+    ok = ok && std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), nl, grid, ms) > 0;
     ok = (std::fclose(f) == 0) && ok;
     if (!ok || std::rename(tmp.c_str(), path) != 0) std::remove(tmp.c_str());
 }
@@ -2178,12 +2193,12 @@ void cache_store(const char *path, const std::string &key, int nl, int grid, int
 
 extern "C" {
 
-// Times every (tile class, LDS threshold, workgroups per CU) candidate `reps`
+// Times every (LDS threshold, workgroups per CU) candidate `reps`
 // times with events on the context stream and keeps the fastest; with a
 // cache path, a cached entry for this batch is taken instead of timing, and
 // a new result is stored.
 int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, const char *cache_path, int *best_nl, int *best_grid,
-                               int *best_tiles, double *best_ms, int *from_cache) {
+                               double *best_ms, int *from_cache) {
     if (!p || reps < 1) return GENINV_EINVAL;
     geninv_ctx *c = p->c;
     DeviceGuard g(c->device);
@@ -2191,13 +2206,12 @@ int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, const char *cache
     std::string key;
     if (cache_path) {
         key = cache_key(p);
-        int nl = 0, grid = 0, tiles = 0;
+        int nl = 0, grid = 0;
         double ms = 0.0;
-        if (cache_lookup(cache_path, key, p, &nl, &grid, &tiles, &ms)) {
-            CHK(geninv_batch_plan_config(p, nl, grid, tiles));
+        if (cache_lookup(cache_path, key, p, &nl, &grid, &ms)) {
+            CHK(geninv_batch_plan_config(p, nl, grid));
             if (best_nl) *best_nl = nl;
             if (best_grid) *best_grid = grid;
-            if (best_tiles) *best_tiles = tiles;
             if (best_ms) *best_ms = ms;
             if (from_cache) *from_cache = 1;
             return GENINV_OK;
@@ -2208,38 +2222,34 @@ int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, const char *cache
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     double best = 1e300;
-    int bnl = p->nl, bgrid = p->grid, btiles = p->tiles;
-    for (int tiles : {8, 4}) {
-        for (int nl : cand_nl) {
-            if (nl > p->nmax && nl != 128) continue;
-            const int nlc = std::min(nl, p->nmax);
-            if (batched_lds_bytes(nlc, p->nmax, p->k) > 160 * 1024) continue;
-            const int w = wgs_per_cu(nlc, p->nmax, p->k);
-            for (int ww = 1; ww <= w; ww *= 2) {
-                const int grid = 256 * ww;
-                plan_drop_graph(p);
-                p->nl = nlc;
-                p->grid = grid;
-                p->tiles = tiles;
-                CHK(plan_launch(p, c->stream));   // warm-up
-                std::vector<float> t;
-                for (int r = 0; r < reps; ++r) {
-                    HIPCHK(hipEventRecord(a, c->stream));
-                    CHK(plan_launch(p, c->stream));
-                    HIPCHK(hipEventRecord(b, c->stream));
-                    HIPCHK(hipEventSynchronize(b));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, a, b));
-                    t.push_back(ms);
-                }
-                std::sort(t.begin(), t.end());
-                const double med = t[t.size() / 2];
-                if (med < best) {
-                    best = med;
-                    bnl = nlc;
-                    bgrid = grid;
-                    btiles = tiles;
-                }
+    int bnl = p->nl, bgrid = p->grid;
+    for (int nl : cand_nl) {
+        if (nl > p->nmax && nl != 128) continue;
+        const int nlc = std::min(nl, p->nmax);
+        if (batched_lds_bytes(nlc, p->nmax, p->k) > 160 * 1024) continue;
+        const int w = wgs_per_cu(nlc, p->nmax, p->k);
+        for (int ww = 1; ww <= w; ww *= 2) {
+            const int grid = 256 * ww;
+            plan_drop_graph(p);
+            p->nl = nlc;
+            p->grid = grid;
+            CHK(plan_launch(p, c->stream));   // warm-up
+            std::vector<float> t;
+            for (int r = 0; r < reps; ++r) {
+                HIPCHK(hipEventRecord(a, c->stream));
+                CHK(plan_launch(p, c->stream));
+                HIPCHK(hipEventRecord(b, c->stream));
+                HIPCHK(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, a, b));
+                t.push_back(ms);
+            }
+            std::sort(t.begin(), t.end());
+            const double med = t[t.size() / 2];
+            if (med < best) {
+                best = med;
+                bnl = nlc;
+                bgrid = grid;
             }
         }
     }
@@ -2248,11 +2258,9 @@ int geninv_batch_plan_autotune(geninv_batch_plan *p, int reps, const char *cache
     plan_drop_graph(p);
     p->nl = bnl;
     p->grid = bgrid;
-    p->tiles = btiles;
-    if (cache_path) cache_store(cache_path, key, bnl, bgrid, btiles, best);
+    if (cache_path) cache_store(cache_path, key, bnl, bgrid, best);
     if (best_nl) *best_nl = bnl;
     if (best_grid) *best_grid = bgrid;
-    if (best_tiles) *best_tiles = btiles;
     if (best_ms) *best_ms = best;
     return GENINV_OK;
 }

@@ -1,16 +1,17 @@
 // Batched least squares W_b = G_b^+ F_b for thousands of small, unevenly sized
-// problems (either orientation: m_b < n_b takes the Appendix's transpose
-// branch) in one persistent launch (Section 1's least-squares use of the
+// problems in one persistent launch (Section 1's least-squares use of the
 // method, Section 4's many small fits; the method itself is the Appendix's).
+// This launch takes the tall problems (m_b >= n_b); wide ones run in a second
+// persistent launch with the Appendix's transpose branch (end of the file).
 //
 // Every workgroup (256 threads) takes problems from a device work queue (an
 // atomic counter over a host-computed order, largest first) until the queue
 // is empty; all workgroups reach that exit.  One problem runs entirely inside
 // one workgroup:
 //
-//   1. A = G'G and B = G'F, float32 inputs accumulated in float64 on the
-//      FP64 matrix cores (16 x 16 output tiles, G staged through LDS 16 rows
-//      at a time, the next stage prefetched into registers)
+//   1. A = G'G and B = G'F, float32 inputs accumulated in float64 (register
+//      tiles of 8 x 4 outputs per thread, G staged through LDS 16 rows at a
+//      time)
 //   2. tol = 1e-9 min{A_kk > 0} (or the caller's), then the full-rank Cholesky
 //      of A in place, column by column with the paper's strict test
 //   3. C = L'L and T = L'B, as a second Gram product over the kept columns
@@ -30,143 +31,100 @@ constexpr int BT_STAGE_ROWS = 16;
 __device__ __forceinline__ double ldv(const float *p) { return (double)*p; }
 __device__ __forceinline__ double ldv(const double *p) { return *p; }
 
-typedef double bd4 __attribute__((ext_vector_type(4)));
-
 // Lower triangle of X(:, cols)' X(:, cols) into Aout (nc x nc, lda) and
 // X(:, cols)' F into Bout (nc x k, ldb).  cols[c] selects the source column of
 // output column c (identity when cols == nullptr); with `tri`, the source is
-// taken as zero above row cols[c] (a lower trapezoidal factor).  With
-// TRANS, X(row, c) is read as X[c + row ldx] (the Gram matrix of the rows:
-// X X' for a matrix stored nc x rows).
-//
-// On the FP64 matrix cores: the outputs are 16 x 16 tiles (the lower
-// triangle's T(T+1)/2 tiles, T = ceil(nc / 16), then T tiles of X'F), each a
-// chain of v_mfma_f64_16x16x4f64 over the rows; a wavefront owns TPW tiles
-// per pass over the rows (the launch's tile class, 4 or 8: more tiles per
-// pass mean fewer passes over G and more registers).  The rows are staged through LDS 16 at a time as
-// float64 (one row of the stage holds every column of X, then F); each
-// thread loads its share of the next stage into registers while the current
-// one is multiplied.
-constexpr int BG_PF = (BATCH_NMAX + BATCH_KMAX) * BT_STAGE_ROWS / BT_THREADS + 1;   // stage loads per thread
-
-template <int TPW, typename T, bool TRANS>
-__device__ void block_gram(const T *X, long ldx, int rows, int nc, const int *cols, bool tri, const T *F, long ldf,
+// taken as zero above row cols[c] (a lower trapezoidal factor).
+template <typename T>
+__device__ __forceinline__ void block_gram(const T *X, long ldx, int rows, int nc, const int *cols, bool tri, const T *F, long ldf,
                            int k, double *Aout, long lda, double *Bout, long ldb, double *stage) {
-    constexpr int NWV = BT_THREADS / 64;
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nt = (nc + 15) >> 4;
-    const int ntri = nt * (nt + 1) / 2;
-    const int ntiles = ntri + (k > 0 ? nt : 0);
-    const int sw = nc + k;                   // stage row length
-    const int li = lane & 15, lk = lane >> 4;
-
-    // stage loads: element q of this thread is row tid % 16 of stage column
-    // tid / 16 + 16 q (16 consecutive rows of a column go to 16 consecutive
-    // lanes: one 64-byte segment per 16 lanes), zero outside X, F or the
-    // trapezoid
-    const int sr = tid % BT_STAGE_ROWS, sc0 = tid / BT_STAGE_ROWS;
-    T px[BG_PF];
-    auto fetch = [&](int k0) {
-        const int row = k0 + sr;
-#pragma unroll
-        for (int q = 0; q < BG_PF; ++q) {
-            const int c = sc0 + (BT_THREADS / BT_STAGE_ROWS) * q;
-            long off = 0;
-            bool ok = row < rows && c < sw;
-            const T *base = X;
-            if (c < nc) {
-                const int src = cols ? cols[c] : c;
-                ok = ok && (!tri || row >= src);
-                off = TRANS ? src + (long)row * ldx : row + (long)src * ldx;
+    // a thread owns 8 output rows x 4 output columns: tiles (ti, tj) with
+    // 4 tj <= 8 ti + 7 cover the lower triangle of X'X (2 ti + 2 of them in
+    // row block ti), then the blocks of X'F
+    const int tid = threadIdx.x;
+    const int nt = (nc + 7) / 8, kt = (k + 3) / 4;
+    const int tri_tiles = nt * (nt + 1);
+    const int ntiles = tri_tiles + nt * kt;
+    const int sw = nc + k;                 // stage width (columns)
+    for (int base = 0; base < ntiles; base += BT_THREADS) {
+        const int t = base + tid;
+        int ti = 0, tj = 0;
+        bool fcol = false, active = t < ntiles;
+        if (active) {
+            if (t < tri_tiles) {
+                ti = (int)((sqrtf(4.0f * t + 1.0f) - 1.0f) * 0.5f);
+                while (ti * (ti + 1) > t) --ti;
+                while ((ti + 1) * (ti + 2) <= t) ++ti;
+                tj = t - ti * (ti + 1);
             } else {
-                base = F;
-                off = row + (long)(c - nc) * ldf;
-            }
-            const T v = ok ? base[off] : T(0);
-            px[q] = v;
-        }
-    };
-    auto put = [&]() {
-#pragma unroll
-        for (int q = 0; q < BG_PF; ++q) {
-            const int c = sc0 + (BT_THREADS / BT_STAGE_ROWS) * q;
-            if (c < sw) stage[sr * sw + c] = (double)px[q];
-        }
-    };
-
-    for (int base = 0; base < ntiles; base += NWV * TPW) {
-        // tile coordinates of this wavefront's tiles (uniform): row block ti,
-        // column block tj (-1: the X'F tile of row block ti)
-        int ti[TPW], tj[TPW];
-#pragma unroll
-        for (int j = 0; j < TPW; ++j) {
-            const int t = base + wave + NWV * j;
-            if (t < ntri) {
-                int a = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-                while (a * (a + 1) / 2 > t) --a;
-                while ((a + 1) * (a + 2) / 2 <= t) ++a;
-                ti[j] = a;
-                tj[j] = t - a * (a + 1) / 2;
-            } else {
-                ti[j] = t < ntiles ? t - ntri : -1;
-                tj[j] = -1;
+                const int u = t - tri_tiles;
+                ti = u / kt;
+                tj = u % kt;
+                fcol = true;
             }
         }
-        bd4 acc[TPW];
+        double acc[8][4];
 #pragma unroll
-        for (int j = 0; j < TPW; ++j) acc[j] = bd4{0.0, 0.0, 0.0, 0.0};
-        fetch(0);
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
         for (int k0 = 0; k0 < rows; k0 += BT_STAGE_ROWS) {
-            __syncthreads();   // the previous stage's readers are done
-            put();
             __syncthreads();
-            if (k0 + BT_STAGE_ROWS < rows) fetch(k0 + BT_STAGE_ROWS);   // in flight during the products
-#pragma unroll 1
-            for (int ks = 0; ks < BT_STAGE_ROWS / 4; ++ks) {
-                const double *srow = stage + (4 * ks + lk) * sw;
+            // branch-free loads (clamped address, then select) so that a
+            // thread's loads of the stage issue back to back
+            for (int e = tid; e < BT_STAGE_ROWS * sw; e += BT_THREADS) {
+                const int r = e % BT_STAGE_ROWS, c = e / BT_STAGE_ROWS;
+                const int row = k0 + r;
+                const bool inx = c < nc;
+                const int src = inx ? (cols ? cols[c] : c) : 0;
+                const bool ok = row < rows && (!inx || !tri || row >= src);
+                const T *p = inx ? X + row + (long)src * ldx : F + row + (long)(c - nc) * ldf;
+                const double v = ldv(ok ? p : X);
+                stage[r * sw + c] = ok ? v : 0.0;
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll 4
+                for (int r = 0; r < BT_STAGE_ROWS; ++r) {
+                    double av[8], bv[4];
+                    const double *srow = stage + r * sw;
 #pragma unroll
-                for (int j = 0; j < TPW; ++j) {
-                    if (ti[j] < 0) continue;
-                    const int ci = ti[j] * 16 + li;
-                    const double av = srow[min(ci, sw - 1)];
-                    const double a = ci < nc ? av : 0.0;
-                    double b;
-                    if (tj[j] >= 0) {
-                        const int cj = tj[j] * 16 + li;
-                        const double bv = srow[min(cj, sw - 1)];
-                        b = cj < nc ? bv : 0.0;
-                    } else {
-                        const double bv = srow[min(nc + li, sw - 1)];
-                        b = li < k ? bv : 0.0;
+                    for (int a = 0; a < 8; ++a) {
+                        const int ci = ti * 8 + a;
+                        av[a] = ci < nc ? srow[ci] : 0.0;
                     }
-                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc[j], 0, 0, 0);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int cj = fcol ? nc + tj * 4 + b : tj * 4 + b;
+                        bv[b] = (fcol ? (tj * 4 + b < k) : (cj < nc)) ? srow[cj] : 0.0;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 8; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
                 }
             }
         }
-        // lane holds output (row 16 ti + l % 16, column 16 tj + l / 16 + 4 v)
+        if (active) {
 #pragma unroll
-        for (int j = 0; j < TPW; ++j) {
-            if (ti[j] < 0) continue;
-            const int i = ti[j] * 16 + li;
-            if (i >= nc) continue;
+            for (int a = 0; a < 8; ++a)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int q = lk + 4 * v;
-                if (tj[j] >= 0) {
-                    const int c = tj[j] * 16 + q;
-                    if (c <= i) Aout[i + (long)c * lda] = acc[j][v];
-                } else if (q < k) {
-                    Bout[i + (long)q * ldb] = acc[j][v];
+                for (int b = 0; b < 4; ++b) {
+                    const int i = ti * 8 + a, j = tj * 4 + b;
+                    if (i >= nc) continue;
+                    if (fcol) {
+                        if (j < k) Bout[i + (long)j * ldb] = acc[a][b];
+                    } else if (j <= i) {
+                        Aout[i + (long)j * lda] = acc[a][b];
+                    }
                 }
-            }
         }
     }
     __syncthreads();
 }
 
 // tol (<= 0: paper default), returns the threshold; also flags non-finite diagonals
-__device__ double block_tol(const double *A, long lda, int n, double user_tol, double *red, int *bad) {
+__device__ __forceinline__ double block_tol(const double *A, long lda, int n, double user_tol, double *red, int *bad) {
     const int tid = threadIdx.x;
     double mn = __builtin_huge_val();
     int b = 0;
@@ -192,7 +150,7 @@ __device__ double block_tol(const double *A, long lda, int n, double user_tol, d
 // full-rank Cholesky in place on the lower triangle of A (n x n): column j
 // kept iff its updated pivot is > tol.  Kept columns hold L (rows >= j), the
 // others are zeroed.  cols[] receives the kept column indices; returns r.
-__device__ int block_frchol(double *A, long lda, int n, double tol, int *cols, int *cnt) {
+__device__ __forceinline__ int block_frchol(double *A, long lda, int n, double tol, int *cols, int *cnt) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) *cnt = 0;
     for (int j = 0; j < n; ++j) {
@@ -232,7 +190,7 @@ __device__ int block_frchol(double *A, long lda, int n, double tol, int *cols, i
 // tiles) instead of one update per column.  Decisions and kept values are
 // those of the column-by-column form up to the grouping of the updates.
 template <int NB>
-__device__ int block_frchol_blocked(double *A, long lda, int n, double tol, int *cols, int *cnt, double *ws) {
+__device__ __forceinline__ int block_frchol_blocked(double *A, long lda, int n, double tol, int *cols, int *cnt, double *ws) {
     const int tid = threadIdx.x;
     double *Ps = ws;   // Ps[i * NB + c] = A(i, j0 + c)
     if (tid == 0) *cnt = 0;
@@ -310,7 +268,7 @@ __device__ int block_frchol_blocked(double *A, long lda, int n, double tol, int 
 
 // in-place Gauss-Jordan inverse of the SPD matrix C (r x r, full storage);
 // returns false if a pivot is not positive
-__device__ bool block_gj(double *C, long ldc, int r, double *rowp, double *colp) {
+__device__ __forceinline__ bool block_gj(double *C, long ldc, int r, double *rowp, double *colp) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     bool ok = true;
     for (int p = 0; p < r; ++p) {
@@ -346,7 +304,7 @@ __device__ bool block_gj(double *C, long ldc, int r, double *rowp, double *colp)
 //   C_bj = R'_j;  C_ib = -Q_i D^-1;  C_bb = D^-1.
 // ws (LDS) holds Q (r x NB), R' (NB x r) and D (NB x NB).
 template <int NB>
-__device__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
+__device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
     const int tid = threadIdx.x;
     double *Qs = ws;                    // Qs[i * NB + c] = C(i, b0 + c)
     double *Rs = Qs + (long)r * NB;     // Rs[c * r + j] = C(b0 + c, j), then R'
@@ -459,8 +417,7 @@ struct BatchDesc {
     int pad;
 };
 
-template <int TPW>
-__global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
+__global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
                                                                    int k, double user_tol, int nl, int *queue,
                                                                    double *slabs, long slab_stride, int nmax,
                                                                    int *rank, int *status) {
@@ -501,23 +458,13 @@ __global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const Batc
         if (slot >= batch) break;
         const int b = order[slot];
         const BatchDesc d = desc[b];
-        const int m = d.m, nfull = d.n;
-        // the Appendix's transpose branch for m < n: factor G G' (m x m), B = F,
-        // and W = G' (L M M L' F); n below is the order of the factored matrix
-        const bool tr = m < nfull;
-        const int n = tr ? m : nfull;
+        const int m = d.m, n = d.n;
         if (tid == 0) ints[2] = 0;
 
-        // 1. A = G'G, B = G'F (transpose branch: A = G G', B = F)
+        // 1. A = G'G, B = G'F
         double *A = (n <= nl) ? big : Lg;
         const long lda = n;
-        if (!tr) {
-            block_gram<TPW, float, false>(d.G, d.ldg, m, n, nullptr, false, d.F, d.ldf, k, A, lda, Bv, n, stage);
-        } else {
-            block_gram<TPW, float, true>(d.G, d.ldg, nfull, n, nullptr, false, d.F, d.ldf, 0, A, lda, Bv, n, stage);
-            for (int e = tid; e < n * k; e += BT_THREADS) Bv[e] = (double)d.F[(e % n) + (long)(e / n) * d.ldf];
-            __syncthreads();
-        }
+        block_gram<float>(d.G, d.ldg, m, n, nullptr, false, d.F, d.ldf, k, A, lda, Bv, n, stage);
         // 2. tolerance and full-rank Cholesky in place
         const double tol = block_tol(A, lda, n, user_tol, red, &ints[2]);
         if (ints[2] && tid == 0) *status = ST_NONFINITE;
@@ -528,7 +475,7 @@ __global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const Batc
         if (d.piv)
             for (int c = tid; c < r; c += BT_THREADS) d.piv[c] = cols[c];
         if (r == 0) {
-            for (int e = tid; e < nfull * k; e += BT_THREADS) d.W[(e % nfull) + (long)(e / nfull) * d.ldw] = 0.0;
+            for (int e = tid; e < n * k; e += BT_THREADS) d.W[(e % n) + (long)(e / n) * d.ldw] = 0.0;
             __syncthreads();
             continue;
         }
@@ -540,7 +487,7 @@ __global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const Batc
         // 3. C = L'L (kept columns), T = L'B
         double *C = (r <= nl) ? big : Cg;
         const long ldc = r;
-        block_gram<TPW, double, false>(Lg, n, n, r, cols, true, Bv, n, k, C, ldc, Tv, r, stage);
+        block_gram<double>(Lg, n, n, r, cols, true, Bv, n, k, C, ldc, Tv, r, stage);
         // full symmetric C from its lower triangle
         for (long e = tid; e < (long)r * r; e += BT_THREADS) {
             const int i = (int)(e % r), j = (int)(e / r);
@@ -568,26 +515,13 @@ __global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const Batc
             Tv[i + (long)q * r] = s;
         }
         __syncthreads();
-        // V = L T: W itself, or (transpose branch) V in Xv and W = G' V
-        double *V = tr ? Xv : nullptr;
         for (int e = tid; e < n * k; e += BT_THREADS) {
             const int i = e % n, q = e / n;
             double s = 0.0;
             for (int c = 0; c < r && cols[c] <= i; ++c) s = fma(Lg[i + (long)cols[c] * n], Tv[c + (long)q * r], s);
-            if (tr) V[i + (long)q * n] = s;
-            else d.W[i + (long)q * d.ldw] = s;
+            d.W[i + (long)q * d.ldw] = s;
         }
         __syncthreads();
-        if (tr) {
-            for (int e = tid; e < nfull * k; e += BT_THREADS) {
-                const int j = e % nfull, q = e / nfull;
-                const float *gj = d.G + (long)j * d.ldg;
-                double s = 0.0;
-                for (int i = 0; i < m; ++i) s = fma((double)gj[i], V[i + (long)q * n], s);
-                d.W[j + (long)q * d.ldw] = s;
-            }
-            __syncthreads();
-        }
     }
 }
 
@@ -605,20 +539,14 @@ size_t batched_slab_doubles(int nmax, int k) {
 }
 
 hipError_t launch_batched(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
-                          double *slabs, int grid, int nmax, int tiles, int *rank, int *status, hipStream_t s) {
-    if (tiles != 4 && tiles != 8) return hipErrorInvalidValue;
+                          double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s) {
     hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = batched_lds_bytes(nl, nmax, k);
-    const long slab = (long)batched_slab_doubles(nmax, k);
-    const BatchDesc *d = static_cast<const BatchDesc *>(desc);
-    if (tiles == 8)
-        hipLaunchKernelGGL(batched_lstsq_kernel<8>, dim3(grid), dim3(BT_THREADS), lds, s, d, order, batch, k, tol, nl,
-                           queue, slabs, slab, nmax, rank, status);
-    else
-        hipLaunchKernelGGL(batched_lstsq_kernel<4>, dim3(grid), dim3(BT_THREADS), lds, s, d, order, batch, k, tol, nl,
-                           queue, slabs, slab, nmax, rank, status);
+    hipLaunchKernelGGL(batched_lstsq_kernel, dim3(grid), dim3(BT_THREADS), lds, s,
+                       static_cast<const BatchDesc *>(desc), order, batch, k, tol, nl, queue, slabs,
+                       (long)batched_slab_doubles(nmax, k), nmax, rank, status);
     return hipGetLastError();
 }
 
@@ -633,5 +561,200 @@ void batched_fill_desc(void *out, const float *G, const float *F, double *W, int
 }
 
 void batched_set_piv(void *desc, int b, int *piv) { static_cast<BatchDesc *>(desc)[b].piv = piv; }
+
+// ---------------------------------------------------------------------------
+// Wide problems (m_b < n_b): the Appendix's transpose branch, one problem per
+// workgroup as above.  The m x m matrix G G' is factored (its lower triangle
+// from the rows of G, staged 16 columns of G at a time), B = F, and after
+// X = M (M (L' F)) the weights are W = G' (L X).  A separate kernel, so that
+// the tall problems' kernel stays as it is.
+// ---------------------------------------------------------------------------
+
+// Lower triangle of G G' (m x m, lda) for G m x n (ldg): the stage holds
+// columns k0 .. k0 + 15 of G as rows, 8 x 4 output tiles per thread.
+__device__ __forceinline__ void block_gram_rows(const float *G, long ldg, int m, int n, double *Aout, long lda, double *stage) {
+    const int tid = threadIdx.x;
+    const int nt = (m + 7) / 8;
+    const int ntiles = nt * (nt + 1);
+    for (int base = 0; base < ntiles; base += BT_THREADS) {
+        const int t = base + tid;
+        int ti = 0, tj = 0;
+        const bool active = t < ntiles;
+        if (active) {
+            ti = (int)((sqrtf(4.0f * t + 1.0f) - 1.0f) * 0.5f);
+            while (ti * (ti + 1) > t) --ti;
+            while ((ti + 1) * (ti + 2) <= t) ++ti;
+            tj = t - ti * (ti + 1);
+        }
+        double acc[8][4];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int k0 = 0; k0 < n; k0 += BT_STAGE_ROWS) {
+            __syncthreads();
+            // stage row r = column k0 + r of G (m consecutive floats)
+            for (int e = tid; e < BT_STAGE_ROWS * m; e += BT_THREADS) {
+                const int c = e % m, r = e / m;
+                const bool ok = k0 + r < n;
+                const double v = (double)G[ok ? c + (long)(k0 + r) * ldg : 0];
+                stage[r * m + c] = ok ? v : 0.0;
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll 4
+                for (int r = 0; r < BT_STAGE_ROWS; ++r) {
+                    double av[8], bv[4];
+                    const double *srow = stage + r * m;
+#pragma unroll
+                    for (int a = 0; a < 8; ++a) {
+                        const int ci = ti * 8 + a;
+                        av[a] = ci < m ? srow[ci] : 0.0;
+                    }
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int cj = tj * 4 + b;
+                        bv[b] = cj < m ? srow[cj] : 0.0;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 8; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+                }
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = ti * 8 + a, j = tj * 4 + b;
+                    if (i < m && j <= i) Aout[i + (long)j * lda] = acc[a][b];
+                }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(BT_THREADS) void batched_wide_kernel(const BatchDesc *desc, const int *order, int batch,
+                                                                  int k, double user_tol, int nl, int *queue,
+                                                                  double *slabs, long slab_stride, int nmax,
+                                                                  int *rank, int *status) {
+    extern __shared__ __attribute__((aligned(16))) double lds[];
+    double *big = lds;
+    double *stage = big + (long)nl * nl;
+    double *red = stage + BT_STAGE_ROWS * (nmax + k);
+    double *rowp = red + BT_THREADS;
+    double *colp = rowp + nmax;
+    int *cols = reinterpret_cast<int *>(colp + nmax);
+    int *ints = cols + nmax;
+
+    double *slab = slabs + (long)blockIdx.x * slab_stride;
+    double *Lg = slab;
+    double *Cg = Lg + (long)nmax * nmax;
+    double *Bv = Cg + (long)nmax * nmax;
+    double *Tv = Bv + (long)nmax * k;
+    double *Xv = Tv + (long)nmax * k;
+
+    const int tid = threadIdx.x;
+    const long ws_cap = (long)nl * nl + (long)BT_STAGE_ROWS * (nmax + k);
+    int gj_nb = 0, fr_nb = 0;
+    for (int nbc = 8; nbc >= 4; nbc /= 2) {
+        if (gj_nb == 0 && ws_cap >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
+        if (fr_nb == 0 && ws_cap >= (long)nmax * nbc) fr_nb = nbc;
+    }
+    for (;;) {
+        if (tid == 0) ints[0] = atomicAdd(queue, 1);
+        __syncthreads();
+        const int slot = ints[0];
+        __syncthreads();
+        if (slot >= batch) break;
+        const int b = order[slot];
+        const BatchDesc d = desc[b];
+        const int m = d.m, n = d.n;   // m < n: the factored order is m
+        if (tid == 0) ints[2] = 0;
+
+        // 1. A = G G' (m x m), B = F
+        double *A = (m <= nl) ? big : Lg;
+        const long lda = m;
+        block_gram_rows(d.G, d.ldg, m, n, A, lda, stage);
+        for (int e = tid; e < m * k; e += BT_THREADS) Bv[e] = (double)d.F[(e % m) + (long)(e / m) * d.ldf];
+        __syncthreads();
+        // 2. tolerance and full-rank Cholesky in place
+        const double tol = block_tol(A, lda, m, user_tol, red, &ints[2]);
+        if (ints[2] && tid == 0) *status = ST_NONFINITE;
+        const int r = (A == Lg && fr_nb == 8)   ? block_frchol_blocked<8>(A, lda, m, tol, cols, &ints[1], big)
+                      : (A == Lg && fr_nb == 4) ? block_frchol_blocked<4>(A, lda, m, tol, cols, &ints[1], big)
+                                                : block_frchol(A, lda, m, tol, cols, &ints[1]);
+        if (tid == 0) rank[b] = r;
+        if (d.piv)
+            for (int c = tid; c < r; c += BT_THREADS) d.piv[c] = cols[c];
+        if (r == 0) {
+            for (int e = tid; e < n * k; e += BT_THREADS) d.W[(e % n) + (long)(e / n) * d.ldw] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        if (A == big) {
+            for (long e = tid; e < (long)m * m; e += BT_THREADS) Lg[e] = big[e];
+            __syncthreads();
+        }
+        // 3. C = L'L (kept columns), T = L'F
+        double *C = (r <= nl) ? big : Cg;
+        const long ldc = r;
+        block_gram<double>(Lg, m, m, r, cols, true, Bv, m, k, C, ldc, Tv, r, stage);
+        for (long e = tid; e < (long)r * r; e += BT_THREADS) {
+            const int i = (int)(e % r), j = (int)(e / r);
+            if (i < j) C[i + (long)j * ldc] = C[j + (long)i * ldc];
+        }
+        __syncthreads();
+        // 4. M = C^-1
+        const bool ok = (C == Cg && gj_nb == 8)   ? block_gj_blocked<8>(C, ldc, r, big)
+                        : (C == Cg && gj_nb == 4) ? block_gj_blocked<4>(C, ldc, r, big)
+                                                  : block_gj(C, ldc, r, rowp, colp);
+        if (!ok && tid == 0) *status = ST_NOTSPD;
+        // 5. X = M T, T = M X, V = L T (m x k, into Xv), W = G' V
+        for (int e = tid; e < r * k; e += BT_THREADS) {
+            const int i = e % r, q = e / r;
+            double s = 0.0;
+            for (int j = 0; j < r; ++j) s = fma(C[i + (long)j * ldc], Tv[j + (long)q * r], s);
+            Xv[i + (long)q * r] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < r * k; e += BT_THREADS) {
+            const int i = e % r, q = e / r;
+            double s = 0.0;
+            for (int j = 0; j < r; ++j) s = fma(C[i + (long)j * ldc], Xv[j + (long)q * r], s);
+            Tv[i + (long)q * r] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < m * k; e += BT_THREADS) {
+            const int i = e % m, q = e / m;
+            double s = 0.0;
+            for (int c = 0; c < r && cols[c] <= i; ++c) s = fma(Lg[i + (long)cols[c] * m], Tv[c + (long)q * r], s);
+            Xv[i + (long)q * m] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * k; e += BT_THREADS) {
+            const int j = e % n, q = e / n;
+            const float *gj = d.G + (long)j * d.ldg;
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s = fma((double)gj[i], Xv[i + (long)q * m], s);
+            d.W[j + (long)q * d.ldw] = s;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_batched_wide(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
+                               double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s) {
+    hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = batched_lds_bytes(nl, nmax, k);
+    hipLaunchKernelGGL(batched_wide_kernel, dim3(grid), dim3(BT_THREADS), lds, s,
+                       static_cast<const BatchDesc *>(desc), order, batch, k, tol, nl, queue, slabs,
+                       (long)batched_slab_doubles(nmax, k), nmax, rank, status);
+    return hipGetLastError();
+}
 
 }  // namespace geninv

@@ -185,7 +185,9 @@ hipError_t launch_trinv64(const double *T, long ldt, int r, double *Dinv, hipStr
 constexpr int BATCH_NMAX = 256;
 constexpr int BATCH_KMAX = 16;
 hipError_t launch_batched(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
-                          double *slabs, int grid, int nmax, int tiles, int *rank, int *status, hipStream_t s);
+                          double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s);
+hipError_t launch_batched_wide(const void *desc, const int *order, int batch, int k, double tol, int nl, int *queue,
+                               double *slabs, int grid, int nmax, int *rank, int *status, hipStream_t s);
 size_t batched_lds_bytes(int nl, int nmax, int k);
 size_t batched_slab_doubles(int nmax, int k);
 size_t batched_desc_bytes();

@@ -122,13 +122,13 @@ def test_batched_random_uneven_sizes_all_lds_thresholds():
     print("[case] batched 96 problems", flush=True)
     B = w.batch_lowrank(96, seed=11, m_hi=600, n_hi=200)
     plan = api.BatchPlan(B.G, B.F)
-    for nl, grid, tiles in [(0, 256, 8), (64, 512, 4), (128, 256, 8), (32, 1024, 4)]:
-        plan.config(nl, grid, tiles)
+    for nl, grid in [(0, 256), (64, 512), (128, 256), (32, 1024)]:
+        plan.config(nl, grid)
         plan.Wbuf.zero_()
         plan.run(use_graph=False)
         torch.cuda.synchronize()
         worst = _check(plan, B.G, B.F)
-        print(f"  nl={nl} grid={grid} tiles={tiles} worst relF(W)={worst:.2e}", flush=True)
+        print(f"  nl={nl} grid={grid} worst relF(W)={worst:.2e}", flush=True)
     plan.close()
 
 
@@ -164,11 +164,48 @@ def test_batched_autotune_picks_a_valid_config():
     B = w.batch_lowrank(128, seed=13, m_hi=500, n_hi=160)
     plan = api.BatchPlan(B.G, B.F)
     t = plan.autotune(reps=2)
-    assert t.grid in (256, 512, 768, 1024) and 0 <= t.nl <= 128 and t.tiles in (4, 8) and t.ms > 0
-    assert not t.from_cache and plan.config() == (t.nl, t.grid, t.tiles)
+    assert t.grid in (256, 512, 768, 1024) and 0 <= t.nl <= 128 and t.ms > 0
+    assert not t.from_cache and plan.config() == (t.nl, t.grid)
     plan.run(use_graph=False)
     torch.cuda.synchronize()
     _check(plan, B.G, B.F)
+    plan.close()
+
+
+def test_batched_every_launch_configuration_on_the_c4_draw():
+    """Every configuration the autotuner can choose (LDS threshold x
+    workgroups per compute unit, up to four workgroups per compute unit
+    resident together) on the 4096-problem C4 batch: the device status
+    stays 0, W is finite, the ranks are those of the first configuration,
+    and configurations that differ only in the grid give bit-identical W
+    (one problem per workgroup: the grid only changes which workgroup)."""
+    print("[case] batched configuration sweep on C4", flush=True)
+    B = w.c4_problem()
+    plan = api.BatchPlan(B.G, B.F)
+    assert api.sync_status(0) == 0
+    ranks0 = None
+    for nl in (128, 96, 64, 48, 32, 0):
+        Wnl = None
+        for grid in (256, 512, 768, 1024):
+            try:
+                plan.config(nl, grid)
+            except api.GeninvError:
+                continue      # LDS does not fit
+            plan.Wbuf.zero_()
+            plan.run(use_graph=False)
+            st = api.sync_status(0)
+            W = plan.Wbuf.cpu()
+            ranks = plan.rank.cpu().numpy()
+            print(f"  nl={nl} grid={grid}: status {st}", flush=True)
+            assert st == 0, (nl, grid, st)
+            assert torch.isfinite(W).all(), (nl, grid)
+            if ranks0 is None:
+                ranks0 = ranks.copy()
+            assert np.array_equal(ranks, ranks0), (nl, grid, int((ranks != ranks0).sum()))
+            if Wnl is None:
+                Wnl = W
+            else:
+                assert torch.equal(W, Wnl), (nl, grid)
     plan.close()
 
 
@@ -184,19 +221,20 @@ def test_batched_autotune_cache(tmp_path):
     t1 = p1.autotune(reps=1, cache=path)
     assert not t1.from_cache
     lines = open(path).read().splitlines()
-    assert len(lines) == 1 and lines[0].split()[1:4] == [str(t1.nl), str(t1.grid), str(t1.tiles)]
+    assert len(lines) == 1 and lines[0].split()[1:3] == [str(t1.nl), str(t1.grid)]
     p2 = api.BatchPlan(B.G, B.F)
-    p2.config(0, 256, 4 if t1.tiles == 8 else 8)
+    p2.config(0, 256 if t1.grid != 256 else 512)
     t2 = p2.autotune(reps=1, cache=path)
-    assert t2.from_cache and (t2.nl, t2.grid, t2.tiles) == (t1.nl, t1.grid, t1.tiles)
-    assert p2.config() == (t1.nl, t1.grid, t1.tiles)
+    assert t2.from_cache and (t2.nl, t2.grid) == (t1.nl, t1.grid)
+    assert p2.config() == (t1.nl, t1.grid)
     C = w.batch_lowrank(32, seed=19, m_hi=300, n_hi=100)
     p3 = api.BatchPlan(C.G, C.F)
     assert not p3.autotune(reps=1, cache=path).from_cache
     assert len(open(path).read().splitlines()) == 2
     key = lines[0].split()[0]
     with open(path, "w") as f:
-        f.write("garbage line\n" + key + " 0 99999 8 1.0\n" + key + " 0 256 5 1.0\n\x00\x01\n")
+        f.write("garbage line\n" + key + " 0 99999 1.0\n" + key + " 0 256 1.0 extra\n" + key + " 0 256 -1\n"
+                "\x00\x01\n")
     p4 = api.BatchPlan(B.G, B.F)
     t4 = p4.autotune(reps=1, cache=path)
     assert not t4.from_cache
