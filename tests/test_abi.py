@@ -58,6 +58,14 @@ def test_null_context_is_einval(lib):
     assert lib.geninv_sync_status(None) == -1
     assert lib.geninv_lstsq_batched(None, 0, None, None, 4, None, None, None, None, 0.0, None, None, None,
                                     None) == -1
+    assert lib.geninv_set_workspace_limit(None, 0) == -1
+    assert lib.geninv_set_debug(None, 0) == -1
+    assert lib.geninv_debug_poison(None) == -1
+    assert lib.geninv_batch_plan_graph_fallbacks(None) == -1
+    assert lib.geninv_batch_plan_autotune(None, 1, None, None, None, None, None) == -1
+    assert lib.geninv_batch_plan_config(None, 0, 256) == -1
+    assert lib.geninv_batch_plan_get_config(None, None, None) == -1
+    assert lib.geninv_dlstsq_noalloc(None, 3, 3, 1, None, 3, None, 3, 0.0, None, 3, None) == -1
     assert lib.geninv_destroy(None) == 0
 
 
