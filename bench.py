@@ -27,6 +27,7 @@ from __future__ import annotations
 import argparse
 import ctypes
 import json
+import math
 import os
 import sys
 import time
@@ -94,6 +95,18 @@ def _counter_traffic(kernel_class: str, tag: str):
             return None
         return int(fields["read_bytes"]) + int(fields["write_bytes"])
     return None
+
+
+def _finite(x):
+    """The report with non-finite numbers (e.g. an infinite rounding spread
+    where a perturbed Gram matrix changes the rank) as null: strict JSON."""
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_finite(v) for v in x]
+    if isinstance(x, float) and not math.isfinite(x):
+        return None
+    return x
 
 
 def _timed(fn, steps, sync):
@@ -868,7 +881,7 @@ def main():
         "kernel_ms_one_step": breakdown,
         "forms": forms,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(_finite(out), allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":
