@@ -83,9 +83,15 @@ __host__ __device__ inline long tiles_of(const GemmArgs &p) {
 }
 
 // Workgroup -> tile: the linear ids a single XCD receives (id mod 8) are
-// given one contiguous run of the tile order, which goes down the columns of
-// C (tile column by fixed, row bx running), so that the workgroups resident
-// on one XCD share operand panels in its L2.
+// given one contiguous run of the tile order, so that the workgroups resident
+// on one XCD at a time share operand panels in its L2.  For a full product
+// the order takes bands of TILE_BAND tile rows and walks each band column by
+// column: a run of 32 consecutive tiles (one per compute unit of an XCD)
+// covers 4 x 8 tiles and streams 4 panels of A and 8 of B, where a walk down
+// whole columns of C streams 1 panel of B and 32 of A.  Bands of fewer rows
+// at the bottom edge are walked the same way.
+constexpr int TILE_BAND = 4;
+
 template <int BM, int BN>
 __device__ __forceinline__ void tile_of(const GemmArgs &p, int &bx, int &by) {
     const long T = gridDim.x;
@@ -94,8 +100,12 @@ __device__ __forceinline__ void tile_of(const GemmArgs &p, int &bx, int &by) {
     long t = x * q + (x < rem ? x : rem) + lin / 8;
     const int tm = (p.M.host + BM - 1) / BM;
     if (p.uplo != GEMM_LOWER) {
-        bx = (int)(t % tm);
-        by = (int)(t / tm);
+        const long tn = (p.N.host + BN - 1) / BN;
+        const long band = t / (TILE_BAND * tn);
+        const long in = t - band * TILE_BAND * tn;
+        const int g = min(TILE_BAND, tm - (int)band * TILE_BAND);
+        bx = (int)(band * TILE_BAND + in % g);
+        by = (int)(in / g);
         return;
     }
     int c = 0;

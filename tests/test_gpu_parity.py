@@ -376,6 +376,59 @@ def test_geninv_c2_full_size():
     assert rg <= rr * (1.0 + 10 * spread)
 
 
+def test_geninv_c5_full_size_properties():
+    """The benchmark's workload at full size, as the benchmark times it (RBF
+    design 131072 x 8192, 7000 unique centers and 1192 exact duplicates placed
+    after their originals).  The oracle cannot run at this size, so the
+    checks are properties that hold at any size:
+    * decisions: every unique center's first column is kept and every
+      duplicate dropped (a duplicate's updated pivot is zero up to rounding,
+      far below tol), so r = 7000 and piv is exactly the set of first
+      occurrences;
+    * G Y G = G on 64 sampled columns (float64 form measured at 5e-5
+      relative; a wrong factor or inverse gives O(1));
+    * the least-squares weights: G'(G W - F) = 0 up to rounding, relative
+      to |G| |G W - F|, and the residual of random F against a rank-7000
+      column space within 0.5 % of its expected value sqrt(1 - 7000/131072);
+    * W from geninv_dlstsq equals Y F from geninv_dgeninv within float64
+      rounding of the factored evaluation."""
+    _print_case("geninv + lstsq", cfg="c5 rbf 131072x8192")
+    G, F, idx = w.c5_problem()
+    m, n = G.shape
+    first = np.zeros(n, bool)
+    seen = set()
+    for j in range(n):
+        if idx[j] not in seen:
+            first[j] = True
+            seen.add(idx[j])
+    Gd, Fd = up(G), up(F)
+    del G
+    Y, r, piv = api.geninv(Gd, return_piv=True)
+    pg = down(piv).astype(np.int64)
+    print(f"  rank {r}", flush=True)
+    assert r == 7000 == int(first.sum())
+    assert np.array_equal(np.sort(pg), np.nonzero(first)[0])
+    rng = np.random.default_rng(5)
+    cols = torch.from_numpy(np.sort(rng.choice(n, size=64, replace=False))).to(DEV)
+    Gs = Gd[:, cols]
+    gyg = float(torch.linalg.norm(Gd @ (Y @ Gs) - Gs) / torch.linalg.norm(Gs))
+    print(f"  relF(G Y G - G) on 64 columns: {gyg:.3e}", flush=True)
+    W, r2 = api.lstsq(Gd, Fd)
+    R = Gd @ W - Fd
+    ne = float(torch.linalg.norm(Gd.t() @ R) / (torch.linalg.norm(Gd) * torch.linalg.norm(R)))
+    res = float(torch.linalg.norm(R) / torch.linalg.norm(Fd))
+    print(f"  normal equations {ne:.3e}; LS residual {res:.6f} (expected about {np.sqrt(1 - r / m):.6f})",
+          flush=True)
+    dW = float(torch.linalg.norm(W - Y @ Fd) / torch.linalg.norm(W))
+    print(f"  relF(W - Y F) {dW:.3e}", flush=True)
+    assert gyg <= 1e-3
+    assert r2 == r
+    assert ne <= 1e-6
+    assert abs(res - np.sqrt(1 - r / m)) <= 0.005 * np.sqrt(1 - r / m)
+    assert dW <= 1e-6
+    del Y, W, R, Gd
+
+
 def test_geninv_split_products_parity():
     """A size at which L'L, L M and K K' are split over K (partials summed in
     a fixed order, so that the 128 x 128 kernel fills the chip): rank and Y
