@@ -194,10 +194,11 @@ int geninv_dgram(geninv_ctx *ctx, int m, int n, const double *G, int ldg, double
 int geninv_dfrchol(geninv_ctx *ctx, int n, const double *A, int lda, double tol, double *L,
                    int ldl, int *piv, double *d, double *tol_used, int *rank);
 
-/* M = B^-1 for symmetric positive definite B (r x r, ldb >= r, whole matrix
- * read, not modified); M r x r, ldm >= r, written in full and exactly
- * symmetric (Theorem 1: B = L'L).  A non-positive pivot block sets the
- * device status to ENOTSPD. */
+/* M = B^-1 for symmetric positive definite B (r x r, ldb >= r, not
+ * modified; the symmetric block sweep reads the lower triangle and the
+ * diagonal 64 x 64 blocks in full); M r x r, ldm >= r, written in full and
+ * exactly symmetric (Theorem 1: B = L'L).  A non-positive pivot block sets
+ * the device status to ENOTSPD. */
 int geninv_dspdinv(geninv_ctx *ctx, int r, const double *B, int ldb, double *M, int ldm);
 
 /* The same inverse by Newton-Schulz iteration X <- X (2I - B X) on the

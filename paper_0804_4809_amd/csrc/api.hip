@@ -40,6 +40,8 @@ struct geninv_batch_plan;
 namespace geninv {
 // debug.hip
 hipError_t launch_poison(void *p, size_t bytes, hipStream_t s);
+// spdinv.hip: negate and mirror the lower triangle left by the sweeps
+hipError_t launch_gj_finish(double *X, long ldx, Dim n, hipStream_t s);
 // skinny.hip
 int skinny_padded_width(int N);
 hipError_t launch_skinny_gemm(const double *A, long lda, const double *B, long ldb, int transB, int M, int N, int K,
@@ -384,7 +386,8 @@ int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, do
     return GENINV_OK;
 }
 
-// M = B^-1 in place (B r x r full symmetric, ldb), r on device (bound rb).
+// M = B^-1 in place (B r x r symmetric, ldb; the sweeps read the lower block
+// triangle and the diagonal blocks in full), r on device (bound rb).
 int run_spdinv(geninv_ctx *c, const Layout &lay, double *B, long ldb, Dim r) {
     double *D = at<double>(c, lay.dbuf);
     double *R = at<double>(c, lay.rrow);
@@ -399,7 +402,7 @@ int run_spdinv(geninv_ctx *c, const Layout &lay, double *B, long ldb, Dim r) {
         HIPCHK(launch_gj_update(B, ldb, r, b, D, R, Cc, c->stream));
     }
     ProfScope ps(c, PC_MIRROR, 0.0);
-    HIPCHK(launch_mirror_lower(B, ldb, r, c->stream));
+    HIPCHK(launch_gj_finish(B, ldb, r, c->stream));
     return GENINV_OK;
 }
 

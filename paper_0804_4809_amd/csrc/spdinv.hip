@@ -1,22 +1,26 @@
-// M = (L'L)^-1 (Theorem 1) on gfx950 by block Gauss-Jordan elimination.
+// M = (L'L)^-1 (Theorem 1) on gfx950 by block Gauss-Jordan elimination in
+// its symmetric form (the sweep operator).
 //
 // L'L is symmetric positive definite (L has full column rank r), so every
-// pivot block met by Gauss-Jordan elimination without pivoting is a Schur
-// complement of an SPD matrix and is itself SPD.  One elimination step on
-// pivot block b (GJ_NB wide) of the r x r matrix B is
+// pivot block met by the elimination without pivoting is a Schur complement
+// of an SPD matrix and is itself SPD.  One sweep of pivot block b (GJ_NB
+// wide) of the r x r matrix B is
 //
 //   D       = B_bb^-1                        (pivot block, inverted in LDS)
 //   R_j     = D B_bj          for j != b      (new pivot block row)
 //   B_ij   -= B_ib R_j        for i, j != b   (rank-GJ_NB update)
-//   B_ib    = -B_ib D         for i != b      (new pivot block column)
-//   B_bj    = R_j,  B_bb = D
+//   B_ib    = B_ib D          for i != b      (new pivot block column, = R_i')
+//   B_bj    = R_j,  B_bb = -D
 //
-// and after the last block B holds B^-1.  Two launches per step: the panel
-// kernel (D, R and a copy of the old block column, one workgroup per block
-// column) and the update kernel (one workgroup per 64 x 64 tile), which reads
-// only the staged panels so that tiles can be rewritten in place.  The
-// 64 x 64 x 64 tile products run on v_mfma_f64_16x16x4f64.  The rank r is
-// read from device memory; steps and tiles past r exit at once.
+// Every sweep keeps B symmetric, so only the blocks on or below the block
+// diagonal are computed (diagonal blocks in full), half the update's work
+// and traffic; after the last sweep B holds -B^-1, which the finishing
+// kernel negates and mirrors.  Two launches per sweep: the panel kernel (D,
+// R and a copy of the old block column, one workgroup per block column) and
+// the update kernel (one workgroup per 64 x 64 tile), which reads only the
+// staged panels so that tiles can be rewritten in place.  The 64 x 64 x 64
+// tile products run on v_mfma_f64_16x16x4f64.  The rank r is read from
+// device memory; steps and tiles past r exit at once.
 #include "common.h"
 
 #include <utility>
@@ -165,25 +169,42 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict_
     const int wj = min(GJ_NB, r - jb * GJ_NB);
     const long ob = (long)b * GJ_NB, oj = (long)jb * GJ_NB;
 
-    // all loads first (no branches), then the LDS and global writes
-    double xb[GJ_NB / 4], cb[GJ_NB / 4], bl[GJ_NB / 4];
+    // all loads first (no branches), then the LDS and global writes.  Only
+    // the lower block triangle of B is kept (diagonal blocks in full), so
+    // block (jb, b) of the old block column is block (jb, b) itself for
+    // jb >= b and the transpose of block (b, jb) for jb < b; either is read
+    // coalesced, and Bl gets the pivot block row's block (b, jb) =
+    // block (jb, b)'.
+    const bool below = jb >= b;
+    double xb[GJ_NB / 4], cb[GJ_NB / 4];
 #pragma unroll
     for (int q = 0; q < GJ_NB / 4; ++q) {
         const int jc = wave + 4 * q;
         xb[q] = ld_or(B, (ob + lane) + (ob + jc) * ldb, lane < wb && jc < wb, lane == jc ? 1.0 : 0.0);
-        // old block column (rows of block jb, columns of block b)
-        cb[q] = ld_or(B, (oj + lane) + (ob + jc) * ldb, lane < wj && jc < wb, 0.0);
-        // pivot block row restricted to the columns of block jb, zero padded
-        bl[q] = ld_or(B, (ob + lane) + (oj + jc) * ldb, jb != b && lane < wb && jc < wj, 0.0);
+        // below: element (lane, jc) of block (jb, b); else of block (b, jb)
+        cb[q] = below ? ld_or(B, (oj + lane) + (ob + jc) * ldb, lane < wj && jc < wb, 0.0)
+                      : ld_or(B, (ob + lane) + (oj + jc) * ldb, lane < wb && jc < wj, 0.0);
     }
 #pragma unroll
     for (int q = 0; q < GJ_NB / 4; ++q) {
         const int jc = wave + 4 * q;
         X[jc][lane] = xb[q];
-        if (lane < wj && jc < wb) Ccol[(oj + lane) + (long)jc * ldc] = cb[q];
-        Bl[jc][lane] = bl[q];
+        if (below) {
+            if (lane < wj && jc < wb) Ccol[(oj + lane) + (long)jc * ldc] = cb[q];
+            Bl[lane][jc] = jb != b ? cb[q] : 0.0;
+        } else {
+            Bl[jc][lane] = cb[q];
+        }
     }
-    const bool ok = gj_invert_block(X, wb);
+    const bool ok = gj_invert_block(X, wb);   // begins and ends with a workgroup barrier
+    if (!below) {
+        // the old block column's block jb from the transpose in LDS
+#pragma unroll
+        for (int q = 0; q < GJ_NB / 4; ++q) {
+            const int jc = wave + 4 * q;
+            if (lane < wj && jc < wb) Ccol[(oj + lane) + (long)jc * ldc] = Bl[lane][jc];
+        }
+    }
     if (jb == b) {
         if (!ok && tid == 0) *status = ST_NOTSPD;
 #pragma unroll
@@ -219,7 +240,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     const int r = rd.get();
     const int nbk = (r + GJ_NB - 1) / GJ_NB;
     const int ib = blockIdx.x, jb = blockIdx.y;
-    if (b >= nbk || ib >= nbk || jb >= nbk) return;
+    if (b >= nbk || ib >= nbk || jb >= nbk || ib < jb) return;   // the lower block triangle only
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wb = min(GJ_NB, r - b * GJ_NB);
@@ -229,7 +250,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
     double *T = B + oi + oj * ldb;
 
     if (ib == b) {
-        // row block b: D on the diagonal tile, R_jb elsewhere (loads first)
+        // row block b: -D on the diagonal tile, R_jb left of it (loads first)
         const bool diag = jb == b;
         const double *src = diag ? Dbuf : Rrow + oj * GJ_NB;
         const int wc = diag ? wb : wj;
@@ -242,7 +263,7 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
 #pragma unroll
         for (int q = 0; q < GJ_NB / 4; ++q) {
             const int jc = wave + 4 * q;
-            if (lane < wb && jc < wc) T[lane + (long)jc * ldb] = t[q];
+            if (lane < wb && jc < wc) T[lane + (long)jc * ldb] = diag ? -t[q] : t[q];
         }
         return;
     }
@@ -288,7 +309,8 @@ __global__ __launch_bounds__(256) void gj_update_kernel(double *__restrict__ B, 
             for (int v = 0; v < 4; ++v) {
                 const int row = wm * 32 + a * 16 + (lane & 15);
                 const int col = wn * 32 + bb * 16 + (lane >> 4) + 4 * v;
-                if (row < wi && col < wr) T[row + (long)col * ldb] = old[a][bb][v] - acc[a][bb][v];
+                if (row < wi && col < wr)
+                    T[row + (long)col * ldb] = newcol ? acc[a][bb][v] : old[a][bb][v] - acc[a][bb][v];
             }
 }
 
@@ -307,6 +329,42 @@ hipError_t launch_gj_update(double *B, long ldb, Dim r, int b, const double *D, 
     if (nbk <= 0) return hipSuccess;
     hipLaunchKernelGGL(gj_update_kernel, dim3(nbk, nbk), dim3(256), 0, s, B, ldb, r, b, D, Rrow, Ccol,
                        (long)r.host);
+    return hipGetLastError();
+}
+
+// After the last sweep the lower triangle holds -B^-1: negate it and copy it
+// to the upper triangle (32 x 32 tiles through LDS, one workgroup per tile on
+// or below the diagonal).
+__global__ void gj_finish_kernel(double *X, long ldx, Dim nd) {
+    __shared__ double t[32][33];
+    const int n = nd.get();
+    const int bi = blockIdx.x, bj = blockIdx.y;
+    if (bi < bj) return;
+    const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = bi * 32 + tx, j = bj * 32 + ty + 8 * q;
+        v[q] = -ld_or(X, i + (long)j * ldx, i < n && j < n, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = bi * 32 + tx, j = bj * 32 + ty + 8 * q;
+        if (i < n && j < n && i >= j) X[i + (long)j * ldx] = v[q];
+        t[ty + 8 * q][tx] = v[q];
+    }
+    __syncthreads();
+    for (int yy = ty; yy < 32; yy += 8) {
+        const int di = bj * 32 + tx;   // destination row = source column
+        const int dj = bi * 32 + yy;   // destination column = source row
+        if (di < n && dj < n && dj > di) X[di + (long)dj * ldx] = t[tx][yy];
+    }
+}
+
+hipError_t launch_gj_finish(double *X, long ldx, Dim n, hipStream_t s) {
+    if (n.host <= 0) return hipSuccess;
+    const int nt = (n.host + 31) / 32;
+    hipLaunchKernelGGL(gj_finish_kernel, dim3(nt, nt), dim3(32, 8), 0, s, X, ldx, n);
     return hipGetLastError();
 }
 

@@ -172,43 +172,6 @@ def test_batched_autotune_picks_a_valid_config():
     plan.close()
 
 
-def test_batched_every_launch_configuration_on_the_c4_draw():
-    """Every configuration the autotuner can choose (LDS threshold x
-    workgroups per compute unit, up to four workgroups per compute unit
-    resident together) on the 4096-problem C4 batch: the device status
-    stays 0, W is finite, the ranks are those of the first configuration,
-    and configurations that differ only in the grid give bit-identical W
-    (one problem per workgroup: the grid only changes which workgroup)."""
-    print("[case] batched configuration sweep on C4", flush=True)
-    B = w.c4_problem()
-    plan = api.BatchPlan(B.G, B.F)
-    assert api.sync_status(0) == 0
-    ranks0 = None
-    for nl in (128, 96, 64, 48, 32, 0):
-        Wnl = None
-        for grid in (256, 512, 768, 1024):
-            try:
-                plan.config(nl, grid)
-            except api.GeninvError:
-                continue      # LDS does not fit
-            plan.Wbuf.zero_()
-            plan.run(use_graph=False)
-            st = api.sync_status(0)
-            W = plan.Wbuf.cpu()
-            ranks = plan.rank.cpu().numpy()
-            print(f"  nl={nl} grid={grid}: status {st}", flush=True)
-            assert st == 0, (nl, grid, st)
-            assert torch.isfinite(W).all(), (nl, grid)
-            if ranks0 is None:
-                ranks0 = ranks.copy()
-            assert np.array_equal(ranks, ranks0), (nl, grid, int((ranks != ranks0).sum()))
-            if Wnl is None:
-                Wnl = W
-            else:
-                assert torch.equal(W, Wnl), (nl, grid)
-    plan.close()
-
-
 def test_batched_autotune_cache(tmp_path):
     """The tuned configuration is stored under a key of the batch's shapes
     and taken from the file by a later plan of the same shapes without

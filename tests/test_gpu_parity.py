@@ -176,7 +176,13 @@ def test_spdinv_parity_path_sizes(r, smin):
     B = X'X with X's singular values log-spaced from 1 to smin (cond(B) =
     smin^-2).  Forward error against the oracle within the normwise bound
     c r cond(B) u, and the residual ||I - B M|| / sqrt(r) within c r cond u
-    (a backward-type check that does not go through the oracle)."""
+    (a backward-type check that does not go through the oracle).  The
+    residual's constant is larger: Gauss-Jordan elimination (either storage
+    form) has a forward error like a Cholesky-based inverse's but a residual
+    bounded only through |B| |M|, which for SPD B is up to r cond(B); a
+    float64 simulation of 64-wide block sweeps on this B (cond 1e8) gives
+    1.0e-3 (full storage) and 1.7e-3 (symmetric, lower only), 40-70 r cond u,
+    where LAPACK's inverse gives 2.6e-9."""
     _print_case("spdinv", r=r, smin=smin)
     rng = np.random.default_rng(r)
     Q1, _ = np.linalg.qr(rng.standard_normal((r, r)))
@@ -193,7 +199,7 @@ def test_spdinv_parity_path_sizes(r, smin):
     res = np.linalg.norm(np.eye(r) - B @ M) / np.sqrt(r)
     print(f"  relF vs oracle {err:.3e}; residual {res:.3e}; cond {cond:.1e}", flush=True)
     assert err <= 50 * cond * u * r
-    assert res <= 50 * cond * u * r
+    assert res <= 200 * cond * u * r
 
 
 @pytest.mark.parametrize("r,smin", [(1, 1.0), (64, 1e-2), (200, 1e-3), (513, 1e-1), (1000, 1e-3)])
