@@ -124,6 +124,8 @@ def _timed(fn, steps, sync):
 MIXED_C3 = [
     ("int8_m16", 2, 16, 16, 0),
     ("int8_m13", 2, 13, 13, 0),
+    ("int8_g13_c10", 2, 13, 10, 0),
+    ("int8_g10_c10", 2, 10, 10, 0),
     ("int8_m16_ns1", 2, 16, 16, 1),
     ("bf16_s4", 1, 4, 4, 0),
     ("bf16_s4_ns1", 1, 4, 4, 1),

@@ -47,6 +47,9 @@ int skinny_padded_width(int N);
 hipError_t launch_skinny_gemm(const double *A, long lda, const double *B, long ldb, int transB, int M, int N, int K,
                               double alpha, double beta, double *C, long ldc, int kchunk, double *Bt, double *part,
                               hipStream_t s);
+hipError_t launch_skinny_gemm_t(const double *A, long lda, const double *B, long ldb, int M, int N, int K,
+                                double alpha, double beta, double *C, long ldc, int kchunk, double *part,
+                                hipStream_t s);
 }  // namespace geninv
 
 // Fixed device scratch area of geninv_dlstsq_noalloc, for callers that
@@ -678,6 +681,7 @@ int run_mod_product(geninv_ctx *c, const ModPlan &P, const ModConsts &mc, int tr
 // ---- the mixed form's workspace ---------------------------------------------
 
 constexpr int PROBES = 16;   // random sign vectors of the error estimate
+constexpr long PROBE_PART = 1024L * 256;   // rows x K chunks of a probe product's partial sums at most
 
 // After the float64 layout of the factored dimension nn: the engine's
 // operands (bf16 slice planes, or the int8 plans of the Gram matrix and of
@@ -688,7 +692,7 @@ struct MixedPlan {
     MixedLayout bf{};
     ModConsts mg{}, mch{};
     ModPlan pg{}, pch{};
-    size_t probe = 0, norms = 0, total = 0;
+    size_t probe = 0, norms = 0, skin = 0, total = 0;
     long pld = 0;   // rows of each probe block
 };
 
@@ -725,6 +729,8 @@ int make_mixed_plan(size_t base, int m, int n, int precision, int gd, int cd, in
     P.pld = std::max(m, n);
     P.probe = take((size_t)8 * P.pld * PROBES * sizeof(double));
     P.norms = take((size_t)(8 + nn) * sizeof(double));   // sums, then the Gram diagonal
+    // the probe products' K-chunk partial sums and transposed right factor
+    P.skin = take((size_t)(std::max(PROBE_PART, P.pld) + P.pld) * PROBES * sizeof(double));
     P.total = off;
     return GENINV_OK;
 }
@@ -915,6 +921,18 @@ int geninv_dgemm(geninv_ctx *c, int transA, int transB, int M, int N, int K, dou
         double *part = at<double>(c, 0);
         HIPCHK(launch_skinny_gemm(A, lda, B, ldb, transB ? 1 : 0, M, N, K, alpha, beta, C, ldc, kchunk, part + pelems,
                                   part, c->stream));
+        return GENINV_OK;
+    }
+    // the same with A transposed (op(A) = A', A K x M, B not transposed): a
+    // wavefront walks rows of A for four of its columns (skinny.hip)
+    if (transA && !transB && N <= 16 && K >= 1024) {
+        const long colblocks = (M + 15) / 16;
+        const int S = (int)std::max<long>(1, std::min<long>({64L, (1024 + colblocks - 1) / colblocks, (long)K / 256}));
+        const int kchunk = (K + S - 1) / S;
+        const int Sx = (K + kchunk - 1) / kchunk;
+        CHK(ensure_ws(c, (size_t)Sx * M * N * sizeof(double)));
+        HIPCHK(launch_skinny_gemm_t(A, lda, B, ldb, M, N, K, alpha, beta, C, ldc, kchunk, at<double>(c, 0),
+                                    c->stream));
         return GENINV_OK;
     }
     // a skinny product (few output tiles, long K) is split over K: about 1024
@@ -1625,8 +1643,34 @@ int geninv_bchain(geninv_ctx *c, int n, int m, int k, const double *P, int ldp, 
 struct MixedProbe {
     double *blk, *nrm;
     long L;
+    double *skin;   // (max(PROBE_PART, L) + L) PROBES doubles of scratch for probe_mm
     double *col(int i) const { return blk + (long)i * L * PROBES; }
 };
+
+// C (M x PROBES, leading dimension pr.L) = op(X) B, B K x PROBES (ldb): a
+// product with 16 columns and a long K reads X once and is bound by HBM, so
+// it runs on the bandwidth kernels of skinny.hip (X in place, or X' through
+// the transposed form), split into chunks of K so that about a thousand
+// workgroups stream X (at most PROBE_PART / M chunks: the partial sums' room).
+int probe_mm(geninv_ctx *c, const MixedProbe &pr, const double *X, long ldx, int tX, const double *B, long ldb,
+             double *C, int M, int K) {
+    const int p = PROBES;
+    if (M <= 0) return GENINV_OK;
+    if (K <= 0) {
+        HIPCHK(launch_fill(C, pr.L, M, p, 0.0, c->stream));
+        return GENINV_OK;
+    }
+    double *part = pr.skin, *Bt = pr.skin + std::max(PROBE_PART, pr.L) * p;
+    const long blocks = tX ? (M + 15) / 16 : (M + 255) / 256;   // workgroups per chunk of K
+    const int S = (int)std::max<long>(1, std::min<long>({64L, (1024 + blocks - 1) / blocks, (long)K / 256,
+                                                         PROBE_PART / M}));
+    const int kchunk = (K + S - 1) / S;
+    if (!tX)
+        HIPCHK(launch_skinny_gemm(X, ldx, B, ldb, 0, M, p, K, 1.0, 0.0, C, pr.L, kchunk, Bt, part, c->stream));
+    else
+        HIPCHK(launch_skinny_gemm_t(X, ldx, B, ldb, M, p, K, 1.0, 0.0, C, pr.L, kchunk, part, c->stream));
+    return GENINV_OK;
+}
 
 // resA terms (nrm[0], nrm[1]) right after the Gram matrix, mirrored to full
 // in A (the factorization reads only the lower triangle), and its diagonal
@@ -1639,7 +1683,7 @@ int probe_gram(geninv_ctx *c, const Layout &lay, const MixedProbe &pr, int m, in
     const long L = pr.L;
     double *V = pr.col(0), *W1 = pr.col(1), *W2 = pr.col(2), *U = pr.col(3);
     auto mm_ = [&](const double *X, long ldx, int tX, const double *Bm, long ldb, double *Cm, int M, int K) {
-        return gemm_splitk(c, lay, gemm(X, ldx, tX, Bm, ldb, 0, Cm, L, hdim(M), hdim(p), hdim(K), 1.0, 0.0));
+        return probe_mm(c, pr, X, ldx, tX, Bm, ldb, Cm, M, K);
     };
     HIPCHK(launch_fill(pr.nrm, 8, 8, 1, 0.0, c->stream));
     HIPCHK(launch_copy(A, lda + 1, diag, 1, hdim(1), hdim(nn), c->stream));
@@ -1667,7 +1711,7 @@ int probe_finish(geninv_ctx *c, const Layout &lay, const MixedProbe &pr, int m, 
     const long L = pr.L;
     double *Oy = pr.col(4), *T = pr.col(5), *Yr = pr.col(6), *Yo = pr.col(7);
     auto mm_ = [&](const double *X, long ldx, int tX, const double *Bm, long ldb, double *Cm, int M, int K) {
-        return gemm_splitk(c, lay, gemm(X, ldx, tX, Bm, ldb, 0, Cm, L, hdim(M), hdim(p), hdim(K), 1.0, 0.0));
+        return probe_mm(c, pr, X, ldx, tX, Bm, ldb, Cm, M, K);
     };
     HIPCHK(launch_probe_fill(Oy, L, m, p, 0x5eed0002ULL, c->stream));
     CHK(mm_(Y, ldy, 0, Oy, L, Yo, n, m));
@@ -1747,7 +1791,7 @@ int geninv_mixed(geninv_ctx *c, int m, int n, const double *G, int ldg, double t
         CHK(run_mod_product(c, mp.pg, mp.mg, tr ? 0 : 1, G, ldg, tr ? 1 : 0, G, ldg, A, ld));
     }
     const bool estimate = err_est || target > 0.0;
-    const MixedProbe pr{at<double>(c, mp.probe), at<double>(c, mp.norms), mp.pld};
+    const MixedProbe pr{at<double>(c, mp.probe), at<double>(c, mp.norms), mp.pld, at<double>(c, mp.skin)};
     double *diag = pr.nrm + 8;
     if (estimate) {
         HIPCHK(launch_mirror_lower(A, ld, hdim(nn), c->stream));

@@ -337,14 +337,9 @@ __global__ __launch_bounds__(CF::NT) void mod_reconstruct_kernel(ModRecArgs a) {
         const int c0 = by * TILE + wn * WTN + bb * 16 + 4 * (lane >> 4);
         if (r >= a.M || c0 >= a.N || (a.lower && r < c0)) continue;
         double t[4] = {0, 0, 0, 0}, T1[4] = {0, 0, 0, 0}, T2[4] = {0, 0, 0, 0}, T3[4] = {0, 0, 0, 0};
-        for (int l = 0; l < n; ++l) {
-            int R[4] = {0, 0, 0, 0};
-            for (int z = 0; z < a.splitk; ++z) {
-                const unsigned w = reinterpret_cast<const unsigned *>(a.R + ((long)l * a.splitk + z) * a.strideR)
-                    [(tile * CF::NG + g) * NT + tid];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) R[v] += (int)(signed char)((w >> (8 * v)) & 0xff);
-            }
+        const long word = (tile * CF::NG + g) * NT + tid;
+        // modulus l's residues of the 4 outputs: their sum over the K slices
+        auto accumulate = [&](int l, const int (&R)[4]) {
             const int y = a.mc.y[l];
             const double pf = a.mc.pf[l], invp = a.mc.invp[l];
 #pragma unroll
@@ -357,6 +352,31 @@ __global__ __launch_bounds__(CF::NT) void mod_reconstruct_kernel(ModRecArgs a) {
                 T1[v] = fma(s, a.mc.w1[l], T1[v]);
                 T2[v] = fma(s, a.mc.w2[l], T2[v]);
                 T3[v] = fma(s, a.mc.w3[l], T3[v]);
+            }
+        };
+        if (a.splitk == 1) {
+            // one residue word per modulus: all of them in flight at once
+            unsigned wv[MOD_MAX];
+#pragma unroll
+            for (int l = 0; l < MOD_MAX; ++l)
+                wv[l] = l < n ? reinterpret_cast<const unsigned *>(a.R + (long)l * a.strideR)[word] : 0u;
+#pragma unroll
+            for (int l = 0; l < MOD_MAX; ++l) {
+                if (l >= n) break;
+                int R[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R[v] = (int)(signed char)((wv[l] >> (8 * v)) & 0xff);
+                accumulate(l, R);
+            }
+        } else {
+            for (int l = 0; l < n; ++l) {
+                int R[4] = {0, 0, 0, 0};
+                for (int z = 0; z < a.splitk; ++z) {
+                    const unsigned w = reinterpret_cast<const unsigned *>(a.R + ((long)l * a.splitk + z) * a.strideR)[word];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) R[v] += (int)(signed char)((w >> (8 * v)) & 0xff);
+                }
+                accumulate(l, R);
             }
         }
         const int er = a.ea[r];

@@ -97,4 +97,111 @@ hipError_t launch_skinny_gemm(const double *A, long lda, const double *B, long l
     return launch_splitk_reduce(part, M, strideP, S, C, ldc, hdim(M), hdim(N), alpha, beta, GEMM_FULL, s);
 }
 
+// ---- transposed A: C (M x N) = alpha A' B + beta C, A (K x M), B (K x N),
+// N <= 16 -------------------------------------------------------------------
+//
+// The error estimate's G' V and G' (P V) (K = m rows of G, M = n columns).
+// Each wavefront owns SKT_COLS consecutive columns of A and walks the rows
+// of a chunk of K, one row per lane: every load of A covers 64 consecutive
+// rows of one column (coalesced), and the four wavefronts of a workgroup
+// (neighbouring column groups) load the same rows of B at the same time, so
+// B is fetched about once per workgroup.  A lane's SKT_COLS x NP sums are
+// reduced over the wavefront by a butterfly that halves the values each lane
+// keeps at every step (63 exchanges for 64 values instead of 6 per value),
+// and the chunks of K by the reduction kernel in a fixed order.
+
+constexpr int SKT_COLS = 4;     // columns of A (rows of C) per wavefront
+constexpr int SKT_UNROLL = 2;   // rows per lane per step (loads in flight: 2 (SKT_COLS + NP))
+
+// cur[0..W) summed over the wavefront: at offset O a lane keeps half of its
+// values (the upper half if lane & O) plus its partner's copy of that half;
+// once one value is left the remaining offsets add it up.  Afterwards the
+// lane holds the total of value index `base`.
+template <int W, int O>
+__device__ __forceinline__ void skt_butterfly(double *cur, int lane, int &base) {
+    if constexpr (O >= 1) {
+        if constexpr (W > 1) {
+            constexpr int H = W / 2;
+            const bool up = (lane & O) != 0;
+#pragma unroll
+            for (int t = 0; t < H; ++t) {
+                const double send = up ? cur[t] : cur[t + H];
+                const double keep = up ? cur[t + H] : cur[t];
+                cur[t] = keep + __shfl_xor(send, O);
+            }
+            if (up) base += H;
+            skt_butterfly<H, O / 2>(cur, lane, base);
+        } else {
+            cur[0] += __shfl_xor(cur[0], O);
+            skt_butterfly<1, O / 2>(cur, lane, base);
+        }
+    }
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void skt_partial_kernel(const double *__restrict__ A, long lda,
+                                                          const double *__restrict__ B, long ldb, int M, int N, int K,
+                                                          int kchunk, double *__restrict__ part, long strideP) {
+    constexpr int V = SKT_COLS * NP;   // sums per lane, value index c NP + q
+    static_assert(V <= 64 && (V & (V - 1)) == 0, "value count");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j0 = (blockIdx.x * 4 + wave) * SKT_COLS;
+    const int kb = blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+    const double *acol[SKT_COLS];
+#pragma unroll
+    for (int c = 0; c < SKT_COLS; ++c) acol[c] = A + (long)min(j0 + c, M - 1) * lda;
+    const double *bcol[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) bcol[q] = B + (long)min(q, N - 1) * ldb;
+    double acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+    for (int i0 = kb + lane; i0 < ke; i0 += SKT_UNROLL * 64) {
+        double av[SKT_UNROLL][SKT_COLS], bv[SKT_UNROLL][NP];
+#pragma unroll
+        for (int u = 0; u < SKT_UNROLL; ++u) {
+            const int i = i0 + u * 64;
+            const bool ok = i < ke;
+#pragma unroll
+            for (int c = 0; c < SKT_COLS; ++c) av[u][c] = ld_or(acol[c], i, ok, 0.0);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) bv[u][q] = ld_or(bcol[q], i, ok && q < N, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < SKT_UNROLL; ++u)
+#pragma unroll
+            for (int c = 0; c < SKT_COLS; ++c)
+#pragma unroll
+                for (int q = 0; q < NP; ++q) acc[c * NP + q] = __builtin_fma(av[u][c], bv[u][q], acc[c * NP + q]);
+    }
+    int base = 0;
+    skt_butterfly<V, 32>(acc, lane, base);
+    const int c = base / NP, q = base % NP;
+    if ((lane & (64 / V - 1)) == 0 && j0 + c < M && q < N)
+        part[(long)blockIdx.y * strideP + (j0 + c) + (long)q * M] = acc[0];
+}
+
+// part needs S * M * N doubles, S = ceil(K / kchunk); C = alpha * sum of the
+// partials + beta * C.
+hipError_t launch_skinny_gemm_t(const double *A, long lda, const double *B, long ldb, int M, int N, int K,
+                                double alpha, double beta, double *C, long ldc, int kchunk, double *part,
+                                hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (N > 16 || K <= 0 || kchunk <= 0) return hipErrorInvalidValue;
+    const int NP = skinny_padded_width(N);
+    const int S = (K + kchunk - 1) / kchunk;
+    const dim3 grid((M + 4 * SKT_COLS - 1) / (4 * SKT_COLS), S);
+    const long strideP = (long)M * N;
+    switch (NP) {
+    case 1: hipLaunchKernelGGL(skt_partial_kernel<1>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kchunk, part, strideP); break;
+    case 2: hipLaunchKernelGGL(skt_partial_kernel<2>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kchunk, part, strideP); break;
+    case 4: hipLaunchKernelGGL(skt_partial_kernel<4>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kchunk, part, strideP); break;
+    case 8: hipLaunchKernelGGL(skt_partial_kernel<8>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kchunk, part, strideP); break;
+    default: hipLaunchKernelGGL(skt_partial_kernel<16>, grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, kchunk, part, strideP); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_splitk_reduce(part, M, strideP, S, C, ldc, hdim(M), hdim(N), alpha, beta, GEMM_FULL, s);
+}
+
 }  // namespace geninv

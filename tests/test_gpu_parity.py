@@ -62,6 +62,11 @@ def _print_case(label, **kw):
     # skinny products (N <= 16, long K: row-per-thread kernel, K split in chunks)
     (3001, 1, 5000, 0, 0), (2048, 8, 8192, 0, 0), (999, 5, 2000, 0, 1), (4097, 16, 1500, 0, 0),
     (513, 3, 1024, 0, 1),
+    # the transposed form (A' B, a wavefront per four columns of A, a lane per
+    # row, butterfly reduction): ragged column blocks, every padded width,
+    # K split into many chunks where the columns are few
+    (3001, 1, 5000, 1, 0), (2048, 16, 8192, 1, 0), (999, 5, 2000, 1, 0), (4097, 16, 1500, 1, 0),
+    (6, 16, 40000, 1, 0), (1, 3, 1024, 1, 0), (130, 2, 70001, 1, 0),
 ])
 def test_dgemm_parity(M, N, K, tA, tB):
     _print_case("dgemm", M=M, N=N, K=K, tA=tA, tB=tB)
