@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 // TILE B rows) go straight from global memory into LDS
 // (global_load_lds_dwordx4, three buffers, loads two stages ahead).  A
 // wavefront's direct load fills a 1 KiB chunk of 16 rows; the four 16-byte
-// granules of row r sit XOR-permuted by (r / 4) mod 4 so that the fragment
+// granules of row r sit XOR-permuted by mg_swz(r) so that the fragment
 // reads (16 rows, one granule) meet distinct banks.  Every fragment address
 // is "buffer + opaque lane offset + constant", so the compiler keeps the
 // three buffers apart in its wait counts.  The grid is one-dimensional over
@@ -139,6 +139,15 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 // A operand), so lane l holds C(row l % 16, column 4 (l / 16) + v).
 // ---------------------------------------------------------------------------
 constexpr int MG_BK = 64, MG_GM = 8;
+
+// Slot of granule g of row r in LDS: g ^ mg_swz(r).  A fragment read has 16
+// consecutive rows at one granule; the LDS serves a 16-byte read for 8 (or
+// 16) consecutive lanes at a time, which must fall in distinct 16-byte bank
+// groups of 128 (or 256) bytes: with rows of 64 bytes that asks for distinct
+// slots among rows of equal r mod 2 in each 8 (and of equal r mod 4 in each
+// 16), which (r / 2 xor r / 4) mod 4 gives (a plain (r / 4) mod 4 leaves
+// rows r and r + 2 on one bank group).
+__device__ __forceinline__ int mg_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 constexpr int MG_MAX_STAGES = 1024;              // stages per split: sums of 65536 products
 
 template <int TILE_, int WM_, int WN_>
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(CF::NT) void mod_gemm_kernel(ModGemmArgs p) {
 
     // Direct loads: chunk q (16 rows; A rows for q < TILE / 16, B rows after)
     // is loaded by wavefront q % NWV.  Lane l fills row l / 4 of its chunk,
-    // slot l % 4, with granule (l % 4) ^ (l / 16).  Rows past M (N) are read
+    // slot l % 4, with granule (l % 4) ^ mg_swz(l / 4).  Rows past M (N) are read
     // clamped: they only reach outputs that are never stored.
     constexpr int ACH = TILE / 16;
     unsigned srcoff[CPW];
@@ -226,7 +235,7 @@ __global__ __launch_bounds__(CF::NT) void mod_gemm_kernel(ModGemmArgs p) {
     for (int i = 0; i < CPW; ++i) {
         const int q = wave + NWV * i;
         const int r = (q % ACH) * 16 + (lane >> 2);
-        const int g = (lane & 3) ^ (lane >> 4);
+        const int g = (lane & 3) ^ mg_swz(lane >> 2);
         srcoff[i] = q < ACH ? (unsigned)((long)min(row0 + r, p.M - 1) * p.lda + 16 * g)
                             : (unsigned)((long)min(col0 + r, p.N - 1) * p.ldb + 16 * g);
     }
@@ -247,7 +256,7 @@ __global__ __launch_bounds__(CF::NT) void mod_gemm_kernel(ModGemmArgs p) {
 
     // lane read offsets: row l % 16 of a 16-row block, granule l / 16
     constexpr int WTM = TILE / CF::WM, WTN = TILE / CF::WN;
-    int rda = (wm * WTM + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ ((lane >> 2) & 3));
+    int rda = (wm * WTM + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ mg_swz(lane & 15));
     int rdb = rda + (TILE + wn * WTN - wm * WTM) * 64;
     asm volatile("" : "+v"(rda), "+v"(rdb));
     auto compute = [&](const char *buf) {
