@@ -325,8 +325,11 @@ __global__ __launch_bounds__(WM * WN * 64) void dgemm_kernel(GemmArgs p) {
 //   MN-major operand (index contiguous in memory): [k][DM_LD] with a padded
 //     row pitch; one k row (128 doubles) is one wavefront load.
 //   K-major operand (k contiguous): [index][32], the 16 two-double granules
-//     of row i XOR-permuted by i mod 16, so that the matrix-core reads (16
-//     consecutive rows at one k) meet distinct banks; four rows per load.
+//     of row i XOR-permuted by i mod 16; four rows per load.  The matrix
+//     cores read it a granule (k, k + 1) per lane, 16 consecutive rows at a
+//     time, for two k steps at once: the LDS serves 16-byte reads 8 lanes at
+//     a time in 128-byte bank rounds, which the permutation keeps distinct
+//     (8-byte reads of one k would meet every bank twice).
 // Edge tiles and the last partial K chunk are staged through registers into
 // the same layouts.  The two stage buffers of each operand are separate LDS
 // arrays and every read address is array + opaque per-lane offset +
@@ -452,25 +455,31 @@ __global__ __launch_bounds__(64 * NW) void dgemm_dma_kernel(GemmArgs p) {
         }
     };
 
-    // ---- matrix-core reads: fragment a of the wavefront's rows wm*TM + 16a
-    // + (lane % 16) at k = kk + lane / 16.  MN-major: one per-lane offset;
-    // K-major: one per-lane offset for each of the 8 k steps of a chunk.
-    int aro[DM_BK / 4], bro[DM_BK / 4];
+    // ---- matrix-core reads.  The chunk's 32 k go to the 8 k steps of the
+    // 16 x 16 x 4 instruction as k = 8 (s / 2) + 2 (lane / 16) + s % 2 (any
+    // assignment that both operands share sums the same products), so that
+    // steps 2 t and 2 t + 1 of a K-major operand come from one granule.
+    // Fragment a covers the wavefront's rows wm*TM + 16a + (lane % 16).
+    // MN-major: one per-lane offset (k = 2 (lane / 16)) plus a constant per
+    // step; K-major: one per-lane offset per step pair t (k = 8 t + 2 (lane / 16)).
+    int aro[DM_BK / 8], bro[DM_BK / 8];
 #pragma unroll
-    for (int s = 0; s < DM_BK / 4; ++s) {
-        const int k = 4 * s + (lane >> 4);
-        aro[s] = 8 * OA::lds_index(lane & 15, k);
-        bro[s] = 8 * OB::lds_index(lane & 15, k);
-        if (!AK && s > 0) aro[s] = aro[0];
-        if (!BK_ && s > 0) bro[s] = bro[0];
+    for (int t = 0; t < DM_BK / 8; ++t) {
+        const int k = 8 * t + 2 * (lane >> 4);
+        aro[t] = 8 * OA::lds_index(lane & 15, k);
+        bro[t] = 8 * OB::lds_index(lane & 15, k);
+        if (!AK && t > 0) aro[t] = aro[0];
+        if (!BK_ && t > 0) bro[t] = bro[0];
     }
 #pragma unroll
-    for (int s = 0; s < DM_BK / 4; ++s) {
-        if (AK || s == 0) asm volatile("" : "+v"(aro[s]));
-        if (BK_ || s == 0) asm volatile("" : "+v"(bro[s]));
+    for (int t = 0; t < DM_BK / 8; ++t) {
+        if (AK || t == 0) asm volatile("" : "+v"(aro[t]));
+        if (BK_ || t == 0) asm volatile("" : "+v"(bro[t]));
     }
     // byte offset of row block r (a multiple of 16) at k step s, beyond the lane offset
-    auto rconst = [&](bool kmaj, int r, int s) { return kmaj ? 8 * r * DM_BK : 8 * (4 * s * DM_LD + r); };
+    auto rconst = [&](bool kmaj, int r, int s) {
+        return kmaj ? 8 * r * DM_BK : 8 * ((8 * (s / 2) + s % 2) * DM_LD + r);
+    };
 
     constexpr int FLUSH_CHUNKS = KFLUSH / DM_BK;
     // FL: two-level sums (acc restarted every KFLUSH of K, totals in tot);
@@ -487,22 +496,44 @@ __global__ __launch_bounds__(64 * NW) void dgemm_dma_kernel(GemmArgs p) {
     // chunk (at kn, into na / nb) are spread over its first k steps
     auto compute = [&](const char *as, const char *bs, bool pf, int kn, char *na, char *nb) {
 #pragma unroll
-        for (int s = 0; s < DM_BK / 4; ++s) {
-            if (s < PIECES && pf) dma_piece(s, kn, na, nb);
-            double af[FM], bf[FN];
+        for (int t = 0; t < DM_BK / 8; ++t) {
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
-                af[a] = *reinterpret_cast<const double *>(as + (AK ? aro[s] : aro[0]) +
-                                                          rconst(AK, wm * TM + a * 16, s));
+            for (int h = 0; h < 2; ++h)
+                if (2 * t + h < PIECES && pf) dma_piece(2 * t + h, kn, na, nb);
+            double af[2][FM], bf[2][FN];
 #pragma unroll
-            for (int b = 0; b < FN; ++b)
-                bf[b] = *reinterpret_cast<const double *>(bs + (BK_ ? bro[s] : bro[0]) +
-                                                          rconst(BK_, wn * TN + b * 16, s));
+            for (int a = 0; a < FM; ++a) {
+                if (AK) {
+                    const d2 v = *reinterpret_cast<const d2 *>(as + aro[t] + rconst(true, wm * TM + a * 16, 0));
+                    af[0][a] = v.x;
+                    af[1][a] = v.y;
+                } else {
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+                    for (int h = 0; h < 2; ++h)
+                        af[h][a] = *reinterpret_cast<const double *>(as + aro[0] +
+                                                                      rconst(false, wm * TM + a * 16, 2 * t + h));
+                }
+            }
 #pragma unroll
-                for (int b = 0; b < FN; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < FN; ++b) {
+                if (BK_) {
+                    const d2 v = *reinterpret_cast<const d2 *>(bs + bro[t] + rconst(true, wn * TN + b * 16, 0));
+                    bf[0][b] = v.x;
+                    bf[1][b] = v.y;
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        bf[h][b] = *reinterpret_cast<const double *>(bs + bro[0] +
+                                                                      rconst(false, wn * TN + b * 16, 2 * t + h));
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[h][b], af[h][a], acc[a][b], 0, 0, 0);
         }
     };
 
