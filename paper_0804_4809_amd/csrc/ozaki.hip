@@ -181,12 +181,16 @@ __global__ __launch_bounds__(256) void slice_rows_t_kernel(const double *X, long
 // each wavefront then forms the slice pairs from its registers.
 // Such a load writes 16 consecutive bytes per lane, a wavefront a 1 KiB
 // chunk of 16 rows; the four 16-byte granules of row r sit in the chunk
-// XOR-permuted by (r / 4) mod 4, so that the operand reads (16 rows, one
-// granule) meet distinct banks.  The grid is one-dimensional over the needed
+// XOR-permuted by sg_swz(r), so that the operand reads (16 rows, one
+// granule) meet distinct banks: the LDS serves 16-byte reads 8 (or 16)
+// consecutive lanes at a time in bank rounds of 128 (or 256) bytes, which
+// asks for distinct slots among the rows of equal r mod 2 in each 8 (and of
+// equal r mod 4 in each 16); (r / 2 xor r / 4) mod 4 gives both.  The grid is one-dimensional over the needed
 // tiles (lower triangle for the Gram matrix); each XCD takes a contiguous run
 // of a tile order that walks groups of SG_GM tile rows column by column.
 // ---------------------------------------------------------------------------
 constexpr int SG_BM = 128, SG_BN = 64, SG_BK = 32;
+__device__ __forceinline__ int sg_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 constexpr int SG_ROWS = SG_BM + SG_BN;    // LDS rows per slice per stage: A rows, then B rows
 constexpr int SG_CHUNKS = SG_ROWS / 16;  // 1 KiB LDS chunks (16 rows of 64 bytes) per slice per stage
 constexpr int SG_NT = 512;
@@ -299,7 +303,7 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
     // Direct loads of a stage: chunk q (slice q / 12; A rows for the first 8
     // chunks of a slice, B rows for the last 4) is loaded by wavefront q % 8.
     // Lane l fills row l / 4 of its chunk, slot l % 4, with granule
-    // (l % 4) ^ (l / 16).  Rows past M (N) are read clamped: they only reach
+    // (l % 4) ^ sg_swz(l / 4).  Rows past M (N) are read clamped: they only reach
     // rows (columns) of C that are never stored.
     constexpr int NCH = S * SG_CHUNKS;
     constexpr int CPW = (NCH + 7) / 8;   // chunks per wavefront
@@ -311,7 +315,7 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
         const int q = wave + 8 * i < NCH ? wave + 8 * i : wave;
         const int cq = q % SG_CHUNKS;
         const int r = (cq % 8) * 16 + (lane >> 2);
-        const int g = (lane & 3) ^ (lane >> 4);
+        const int g = (lane & 3) ^ sg_swz(lane >> 2);
         srcoff[i] = cq < 8 ? (unsigned)((long)min(row0 + r, p.M - 1) * p.lda + 8 * g)
                            : (unsigned)((long)min(col0 + r, p.N - 1) * p.ldb + 8 * g);
     }
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(SG_NT) void sliced_gemm_kernel(SlicedGemmArgs p) {
     // opaque, so that every fragment address is one array plus this offset
     // plus a constant: the compiler then still sees which stage buffer a read
     // touches, and does not make it wait for loads into the other buffers.
-    int rda = (wm * 32 + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ ((lane >> 2) & 3));
+    int rda = (wm * 32 + (lane & 15)) * 64 + 16 * ((lane >> 4) ^ sg_swz(lane & 15));
     int rdb = rda + (SG_BM + wn * 32 - wm * 32) * 64;
     asm volatile("" : "+v"(rda), "+v"(rdb));
     auto compute = [&](const char *buf) {
