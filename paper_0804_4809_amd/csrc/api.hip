@@ -305,7 +305,10 @@ int gemm_fill(geninv_ctx *c, const Layout &lay, GemmArgs g) {
     }
     const long tiles = g.uplo == GEMM_LOWER ? lower_tiles128((int)M) : ((M + 127) / 128) * ((N + 127) / 128);
     const int cap = (int)std::min<size_t>(64, lay.split_elems / (size_t)(M * N));
-    const int S = tiles >= 256 ? 0 : fill_splits(tiles, K, cap);
+    // too few tiles for one round: the cheapest split that fills it; else a
+    // split only where the cost model gains on the partly idle last round
+    // (L'L of order 3072: 300 tiles run 2 rounds, the second one 17 % full)
+    const int S = tiles >= 256 ? choose_splits(tiles, K, cap) : fill_splits(tiles, K, cap);
     if (S < 2) {
         HIPCHK(launch_dgemm(g, c->stream));
         return GENINV_OK;
