@@ -28,6 +28,15 @@ namespace geninv {
 constexpr int BT_THREADS = 256;
 constexpr int BT_STAGE_ROWS = 16;
 
+// LDS layouts against bank conflicts (the LDS serves 8-byte reads 16 lanes
+// at a time over 32 four-byte banks).  A stage row keeps element c at
+// c + c / 16 and has an odd pitch: the Gram's reads of four consecutive
+// elements per thread (thread t at 4 t) then meet 16 distinct bank pairs, and
+// the staging writes (16 rows at one element) too.  The blocked routines'
+// panels (NB columns of consecutive rows) have an odd row pitch NB + 1.
+__device__ __forceinline__ int stage_pos(int c) { return c + (c >> 4); }
+__host__ __device__ constexpr int stage_pitch(int w) { return (w + ((w + 15) >> 4)) | 1; }
+
 __device__ __forceinline__ double ldv(const float *p) { return (double)*p; }
 __device__ __forceinline__ double ldv(const double *p) { return *p; }
 
@@ -46,6 +55,7 @@ __device__ __forceinline__ void block_gram(const T *X, long ldx, int rows, int n
     const int tri_tiles = nt * (nt + 1);
     const int ntiles = tri_tiles + nt * kt;
     const int sw = nc + k;                 // stage width (columns)
+    const int swp = stage_pitch(sw);
     for (int base = 0; base < ntiles; base += BT_THREADS) {
         const int t = base + tid;
         int ti = 0, tj = 0;
@@ -68,6 +78,12 @@ __device__ __forceinline__ void block_gram(const T *X, long ldx, int rows, int n
         for (int a = 0; a < 8; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        // stage positions: 8 ti + a and 4 tj + b share their padding for
+        // a < 8, b < 4 (F columns start at nc, anywhere: one per column)
+        const int apos = 8 * ti + (ti >> 1);
+        int bpos[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bpos[b] = fcol ? stage_pos(nc + tj * 4 + b) : 4 * tj + (tj >> 2) + b;
         for (int k0 = 0; k0 < rows; k0 += BT_STAGE_ROWS) {
             __syncthreads();
             // branch-free loads (clamped address, then select) so that a
@@ -80,23 +96,23 @@ __device__ __forceinline__ void block_gram(const T *X, long ldx, int rows, int n
                 const bool ok = row < rows && (!inx || !tri || row >= src);
                 const T *p = inx ? X + row + (long)src * ldx : F + row + (long)(c - nc) * ldf;
                 const double v = ldv(ok ? p : X);
-                stage[r * sw + c] = ok ? v : 0.0;
+                stage[r * swp + stage_pos(c)] = ok ? v : 0.0;
             }
             __syncthreads();
             if (active) {
 #pragma unroll 4
                 for (int r = 0; r < BT_STAGE_ROWS; ++r) {
                     double av[8], bv[4];
-                    const double *srow = stage + r * sw;
+                    const double *srow = stage + r * swp;
 #pragma unroll
                     for (int a = 0; a < 8; ++a) {
                         const int ci = ti * 8 + a;
-                        av[a] = ci < nc ? srow[ci] : 0.0;
+                        av[a] = ci < nc ? srow[apos + a] : 0.0;
                     }
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const int cj = fcol ? nc + tj * 4 + b : tj * 4 + b;
-                        bv[b] = (fcol ? (tj * 4 + b < k) : (cj < nc)) ? srow[cj] : 0.0;
+                        bv[b] = (fcol ? (tj * 4 + b < k) : (cj < nc)) ? srow[bpos[b]] : 0.0;
                     }
 #pragma unroll
                     for (int a = 0; a < 8; ++a)
@@ -185,33 +201,34 @@ __device__ __forceinline__ int block_frchol(double *A, long lda, int n, double t
 
 // The same full-rank Cholesky for A in global memory (the per-workgroup
 // slab), in panels of NB columns: a panel (rows j0..n-1) is factored column
-// by column in LDS (ws, n x NB) with the paper's strict test, written back,
+// by column in LDS (ws, n x NB, row pitch NB + 1) with the paper's strict test, written back,
 // and the columns to its right take one rank-NB update (4 x 4 register
 // tiles) instead of one update per column.  Decisions and kept values are
 // those of the column-by-column form up to the grouping of the updates.
 template <int NB>
 __device__ __forceinline__ int block_frchol_blocked(double *A, long lda, int n, double tol, int *cols, int *cnt, double *ws) {
     const int tid = threadIdx.x;
-    double *Ps = ws;   // Ps[i * NB + c] = A(i, j0 + c)
+    constexpr int PP = NB + 1;   // panel row pitch
+    double *Ps = ws;   // Ps[i * PP + c] = A(i, j0 + c)
     if (tid == 0) *cnt = 0;
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int nb = min(NB, n - j0);
         __syncthreads();
         for (int e = tid; e < (n - j0) * nb; e += BT_THREADS) {
             const int i = j0 + e % (n - j0), c = e / (n - j0);
-            Ps[i * NB + c] = i >= j0 + c ? A[i + (long)(j0 + c) * lda] : 0.0;
+            Ps[i * PP + c] = i >= j0 + c ? A[i + (long)(j0 + c) * lda] : 0.0;
         }
         for (int c = 0; c < nb; ++c) {
             const int j = j0 + c;
             __syncthreads();
-            const double d = Ps[j * NB + c];
+            const double d = Ps[j * PP + c];
             const bool keep = d > tol;
             __syncthreads();   // every thread has read the pivot before it is overwritten
             if (keep) {
                 const double sq = sqrt(d);
-                for (int i = j + 1 + tid; i < n; i += BT_THREADS) Ps[i * NB + c] /= sq;
+                for (int i = j + 1 + tid; i < n; i += BT_THREADS) Ps[i * PP + c] /= sq;
                 if (tid == 0) {
-                    Ps[j * NB + c] = sq;
+                    Ps[j * PP + c] = sq;
                     cols[*cnt] = j;
                     *cnt = *cnt + 1;
                 }
@@ -219,16 +236,16 @@ __device__ __forceinline__ int block_frchol_blocked(double *A, long lda, int n, 
                 // the panel's later columns: Ps(i, c2) -= L(i, j) L(j0 + c2, j), i >= j0 + c2
                 for (int e = tid; e < (n - j0) * nb; e += BT_THREADS) {
                     const int i = j0 + e % (n - j0), c2 = e / (n - j0);
-                    if (c2 > c && i >= j0 + c2) Ps[i * NB + c2] -= Ps[i * NB + c] * Ps[(j0 + c2) * NB + c];
+                    if (c2 > c && i >= j0 + c2) Ps[i * PP + c2] -= Ps[i * PP + c] * Ps[(j0 + c2) * PP + c];
                 }
             } else {
-                for (int i = j + tid; i < n; i += BT_THREADS) Ps[i * NB + c] = 0.0;
+                for (int i = j + tid; i < n; i += BT_THREADS) Ps[i * PP + c] = 0.0;
             }
         }
         __syncthreads();
         for (int e = tid; e < (n - j0) * nb; e += BT_THREADS) {
             const int i = j0 + e % (n - j0), c = e / (n - j0);
-            if (i >= j0 + c) A[i + (long)(j0 + c) * lda] = Ps[i * NB + c];
+            if (i >= j0 + c) A[i + (long)(j0 + c) * lda] = Ps[i * PP + c];
         }
         // columns l >= j0 + nb, rows i >= l: A(i, l) -= sum_c L(i, j0 + c) L(l, j0 + c)
         const int t0 = j0 + nb, nt = (n - t0 + 3) / 4;
@@ -240,14 +257,14 @@ __device__ __forceinline__ int block_frchol_blocked(double *A, long lda, int n, 
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < NB; ++c) q[a][c] = (c < nb && i0 + a < n) ? Ps[(i0 + a) * NB + c] : 0.0;
+                for (int c = 0; c < NB; ++c) q[a][c] = (c < nb && i0 + a < n) ? Ps[(i0 + a) * PP + c] : 0.0;
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
                 const int l = l0 + bb;
                 if (l >= n) continue;
                 double x[NB];
 #pragma unroll
-                for (int c = 0; c < NB; ++c) x[c] = c < nb ? Ps[l * NB + c] : 0.0;
+                for (int c = 0; c < NB; ++c) x[c] = c < nb ? Ps[l * PP + c] : 0.0;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     const int i = i0 + a;
@@ -302,12 +319,13 @@ __device__ __forceinline__ bool block_gj(double *C, long ldc, int r, double *row
 // (D = C_bb, Q = old block column, R = block row):
 //   D^-1 in LDS;  R' = D^-1 R;  C_ij -= Q_i R'_j  (i, j outside the block);
 //   C_bj = R'_j;  C_ib = -Q_i D^-1;  C_bb = D^-1.
-// ws (LDS) holds Q (r x NB), R' (NB x r) and D (NB x NB).
+// ws (LDS) holds Q (r x NB, row pitch NB + 1), R' (NB x r) and D (NB x NB).
 template <int NB>
 __device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
     const int tid = threadIdx.x;
-    double *Qs = ws;                    // Qs[i * NB + c] = C(i, b0 + c)
-    double *Rs = Qs + (long)r * NB;     // Rs[c * r + j] = C(b0 + c, j), then R'
+    constexpr int QP = NB + 1;          // Qs row pitch
+    double *Qs = ws;                    // Qs[i * QP + c] = C(i, b0 + c)
+    double *Rs = Qs + (long)r * QP;     // Rs[c * r + j] = C(b0 + c, j), then R'
     double *Ds = Rs + (long)NB * r;     // Ds[c * NB + c'] = D(c, c'), then D^-1
     bool ok = true;
     for (int b0 = 0; b0 < r; b0 += NB) {
@@ -315,7 +333,7 @@ __device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, dou
         __syncthreads();
         for (int e = tid; e < r * nb; e += BT_THREADS) {
             const int i = e % r, c = e / r;
-            Qs[i * NB + c] = C[i + (long)(b0 + c) * ldc];
+            Qs[i * QP + c] = C[i + (long)(b0 + c) * ldc];
         }
         for (int e = tid; e < nb * r; e += BT_THREADS) {
             const int c = e % nb, j = e / nb;
@@ -324,7 +342,7 @@ __device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, dou
         __syncthreads();
         for (int e = tid; e < nb * nb; e += BT_THREADS) {
             const int c = e % nb, c2 = e / nb;
-            Ds[c * NB + c2] = Qs[(b0 + c) * NB + c2];
+            Ds[c * NB + c2] = Qs[(b0 + c) * QP + c2];
         }
         // D^-1 in place, one pivot at a time (at most 2 elements per thread)
         for (int p = 0; p < nb; ++p) {
@@ -380,7 +398,7 @@ __device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, dou
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int c = 0; c < NB; ++c) q[a][c] = (c < nb && i0 + a < r) ? Qs[(i0 + a) * NB + c] : 0.0;
+                for (int c = 0; c < NB; ++c) q[a][c] = (c < nb && i0 + a < r) ? Qs[(i0 + a) * QP + c] : 0.0;
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) {
                 const int j = j0 + bb;
@@ -417,15 +435,15 @@ struct BatchDesc {
     int pad;
 };
 
-__global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
+__global__ __launch_bounds__(BT_THREADS, 2) void batched_lstsq_kernel(const BatchDesc *desc, const int *order, int batch,
                                                                    int k, double user_tol, int nl, int *queue,
                                                                    double *slabs, long slab_stride, int nmax,
                                                                    int *rank, int *status) {
     extern __shared__ __attribute__((aligned(16))) double lds[];
-    // LDS carve-up: [nl*nl] big | [8*(nmax+k)] stage | [256] red | [nmax] rowp | [nmax] colp | ints
+    // LDS carve-up: [nl*nl] big | [16*stage_pitch(nmax+k)] stage | [256] red | [nmax] rowp | [nmax] colp | ints
     double *big = lds;
     double *stage = big + (long)nl * nl;
-    double *red = stage + BT_STAGE_ROWS * (nmax + k);
+    double *red = stage + BT_STAGE_ROWS * stage_pitch(nmax + k);
     double *rowp = red + BT_THREADS;
     double *colp = rowp + nmax;
     int *cols = reinterpret_cast<int *>(colp + nmax);
@@ -442,13 +460,13 @@ __global__ __launch_bounds__(BT_THREADS) void batched_lstsq_kernel(const BatchDe
     // The blocked Cholesky and Gauss-Jordan keep their panels in the LDS
     // matrix region and the staging rows behind it (contiguous, and both
     // idle while A or L'L lives in the slab).  Block width 8 or 4, whichever
-    // is the larger that fits: panels of nmax x NB (Cholesky), 2 nmax NB +
-    // NB^2 doubles (Gauss-Jordan).
-    const long ws_cap = (long)nl * nl + (long)BT_STAGE_ROWS * (nmax + k);
+    // is the larger that fits: panels of nmax (NB + 1) doubles (Cholesky),
+    // nmax (2 NB + 1) + NB^2 (Gauss-Jordan).
+    const long ws_cap = (long)nl * nl + (long)BT_STAGE_ROWS * stage_pitch(nmax + k);
     int gj_nb = 0, fr_nb = 0;
     for (int nbc = 8; nbc >= 4; nbc /= 2) {
-        if (gj_nb == 0 && ws_cap >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
-        if (fr_nb == 0 && ws_cap >= (long)nmax * nbc) fr_nb = nbc;
+        if (gj_nb == 0 && ws_cap >= (long)nmax * (2 * nbc + 1) + (long)nbc * nbc) gj_nb = nbc;
+        if (fr_nb == 0 && ws_cap >= (long)nmax * (nbc + 1)) fr_nb = nbc;
     }
     for (;;) {
         if (tid == 0) ints[0] = atomicAdd(queue, 1);
@@ -530,7 +548,8 @@ __global__ void reset_queue_kernel(int *q) {
 }
 
 size_t batched_lds_bytes(int nl, int nmax, int k) {
-    return sizeof(double) * ((size_t)nl * nl + (size_t)BT_STAGE_ROWS * (nmax + k) + BT_THREADS + 2 * (size_t)nmax) +
+    return sizeof(double) * ((size_t)nl * nl + (size_t)BT_STAGE_ROWS * stage_pitch(nmax + k) + BT_THREADS +
+                             2 * (size_t)nmax) +
            sizeof(int) * ((size_t)nmax + 4);
 }
 
@@ -576,6 +595,7 @@ __device__ __forceinline__ void block_gram_rows(const float *G, long ldg, int m,
     const int tid = threadIdx.x;
     const int nt = (m + 7) / 8;
     const int ntiles = nt * (nt + 1);
+    const int swp = stage_pitch(m);
     for (int base = 0; base < ntiles; base += BT_THREADS) {
         const int t = base + tid;
         int ti = 0, tj = 0;
@@ -591,6 +611,7 @@ __device__ __forceinline__ void block_gram_rows(const float *G, long ldg, int m,
         for (int a = 0; a < 8; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        const int apos = 8 * ti + (ti >> 1), bpos = 4 * tj + (tj >> 2);   // stage positions of 8 ti and 4 tj
         for (int k0 = 0; k0 < n; k0 += BT_STAGE_ROWS) {
             __syncthreads();
             // stage row r = column k0 + r of G (m consecutive floats)
@@ -598,23 +619,23 @@ __device__ __forceinline__ void block_gram_rows(const float *G, long ldg, int m,
                 const int c = e % m, r = e / m;
                 const bool ok = k0 + r < n;
                 const double v = (double)G[ok ? c + (long)(k0 + r) * ldg : 0];
-                stage[r * m + c] = ok ? v : 0.0;
+                stage[r * swp + stage_pos(c)] = ok ? v : 0.0;
             }
             __syncthreads();
             if (active) {
 #pragma unroll 4
                 for (int r = 0; r < BT_STAGE_ROWS; ++r) {
                     double av[8], bv[4];
-                    const double *srow = stage + r * m;
+                    const double *srow = stage + r * swp;
 #pragma unroll
                     for (int a = 0; a < 8; ++a) {
                         const int ci = ti * 8 + a;
-                        av[a] = ci < m ? srow[ci] : 0.0;
+                        av[a] = ci < m ? srow[apos + a] : 0.0;
                     }
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const int cj = tj * 4 + b;
-                        bv[b] = cj < m ? srow[cj] : 0.0;
+                        bv[b] = cj < m ? srow[bpos + b] : 0.0;
                     }
 #pragma unroll
                     for (int a = 0; a < 8; ++a)
@@ -636,14 +657,14 @@ __device__ __forceinline__ void block_gram_rows(const float *G, long ldg, int m,
     __syncthreads();
 }
 
-__global__ __launch_bounds__(BT_THREADS) void batched_wide_kernel(const BatchDesc *desc, const int *order, int batch,
+__global__ __launch_bounds__(BT_THREADS, 2) void batched_wide_kernel(const BatchDesc *desc, const int *order, int batch,
                                                                   int k, double user_tol, int nl, int *queue,
                                                                   double *slabs, long slab_stride, int nmax,
                                                                   int *rank, int *status) {
     extern __shared__ __attribute__((aligned(16))) double lds[];
     double *big = lds;
     double *stage = big + (long)nl * nl;
-    double *red = stage + BT_STAGE_ROWS * (nmax + k);
+    double *red = stage + BT_STAGE_ROWS * stage_pitch(nmax + k);
     double *rowp = red + BT_THREADS;
     double *colp = rowp + nmax;
     int *cols = reinterpret_cast<int *>(colp + nmax);
@@ -657,11 +678,11 @@ __global__ __launch_bounds__(BT_THREADS) void batched_wide_kernel(const BatchDes
     double *Xv = Tv + (long)nmax * k;
 
     const int tid = threadIdx.x;
-    const long ws_cap = (long)nl * nl + (long)BT_STAGE_ROWS * (nmax + k);
+    const long ws_cap = (long)nl * nl + (long)BT_STAGE_ROWS * stage_pitch(nmax + k);
     int gj_nb = 0, fr_nb = 0;
     for (int nbc = 8; nbc >= 4; nbc /= 2) {
-        if (gj_nb == 0 && ws_cap >= 2L * nmax * nbc + (long)nbc * nbc) gj_nb = nbc;
-        if (fr_nb == 0 && ws_cap >= (long)nmax * nbc) fr_nb = nbc;
+        if (gj_nb == 0 && ws_cap >= (long)nmax * (2 * nbc + 1) + (long)nbc * nbc) gj_nb = nbc;
+        if (fr_nb == 0 && ws_cap >= (long)nmax * (nbc + 1)) fr_nb = nbc;
     }
     for (;;) {
         if (tid == 0) ints[0] = atomicAdd(queue, 1);

@@ -108,7 +108,9 @@ def test_batched_wide_problems_take_the_transpose_branch():
     R = rng.standard_normal((6, 90)).astype(np.float32)
     Gs.append(np.concatenate([R, R[:2]], axis=0)); Fs.append(rng.standard_normal((8, 4)).astype(np.float32))
     plan = api.BatchPlan(Gs, Fs)
-    for nl, grid in [(0, 256), (128, 256)]:
+    # the largest LDS threshold whose LDS fits (order up to 200 and 4
+    # right-hand sides: 112)
+    for nl, grid in [(0, 256), (112, 256)]:
         plan.config(nl, grid)
         plan.Wbuf.zero_()
         plan.run(use_graph=False)
@@ -122,7 +124,7 @@ def test_batched_random_uneven_sizes_all_lds_thresholds():
     print("[case] batched 96 problems", flush=True)
     B = w.batch_lowrank(96, seed=11, m_hi=600, n_hi=200)
     plan = api.BatchPlan(B.G, B.F)
-    for nl, grid in [(0, 256), (64, 512), (128, 256), (32, 1024)]:
+    for nl, grid in [(0, 256), (64, 512), (112, 256), (32, 1024)]:
         plan.config(nl, grid)
         plan.Wbuf.zero_()
         plan.run(use_graph=False)
