@@ -132,7 +132,6 @@ MIXED_C3 = [
 ]
 MIXED_C5 = [
     ("int8_m16", 2, 16, 16, 0),
-    ("int8_g14_c13", 2, 14, 13, 0),
     ("int8_m16_ns1", 2, 16, 16, 1),
     ("bf16_s4", 1, 4, 4, 0),
 ]
