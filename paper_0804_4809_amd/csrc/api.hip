@@ -622,9 +622,10 @@ ModPlan mod_plan(size_t base, int M, int N, int K, const ModConsts &mc, bool sam
         off += align256(bytes);
         return o;
     };
-    P.sa = (long)P.Kpad * M;
+    // planes hold whole 16-row groups (the GEMM loads 16 rows at a time)
+    P.sa = (long)P.Kpad * ((M + 15) / 16 * 16);
     P.pa = take((size_t)mc.n * P.sa);
-    P.sb = same ? P.sa : (long)P.Kpad * N;
+    P.sb = same ? P.sa : (long)P.Kpad * ((N + 15) / 16 * 16);
     P.pb = same ? P.pa : take((size_t)mc.n * P.sb);
     P.ea = take((size_t)std::max(M, 1) * sizeof(int));
     P.eb = same ? P.ea : take((size_t)std::max(N, 1) * sizeof(int));

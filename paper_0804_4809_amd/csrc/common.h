@@ -145,8 +145,8 @@ struct ModConsts {
     double log2M;
 };
 struct ModGemmArgs {
-    const int8_t *A; long lda; long sa;   // opA(i, k) = A[l sa + k + i lda]  (int8 residue planes)
-    const int8_t *B; long ldb; long sb;   // opB(k, j) = B[l sb + k + j ldb]
+    const int8_t *A; long lda; long sa;   // int8 residue plane l of opA at A + l sa: 1 KiB blocks of 16 rows x 64 k
+    const int8_t *B; long ldb; long sb;   // (lda = ldb = Kpad bytes per row), see modular.hip
     int M, N, Kpad;                       // Kpad: multiple of 64, zero padded
     int lower;                            // tiles on or below the diagonal only (M == N)
     int cfg;                              // 0: 128 x 128 tiles, 1: 256 x 256 tiles

@@ -39,6 +39,23 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 // residues of the integer representation
 // ---------------------------------------------------------------------------
 
+// Residue planes are stored in 1 KiB blocks of 16 rows x 64 k, row group
+// major (a row group's K extent is contiguous), each block already in the
+// GEMM's LDS layout: granule g (16 k) of row r at slot g ^ mg_swz(r mod 16).
+// A direct load of 16 rows of a stage is then one contiguous 1 KiB read
+// (whole cache lines), not 64-byte halves of 16 lines.  The slot permutation
+// makes the GEMM's 16-byte fragment reads (16 rows, one granule)
+// bank-conflict free: the LDS serves them 8 (or 16) consecutive lanes at a
+// time in bank rounds of 128 (or 256) bytes, which asks for distinct slots
+// among rows of equal r mod 2 in each 8 (and of equal r mod 4 in each 16).
+__host__ __device__ __forceinline__ int mg_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+// byte offset of element (row i, k) in a plane with ldp = Kpad bytes per row
+__device__ __forceinline__ long mg_plane_off(long i, long k, long ldp) {
+    return (i >> 4) * 16 * ldp + (k >> 6) * 1024 + (i & 15) * 64 + 16 * (((k & 63) >> 4) ^ mg_swz((int)(i & 15))) +
+           (k & 15);
+}
+
 // x (an integer valued double, |x| <= 2^52) mod p, balanced to |r| <= p/2.
 // q = rint(x / p) is within one of the nearest integer (x * (1/p) is off by
 // less than |x| 2^-52 / p < 1), and x - q p is exact: one correction.
@@ -63,9 +80,9 @@ __device__ __forceinline__ uint4 residues16(const double (&v)[16], double p, dou
     return uint4{w[0], w[1], w[2], w[3]};
 }
 
-// planes[l][k + j ldp] = representation of X(k, j) mod p_l, column exponent
-// e[j]; k = rows .. ldp-1 written as zeros.  A thread takes 16 consecutive k
-// of one column (one 16-byte store per modulus).
+// plane l, element (j, k) = representation of X(k, j) mod p_l, column
+// exponent e[j]; k = rows .. ldp-1 written as zeros.  A thread takes 16
+// consecutive k of one column (one 16-byte store per modulus).
 __global__ __launch_bounds__(256) void mod_slice_cols_kernel(const double *X, long ldx, int rows, int cols,
                                                              const int *e, int beta, ModConsts mc, int8_t *planes,
                                                              long ldp, long sp) {
@@ -78,11 +95,11 @@ __global__ __launch_bounds__(256) void mod_slice_cols_kernel(const double *X, lo
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = rint(ldexp(ld_or(col, k0 + q, k0 + q < rows, 0.0), sh));
     for (int l = 0; l < mc.n; ++l)
-        *reinterpret_cast<uint4 *>(planes + l * sp + k0 + (long)j * ldp) = residues16(v, mc.pf[l], mc.invp[l]);
+        *reinterpret_cast<uint4 *>(planes + l * sp + mg_plane_off(j, k0, ldp)) = residues16(v, mc.pf[l], mc.invp[l]);
 }
 
-// transposed: planes[l][k + i ldp] = representation of X(i, k) mod p_l, row
-// exponent e[i]; k = cols .. ldp-1 zero.  A 64 x 64 (rows x k) tile of X is
+// transposed: plane l, element (i, k) = representation of X(i, k) mod p_l,
+// row exponent e[i]; k = cols .. ldp-1 zero.  A 64 x 64 (rows x k) tile of X is
 // staged through LDS: read down the columns (64 rows = 512 contiguous bytes),
 // then each thread takes 16 consecutive k of one row.
 __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, long ldx, int rows, int cols,
@@ -106,7 +123,7 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = rint(ldexp(tile[kc + q][r], sh));
     for (int l = 0; l < mc.n; ++l)
-        *reinterpret_cast<uint4 *>(planes + l * sp + k + (long)i * ldp) = residues16(v, mc.pf[l], mc.invp[l]);
+        *reinterpret_cast<uint4 *>(planes + l * sp + mg_plane_off(i, k, ldp)) = residues16(v, mc.pf[l], mc.invp[l]);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,9 +140,8 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 // K is taken 64 at a time: the stage's rows of 64 bytes (TILE A rows, then
 // TILE B rows) go straight from global memory into LDS
 // (global_load_lds_dwordx4, three buffers, loads two stages ahead).  A
-// wavefront's direct load fills a 1 KiB chunk of 16 rows; the four 16-byte
-// granules of row r sit XOR-permuted by mg_swz(r) so that the fragment
-// reads (16 rows, one granule) meet distinct banks.  Every fragment address
+// wavefront's direct load copies one 1 KiB plane block (16 rows, the
+// stage's 64 k, granules already permuted by mg_swz) into a 1 KiB chunk.  Every fragment address
 // is "buffer + opaque lane offset + constant", so the compiler keeps the
 // three buffers apart in its wait counts.  The grid is one-dimensional over
 // the tiles (lower triangle only for the Gram matrix), each XCD taking a
@@ -140,14 +156,6 @@ __global__ __launch_bounds__(256) void mod_slice_rows_t_kernel(const double *X, 
 // ---------------------------------------------------------------------------
 constexpr int MG_BK = 64, MG_GM = 8;
 
-// Slot of granule g of row r in LDS: g ^ mg_swz(r).  A fragment read has 16
-// consecutive rows at one granule; the LDS serves a 16-byte read for 8 (or
-// 16) consecutive lanes at a time, which must fall in distinct 16-byte bank
-// groups of 128 (or 256) bytes: with rows of 64 bytes that asks for distinct
-// slots among rows of equal r mod 2 in each 8 (and of equal r mod 4 in each
-// 16), which (r / 2 xor r / 4) mod 4 gives (a plain (r / 4) mod 4 leaves
-// rows r and r + 2 on one bank group).
-__device__ __forceinline__ int mg_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 constexpr int MG_MAX_STAGES = 1024;              // stages per split: sums of 65536 products
 
 template <int TILE_, int WM_, int WN_>
@@ -226,21 +234,20 @@ __global__ __launch_bounds__(CF::NT) void mod_gemm_kernel(ModGemmArgs p) {
     const int wm = wave % CF::WM, wn = wave / CF::WM;
 
     // Direct loads: chunk q (16 rows; A rows for q < TILE / 16, B rows after)
-    // is loaded by wavefront q % NWV.  Lane l fills row l / 4 of its chunk,
-    // slot l % 4, with granule (l % 4) ^ mg_swz(l / 4).  Rows past M (N) are read
-    // clamped: they only reach outputs that are never stored.
+    // is loaded by wavefront q % NWV: lane l copies bytes 16 l .. 16 l + 15 of
+    // the plane block of the chunk's row group and the stage.  Row groups past
+    // M (N) are read clamped: they only reach outputs that are never stored.
     constexpr int ACH = TILE / 16;
     unsigned srcoff[CPW];
 #pragma unroll
     for (int i = 0; i < CPW; ++i) {
         const int q = wave + NWV * i;
-        const int r = (q % ACH) * 16 + (lane >> 2);
-        const int g = (lane & 3) ^ mg_swz(lane >> 2);
-        srcoff[i] = q < ACH ? (unsigned)((long)min(row0 + r, p.M - 1) * p.lda + 16 * g)
-                            : (unsigned)((long)min(col0 + r, p.N - 1) * p.ldb + 16 * g);
+        const int grp = q < ACH ? min((row0 >> 4) + q % ACH, (p.M - 1) >> 4)
+                                : min((col0 >> 4) + q % ACH, (p.N - 1) >> 4);
+        srcoff[i] = (unsigned)((long)grp * 16 * (q < ACH ? p.lda : p.ldb) + 16 * lane);
     }
     auto dma = [&](int st, char *buf) {
-        const long k0 = (long)st * MG_BK;
+        const long k0 = (long)st * 1024;   // the stage's block within a row group
 #pragma unroll
         for (int i = 0; i < CPW; ++i) {
             const int q = wave + NWV * i;
@@ -439,8 +446,10 @@ hipError_t launch_mod_gemm(const ModGemmArgs &a, hipStream_t s) {
     if (a.Kpad % MG_BK != 0 || a.splitk < 1 || a.mc.n < 1 || a.mc.n > MOD_MAX) return hipErrorInvalidValue;
     const int nst = a.Kpad / MG_BK;
     if ((nst + a.splitk - 1) / a.splitk > MG_MAX_STAGES) return hipErrorInvalidValue;
-    // lane offsets into a plane are 32-bit byte counts
-    if ((double)(a.M - 1) * a.lda + a.Kpad >= 4294967296.0 || (double)(a.N - 1) * a.ldb + a.Kpad >= 4294967296.0)
+    // lane offsets into a plane (row groups of 16 rows of lda bytes) are
+    // 32-bit byte counts
+    if ((double)((a.M + 15) / 16 * 16) * a.lda >= 4294967296.0 ||
+        (double)((a.N + 15) / 16 * 16) * a.ldb >= 4294967296.0)
         return hipErrorInvalidValue;
     if ((size_t)a.strideR < mod_residue_bytes(a.M, a.N, a.lower, a.cfg)) return hipErrorInvalidValue;
     const long T = mod_tiles(a.M, a.N, a.lower, a.cfg);
