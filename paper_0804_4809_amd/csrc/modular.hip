@@ -81,13 +81,17 @@ __device__ __forceinline__ uint4 residues16(const double (&v)[16], double p, dou
 }
 
 // plane l, element (j, k) = representation of X(k, j) mod p_l, column
-// exponent e[j]; k = rows .. ldp-1 written as zeros.  A thread takes 16
-// consecutive k of one column (one 16-byte store per modulus).
+// exponent e[j]; k = rows .. ldp-1 written as zeros.  A wavefront fills one
+// plane block (16 columns j, 64 k) per modulus with one contiguous 1 KiB
+// store: lane l takes column j0 + l / 4 and the 16 consecutive k of granule
+// l % 4 (one 16-byte store per modulus).  A workgroup's four wavefronts take
+// four consecutive k blocks.
 __global__ __launch_bounds__(256) void mod_slice_cols_kernel(const double *X, long ldx, int rows, int cols,
                                                              const int *e, int beta, ModConsts mc, int8_t *planes,
                                                              long ldp, long sp) {
-    const long k0 = ((long)blockIdx.x * 256 + threadIdx.x) * 16;
-    const int j = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long k0 = ((long)blockIdx.y * 4 + wave) * 64 + 16 * (lane & 3);
+    const int j = blockIdx.x * 16 + (lane >> 2);
     if (k0 >= ldp || j >= cols) return;
     const double *col = X + (long)j * ldx;
     const int sh = beta - e[j];
@@ -413,8 +417,8 @@ __global__ __launch_bounds__(CF::NT) void mod_reconstruct_kernel(ModRecArgs a) {
 hipError_t launch_mod_slice_cols(const double *X, long ldx, int rows, int cols, const int *e, int beta,
                                  const ModConsts &mc, int8_t *planes, long ldp, long sp, hipStream_t s) {
     if (cols <= 0) return hipSuccess;
-    if (ldp % 16 != 0 || sp % 16 != 0 || (reinterpret_cast<uintptr_t>(planes) & 15)) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((ldp / 16 + 255) / 256), cols);
+    if (ldp % 64 != 0 || sp % 16 != 0 || (reinterpret_cast<uintptr_t>(planes) & 15)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((cols + 15) / 16), (unsigned)((ldp / 64 + 3) / 4));
     hipLaunchKernelGGL(mod_slice_cols_kernel, grid, dim3(256), 0, s, X, ldx, rows, cols, e, beta, mc, planes, ldp,
                        sp);
     return hipGetLastError();
