@@ -66,6 +66,10 @@ static std::mutex g_scratch_mu;
 struct geninv_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // a second stream (default priority) for the Cholesky's trailing updates,
+    // joined to `stream` by events within each call
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fact = nullptr, ev_rest[2] = {nullptr, nullptr}, ev_join = nullptr;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int *status = nullptr;     // device status word (separate from the workspace: survives regrowth)
@@ -184,7 +188,7 @@ Layout make_layout(int nn, int k, int kdim = 0) {
     L.slotP = take(n2);
     L.part_elems = (size_t)PART_S * nn * std::max(FR_NB, k);
     L.part = take(L.part_elems * sizeof(double));
-    L.lpan = take((size_t)nn * FR_NB * sizeof(double));
+    L.lpan = take((size_t)2 * nn * FR_NB * sizeof(double));   // two panels: see run_frchol
     L.dbuf = take((size_t)GJ_NB * GJ_NB * sizeof(double));
     L.rrow = take((size_t)GJ_NB * nn * sizeof(double));
     L.ccol = take((size_t)nn * GJ_NB * sizeof(double));
@@ -371,23 +375,54 @@ int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, do
         HIPCHK(launch_fill(L, ldl, nn, nn, 0.0, c->stream));
         HIPCHK(launch_fill_int(rank_buf, np + 1, 0, c->stream));
     }
+    // Without per-class timing (which records events on the call's stream
+    // only) the trailing update of panel p runs on the second stream, beside
+    // the next panel's own column update and factorization: panel p's
+    // contribution to the next panel's columns goes first on the call's
+    // stream, and the rest of the trailing matrix (columns from the panel
+    // after next) on the second stream, which the following column update
+    // waits for (both write those columns).  The two streams touch disjoint
+    // columns meanwhile; the panel buffers alternate, so a factorization does
+    // not overwrite the panel that an update in flight still reads.
+    const bool overlap = c->aux && c->prof.mask == 0 && np > 2;
     for (int p = 0; p < np; ++p) {
         const int k0 = p * FR_NB;
         const int w = std::min(FR_NB, nn - k0);
         double *panel = A + k0 + (long)k0 * lda;
+        double *Lpp = overlap ? Lp + (long)(p & 1) * nn * FR_NB : Lp;
         {
             ProfScope ps(c, PC_PANEL_FACTOR, 0.0);
-            HIPCHK(launch_frchol_panel(panel, lda, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals, Lp, nn,
+            HIPCHK(launch_frchol_panel(panel, lda, L, ldl, rank_buf, p, k0, w, nn, tolp, piv, dvals, Lpp, nn,
                                        c->stream));
         }
         const int k1 = k0 + w;
         const int rows = nn - k1;
-        if (rows > 0) {
+        if (rows <= 0) continue;
+        if (!overlap) {
             ProfScope ps(c, PC_TRAILING, 2.0 * rows * (rows + 1.0) / 2.0 * w);
-            HIPCHK(launch_dgemm(gemm(Lp + k1, nn, 0, Lp + k1, nn, 1, A + k1 + (long)k1 * lda, lda, hdim(rows),
+            HIPCHK(launch_dgemm(gemm(Lpp + k1, nn, 0, Lpp + k1, nn, 1, A + k1 + (long)k1 * lda, lda, hdim(rows),
                                      hdim(rows), hdim(w), -1.0, 1.0, GEMM_LOWER),
                                 c->stream));
+            continue;
         }
+        const int w2 = std::min(FR_NB, rows), k2 = k1 + w2, rest = nn - k2;
+        if (rest > 0) {
+            HIPCHK(hipEventRecord(c->ev_fact, c->stream));
+            HIPCHK(hipStreamWaitEvent(c->aux, c->ev_fact, 0));
+            HIPCHK(launch_dgemm(gemm(Lpp + k2, nn, 0, Lpp + k2, nn, 1, A + k2 + (long)k2 * lda, lda, hdim(rest),
+                                     hdim(rest), hdim(w), -1.0, 1.0, GEMM_LOWER),
+                                c->aux));
+            HIPCHK(hipEventRecord(c->ev_rest[p & 1], c->aux));
+        }
+        // the previous panel's rest update also wrote these columns
+        if (p > 0) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_rest[(p - 1) & 1], 0));
+        HIPCHK(launch_dgemm(gemm(Lpp + k1, nn, 0, Lpp + k1, nn, 1, A + k1 + (long)k1 * lda, lda, hdim(rows),
+                                 hdim(w2), hdim(w), -1.0, 1.0, GEMM_FULL),
+                            c->stream));
+    }
+    if (overlap) {
+        HIPCHK(hipEventRecord(c->ev_join, c->aux));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join, 0));
     }
     return GENINV_OK;
 }
@@ -813,12 +848,27 @@ int geninv_create(geninv_ctx **ctx, int device, void *hip_stream) {
         return GENINV_ENOMEM;
     }
     c->hpin = static_cast<int *>(h);
+    bool aux_ok = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t *e : {&c->ev_fact, &c->ev_rest[0], &c->ev_rest[1], &c->ev_join})
+        aux_ok = aux_ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (!aux_ok) {
+        (void)hipGetLastError();
+        for (hipEvent_t e : {c->ev_fact, c->ev_rest[0], c->ev_rest[1], c->ev_join})
+            if (e) (void)hipEventDestroy(e);
+        if (c->aux) (void)hipStreamDestroy(c->aux);
+        (void)hipHostFree(h);
+        (void)hipFree(p);
+        delete c;
+        return GENINV_EHIP;
+    }
     if (device < NOALLOC_MAX_DEVICES) {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
         if (!g_scratch[device]) {
             void *sp = nullptr;
             if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp) {
                 (void)hipGetLastError();
+                for (hipEvent_t e : {c->ev_fact, c->ev_rest[0], c->ev_rest[1], c->ev_join}) (void)hipEventDestroy(e);
+                (void)hipStreamDestroy(c->aux);
                 (void)hipHostFree(h);
                 (void)hipFree(p);
                 delete c;
@@ -840,6 +890,10 @@ int geninv_destroy(geninv_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     prof_resolve(c);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
+    for (hipEvent_t e : {c->ev_fact, c->ev_rest[0], c->ev_rest[1], c->ev_join})
+        if (e) (void)hipEventDestroy(e);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->ws) (void)hipFree(c->ws);
     if (c->status) (void)hipFree(c->status);
     if (c->hpin) (void)hipHostFree(c->hpin);
