@@ -376,7 +376,7 @@ int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, do
         HIPCHK(launch_fill_int(rank_buf, np + 1, 0, c->stream));
     }
     // Without per-class timing (which records events on the call's stream
-    // only) the trailing update of panel p runs on the second stream, beside
+    // only) and outside stream capture, the trailing update of panel p runs on the second stream, beside
     // the next panel's own column update and factorization: panel p's
     // contribution to the next panel's columns goes first on the call's
     // stream, and the rest of the trailing matrix (columns from the panel
@@ -384,7 +384,13 @@ int run_frchol(geninv_ctx *c, const Layout &lay, double *A, long lda, int nn, do
     // waits for (both write those columns).  The two streams touch disjoint
     // columns meanwhile; the panel buffers alternate, so a factorization does
     // not overwrite the panel that an update in flight still reads.
-    const bool overlap = c->aux && c->prof.mask == 0 && np > 2;
+    // (a stream being captured into a graph keeps the single-stream form)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (c->stream && hipStreamIsCapturing(c->stream, &cap) != hipSuccess) {
+        (void)hipGetLastError();
+        cap = hipStreamCaptureStatusActive;
+    }
+    const bool overlap = c->aux && c->prof.mask == 0 && np > 2 && cap == hipStreamCaptureStatusNone;
     for (int p = 0; p < np; ++p) {
         const int k0 = p * FR_NB;
         const int w = std::min(FR_NB, nn - k0);

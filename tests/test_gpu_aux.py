@@ -8,7 +8,9 @@ normally):
   earlier call (rather than an earlier step of the same call) wrote;
 * a batched plan asked for its graph on a stream that the caller is already
   capturing launches directly into the caller's graph and counts the
-  fallback; every replay of the caller's graph matches the eager run.
+  fallback; every replay of the caller's graph matches the eager run;
+* a least-squares call captured on the caller's stream replays the eager
+  result.
 """
 import numpy as np
 import pytest
@@ -127,3 +129,46 @@ def test_batched_run_inside_a_caller_capture_falls_back_to_direct_launches():
     for b in range(len(Gs)):
         assert torch.equal(plan.W(b), ref[b])
     plan.close()
+
+
+def test_lstsq_captured_into_a_caller_graph_replays_the_eager_result():
+    """geninv_dlstsq without host synchronization, captured on the caller's
+    stream (the factorization then keeps to that one stream) and replayed
+    three times with eager work in between: every replay gives the same W,
+    equal to the eager call's (which runs the trailing updates on the second
+    stream) up to the summation order of the split update."""
+    _case("lstsq in a caller graph", m=3000, n=700)
+    import ctypes
+    G, F = w.lowrank_uv(3000, 700, 500, seed=71, k=4)
+    Gd, Fd = up(G), up(F)
+    Gc, ldg = api.colmajor(Gd)
+    Fc, ldf = api.colmajor(Fd)
+    lib = api.load()
+    vp = ctypes.c_void_p
+    try:
+        api.set_host_sync(False, DEV)
+        W0 = api.empty_colmajor(700, 4, DEV)
+        ctx = api._ctx(DEV)
+        assert lib.geninv_dlstsq(ctx, 3000, 700, 4, vp(Gc.data_ptr()), ldg, vp(Fc.data_ptr()), ldf, 0.0,
+                                 vp(W0.data_ptr()), 700, None) == 0
+        torch.cuda.synchronize()
+        W = api.empty_colmajor(700, 4, DEV)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx = api._ctx(DEV)
+            st = lib.geninv_dlstsq(ctx, 3000, 700, 4, vp(Gc.data_ptr()), ldg, vp(Fc.data_ptr()), ldf, 0.0,
+                                   vp(W.data_ptr()), 700, None)
+        assert st == 0
+        first = None
+        for rep in range(3):
+            W.fill_(0.0)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            if first is None:
+                first = W.clone()
+            assert torch.equal(W, first), rep
+            _ = (torch.ones(1000, device=DEV) * rep).sum().item()   # eager work between replays
+        assert float(torch.linalg.norm(first - W0) / torch.linalg.norm(W0)) <= 1e-10
+    finally:
+        api.set_host_sync(True, DEV)
