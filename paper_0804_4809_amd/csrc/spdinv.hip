@@ -85,15 +85,50 @@ __device__ __forceinline__ double recip(double x) {
 // written per element as v alpha + X(p, j) beta with (alpha, beta) = (1,
 // -X(i, p) d) off row p and (d, 0) on it.  On return X holds the inverse.
 // Returns false (uniformly) if a pivot is not positive.
+//
+// Only row and column p + 1 (mod 4) of every register block take step p's
+// update at once: they hold what step p + 1 publishes.  The other nine
+// entries take it after step p + 1's barrier, while that step's LDS reads
+// are in flight, so the chain from one barrier to the next carries seven
+// updates instead of sixteen.  Every entry still receives the same
+// operations in the same order.
+struct GjPending {
+    double beta[4];   // -X(i, p) d for the thread's rows
+    double rp[4];     // X(p, j) for the thread's columns
+    double d;
+};
 struct GjRegs {
     double v[4][4];   // v[i][j] = X(4 rb + i, 4 cb + j)
     bool ok;
+    GjPending pend[2];   // factors of step p, in slot p mod 2
 };
 
+// the update of entry (I, J) of the register block by a step whose pivot
+// is row / column PR of the register blocks with rb / cb = pq (prow: rb ==
+// pq, pcol: cb == pq)
+template <int PR, int I, int J>
+__device__ __forceinline__ void gj_entry(double &x, const GjPending &f, bool prow, bool pcol) {
+    const bool onrow = I == PR && prow;
+    const double alpha = onrow ? f.d : 1.0;
+    const double be = onrow ? 0.0 : f.beta[I];
+    x = __builtin_fma(f.rp[J], be, x * alpha);
+    if (J == PR && pcol) x = onrow ? f.d : be;
+}
+
+// that update of the entries (I, J) with (I == R || J == R) == NEAR
+template <int PR, int R, bool NEAR, int... E>
+__device__ __forceinline__ void gj_entries(std::integer_sequence<int, E...>, double (&v)[4][4], const GjPending &f,
+                                           bool prow, bool pcol) {
+    ((((E >> 2) == R || (E & 3) == R) == NEAR ? gj_entry<PR, (E >> 2), (E & 3)>(v[E >> 2][E & 3], f, prow, pcol)
+                                               : void()),
+     ...);
+}
+
+// publish row and column p of the thread's register block (the threads that
+// hold them) into buffer p mod 2
 template <int P>
-__device__ __forceinline__ void gj_step(GjRegs &g, int w, int rb, int cb, double (*colb)[GJ_NB],
-                                        double (*rowb)[GJ_NB]) {
-    if (P >= w) return;   // identity padding: the remaining steps change nothing
+__device__ __forceinline__ void gj_publish(const GjRegs &g, int rb, int cb, double (*colb)[GJ_NB],
+                                           double (*rowb)[GJ_NB]) {
     constexpr int b = P & 1, pq = P >> 2, pr = P & 3;
     if (cb == pq) {
 #pragma unroll
@@ -103,33 +138,60 @@ __device__ __forceinline__ void gj_step(GjRegs &g, int w, int rb, int cb, double
 #pragma unroll
         for (int j = 0; j < 4; ++j) rowb[b][4 * cb + j] = g.v[pr][j];   // row p
     }
+}
+
+constexpr auto gj_all = std::make_integer_sequence<int, 16>{};
+
+// keeps x's computation before this point (the compiler would otherwise
+// sink an update to its next use, past the following step's barrier)
+__device__ __forceinline__ void gj_pin(double &x) { asm volatile("" : "+v"(x)); }
+
+template <int R, int... E>
+__device__ __forceinline__ void gj_pin_far(std::integer_sequence<int, E...>, double (&v)[4][4]) {
+    (((E >> 2) != R && (E & 3) != R ? gj_pin(v[E >> 2][E & 3]) : void()), ...);
+}
+
+template <int P>
+__device__ __forceinline__ void gj_step(GjRegs &g, int w, int rb, int cb, double (*colb)[GJ_NB],
+                                        double (*rowb)[GJ_NB]) {
+    if (P >= w) return;   // identity padding: the remaining steps change nothing
+    constexpr int b = P & 1, pr = P & 3, nr = (P + 1) & 3;
     __syncthreads();
-    // every LDS read of the step is issued before the reciprocal
+    // every LDS read of the step is issued first
     const double pv = colb[b][P];
-    double cp[4], rp[4];
+    double cp[4];
+    GjPending &f = g.pend[P & 1];
 #pragma unroll
     for (int i = 0; i < 4; ++i) cp[i] = colb[b][4 * rb + i];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) rp[j] = rowb[b][4 * cb + j];
+    for (int j = 0; j < 4; ++j) f.rp[j] = rowb[b][4 * cb + j];
     __builtin_amdgcn_sched_barrier(0);
-    if (!(pv > 0.0)) g.ok = false;
-    const double dinv = recip(pv);
-    const bool prow = rb == pq;   // this thread holds row p (as its row pr)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const bool onrow = i == pr && prow;
-        const double alpha = onrow ? dinv : 1.0;
-        const double beta = onrow ? 0.0 : -(cp[i] * dinv);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) g.v[i][j] = __builtin_fma(rp[j], beta, g.v[i][j] * alpha);
-        if (cb == pq) g.v[i][pr] = onrow ? dinv : beta;
+    // the previous step's pending update (entries off row and column p mod 4)
+    if constexpr (P > 0) {
+        constexpr int qq = (P - 1) >> 2;
+        gj_entries<(P - 1) & 3, pr, false>(gj_all, g.v, g.pend[(P - 1) & 1], rb == qq, cb == qq);
+        gj_pin_far<pr>(gj_all, g.v);
     }
+    __builtin_amdgcn_sched_barrier(0);   // ... issued while the reads are in flight
+    if (!(pv > 0.0)) g.ok = false;
+    f.d = recip(pv);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.beta[i] = -(cp[i] * f.d);
+    // row and column p + 1 mod 4 now, then publish what step p + 1 reads
+    gj_entries<pr, nr, true>(gj_all, g.v, f, rb == (P >> 2), cb == (P >> 2));
+    gj_publish<P + 1>(g, rb, cb, colb, rowb);
 }
 
 template <int... P>
 __device__ __forceinline__ void gj_steps(std::integer_sequence<int, P...>, GjRegs &g, int w, int rb, int cb,
                                          double (*colb)[GJ_NB], double (*rowb)[GJ_NB]) {
     (gj_step<P>(g, w, rb, cb, colb, rowb), ...);
+}
+
+// the pending update of the last step q (q mod 4 = QR)
+template <int QR>
+__device__ __forceinline__ void gj_flush(GjRegs &g, int q, int rb, int cb) {
+    gj_entries<QR, (QR + 1) & 3, false>(gj_all, g.v, g.pend[QR & 1], rb == (q >> 2), cb == (q >> 2));
 }
 
 __device__ bool gj_invert_block(double (*X)[GJ_LD], int w) {
@@ -144,7 +206,17 @@ __device__ bool gj_invert_block(double (*X)[GJ_LD], int w) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) g.v[i][j] = X[4 * cb + j][4 * rb + i];
-    gj_steps(std::make_integer_sequence<int, GJ_NB>{}, g, w, rb, cb, colb, rowb);
+    if (w > 0) {   // uniform
+        gj_publish<0>(g, rb, cb, colb, rowb);
+        gj_steps(std::make_integer_sequence<int, GJ_NB>{}, g, w, rb, cb, colb, rowb);
+        const int q = w - 1;   // the last step
+        switch (q & 3) {
+        case 0: gj_flush<0>(g, q, rb, cb); break;
+        case 1: gj_flush<1>(g, q, rb, cb); break;
+        case 2: gj_flush<2>(g, q, rb, cb); break;
+        default: gj_flush<3>(g, q, rb, cb); break;
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i)
