@@ -82,9 +82,10 @@ __device__ __forceinline__ double recip(double x) {
 // The two pivot rows and columns are published through LDS, double buffered
 // by the parity of p / 2 (a buffer is rewritten two steps later, after every
 // thread has passed the barrier of the step in between), so one barrier per
-// pair of pivots suffices; the per-step cost is mostly the instruction issue
-// of one wavefront per SIMD, which the pair form cuts by a third per pivot,
-// besides halving the barriers, LDS round trips and reciprocals.  For odd w
+// pair of pivots suffices.  A step's cost is mostly the instruction issue of
+// one wavefront per SIMD plus the barrier, LDS round trip and reciprocal on
+// its dependency chain; per pivot the pair form issues about a fifth fewer
+// instructions and has half as many of the latter.  For odd w
 // the last pair takes pivot w from the identity padding: its row and column
 // are zero off the diagonal, so the step reduces to the scalar one and the
 // padding stays zero next to the w x w block.  On return X holds the
