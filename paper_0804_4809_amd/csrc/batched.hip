@@ -320,6 +320,8 @@ __device__ __forceinline__ bool block_gj(double *C, long ldc, int r, double *row
 //   D^-1 in LDS;  R' = D^-1 R;  C_ij -= Q_i R'_j  (i, j outside the block);
 //   C_bj = R'_j;  C_ib = -Q_i D^-1;  C_bb = D^-1.
 // ws (LDS) holds Q (r x NB, row pitch NB + 1), R' (NB x r) and D (NB x NB).
+// The pivot test's result is that of the first wavefront (the caller reads
+// it on thread 0).
 template <int NB>
 __device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, double *ws) {
     const int tid = threadIdx.x;
@@ -344,29 +346,25 @@ __device__ __forceinline__ bool block_gj_blocked(double *C, long ldc, int r, dou
             const int c = e % nb, c2 = e / nb;
             Ds[c * NB + c2] = Qs[(b0 + c) * QP + c2];
         }
-        // D^-1 in place, one pivot at a time (at most 2 elements per thread)
-        for (int p = 0; p < nb; ++p) {
-            __syncthreads();
-            const double pv = Ds[p * NB + p];
-            if (!(pv > 0.0)) ok = false;
-            const double dinv = 1.0 / pv;
-            double v[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = tid + h * BT_THREADS;
-                v[h] = 0.0;
-                if (e < nb * nb) {
-                    const int c = e % nb, c2 = e / nb;
-                    const double rp = Ds[p * NB + c2] * dinv, cp = Ds[c * NB + p];
-                    v[h] = (c == p) ? ((c2 == p) ? dinv : rp) : ((c2 == p) ? -cp * dinv : Ds[c * NB + c2] - cp * rp);
-                }
+        // D^-1 in place on the first wavefront, one pivot at a time: lane
+        // c + NB c2 holds D(c, c2) (NB^2 <= 64), and a step's pivot row and
+        // column come from the other lanes by shuffles, so the pivots need no
+        // workgroup barrier
+        __syncthreads();
+        if (tid < 64) {
+            const int c = tid % NB, c2 = tid / NB;
+            const bool in = tid < NB * NB && c < nb && c2 < nb;
+            double v = in ? Ds[c * NB + c2] : 0.0;
+            for (int p = 0; p < nb; ++p) {
+                const double pv = __shfl(v, p + NB * p, 64);
+                const double drow = __shfl(v, p + NB * (c2 & (NB - 1)), 64);   // D(p, c2)
+                const double dcol = __shfl(v, c + NB * p, 64);                  // D(c, p)
+                if (!(pv > 0.0)) ok = false;
+                const double dinv = 1.0 / pv;
+                const double rp = drow * dinv, cp = dcol;
+                v = (c == p) ? ((c2 == p) ? dinv : rp) : ((c2 == p) ? -cp * dinv : v - cp * rp);
             }
-            __syncthreads();
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = tid + h * BT_THREADS;
-                if (e < nb * nb) Ds[(e % nb) * NB + e / nb] = v[h];
-            }
+            if (in) Ds[c * NB + c2] = v;
         }
         __syncthreads();
         // R' = D^-1 R (registers first: R is read by every output)
