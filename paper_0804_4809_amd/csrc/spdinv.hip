@@ -73,156 +73,164 @@ __device__ __forceinline__ double recip(double x) {
 // w x w in the top-left corner and identity elsewhere.  The 256 threads form
 // a 16 x 16 grid of 4 x 4 sub-blocks: thread t keeps rows 4 rb .. 4 rb + 3 and
 // columns 4 cb .. 4 cb + 3 (rb = t mod 16, cb = t / 16) in registers for the
-// whole elimination.  A step eliminates the pivot pair P = {p, p + 1} (p
-// even) at once, the 2 x 2 block form of the scalar steps: with E =
-// X(P, P)^-1 (X(P, P) is a Schur complement of an SPD matrix, so symmetric
-// positive definite, and E comes from its determinant),
-//   X(i, j) -= X(i, P) E X(P, j)   (i, j not in P),   X(P, j) = E X(P, j),
-//   X(i, P) = -X(i, P) E,                              X(P, P) = E.
-// The two pivot rows and columns are published through LDS, double buffered
-// by the parity of p / 2 (a buffer is rewritten two steps later, after every
-// thread has passed the barrier of the step in between), so one barrier per
-// pair of pivots suffices.  A step's cost is mostly the instruction issue of
-// one wavefront per SIMD plus the barrier, LDS round trip and reciprocal on
-// its dependency chain; per pivot the pair form issues about a fifth fewer
-// instructions and has half as many of the latter.  For odd w
-// the last pair takes pivot w from the identity padding: its row and column
-// are zero off the diagonal, so the step reduces to the scalar one and the
-// padding stays zero next to the w x w block.  On return X holds the
-// inverse.  Returns false (uniformly) if a pivot is not positive.
-template <int P>
-__device__ __forceinline__ void gj_publish2(const double (&v)[4][4], int rb, int cb, double (*colb)[2][4][16],
-                                            double (*rowb)[2][4][16]) {
-    constexpr int b = (P >> 1) & 1, pq = P >> 2, pr = P & 3;
-    if (cb == pq) {
-        // row 4 rb + i of column p + k at [k][i][rb] (so that no two of a
-        // thread's stores are adjacent and none needs its values gathered
-        // into consecutive registers)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            colb[b][0][i][rb] = v[i][pr];       // column p
-            colb[b][1][i][rb] = v[i][pr + 1];   // column p + 1
-        }
-    }
-    if (rb == pq) {
-        // column 4 cb + j of row p + k at [k][j][cb]
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            rowb[b][0][j][cb] = v[pr][j];       // row p
-            rowb[b][1][j][cb] = v[pr + 1][j];   // row p + 1
-        }
-    }
-}
-
-// Every entry takes one form, y = x m + W0_i R0_j + W1_i R1_j: away from
-// the pivots m = 1, W_i = -X(i, P) E (the new pivot column's values) and
-// R_j = X(P, j), the rank-two update.  On the thread's pivot rows (prow) W_i
-// is the row of E and m = 0, which gives E X(P, j); on its pivot columns
-// (pcol) R_j is the column of the identity and m = 0, which gives -X(i, P) E,
-// and both together give E.
-template <int PR, int I, int J>
-__device__ __forceinline__ void gj_entry2(double &x, const double (&W0)[4], const double (&W1)[4],
-                                          const double (&R0)[4], const double (&R1)[4], double mr, double mc,
-                                          double mrc) {
-    constexpr bool pi = I == PR || I == PR + 1, pj = J == PR || J == PR + 1;
-    const double xm = pi && pj ? x * mrc : pi ? x * mr : pj ? x * mc : x;
-    x = __builtin_fma(W0[I], R0[J], __builtin_fma(W1[I], R1[J], xm));
-}
-
-template <int PR, int... E>
-__device__ __forceinline__ void gj_entries2(std::integer_sequence<int, E...>, double (&v)[4][4],
-                                            const double (&W0)[4], const double (&W1)[4], const double (&R0)[4],
-                                            const double (&R1)[4], double mr, double mc, double mrc) {
-    (gj_entry2<PR, (E >> 2), (E & 3)>(v[E >> 2][E & 3], W0, W1, R0, R1, mr, mc, mrc), ...);
-}
-
-template <int S>
-__device__ __forceinline__ void gj_step2(double (&v)[4][4], bool &ok, int w, int rb, int cb,
-                                         double (*colb)[2][4][16], double (*rowb)[2][4][16]) {
-    constexpr int P = 2 * S;
-    if (P >= w) return;   // identity padding: the remaining steps change nothing
-    constexpr int b = S & 1, pq = P >> 2, pr = P & 3;
-    gj_publish2<P>(v, rb, cb, colb, rowb);
-    __syncthreads();
-    // every LDS read of the step is issued first
-    const double a = colb[b][0][P & 3][P >> 2], bb = colb[b][0][(P + 1) & 3][(P + 1) >> 2],
-                 c = colb[b][1][(P + 1) & 3][(P + 1) >> 2];
-    double c0[4], c1[4], R0[4], R1[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        c0[i] = colb[b][0][i][rb];
-        c1[i] = colb[b][1][i][rb];
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        R0[j] = rowb[b][0][j][cb];
-        R1[j] = rowb[b][1][j][cb];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    const double det = __builtin_fma(a, c, -(bb * bb));
-    if (!(a > 0.0 && det > 0.0)) ok = false;
-    const double inv = recip(det);
-    const double e00 = c * inv, e01 = -(bb * inv), e11 = a * inv;
-    const bool prow = rb == pq, pcol = cb == pq;
-    double W0[4], W1[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        W0[i] = __builtin_fma(c0[i], -e00, c1[i] * -e01);   // -X(i, P) E
-        W1[i] = __builtin_fma(c0[i], -e01, c1[i] * -e11);
-    }
-    W0[pr] = prow ? e00 : W0[pr];
-    W1[pr] = prow ? e01 : W1[pr];
-    W0[pr + 1] = prow ? e01 : W0[pr + 1];
-    W1[pr + 1] = prow ? e11 : W1[pr + 1];
-    R0[pr] = pcol ? 1.0 : R0[pr];
-    R1[pr] = pcol ? 0.0 : R1[pr];
-    R0[pr + 1] = pcol ? 0.0 : R0[pr + 1];
-    R1[pr + 1] = pcol ? 1.0 : R1[pr + 1];
-    const double mr = prow ? 0.0 : 1.0, mc = pcol ? 0.0 : 1.0, mrc = mr * mc;
-    gj_entries2<pr>(std::make_integer_sequence<int, 16>{}, v, W0, W1, R0, R1, mr, mc, mrc);
-}
-
-template <int... S>
-__device__ __forceinline__ void gj_steps2(std::integer_sequence<int, S...>, double (&v)[4][4], bool &ok, int w,
-                                          int rb, int cb, double (*colb)[2][4][16], double (*rowb)[2][4][16]) {
-    (gj_step2<S>(v, ok, w, rb, cb, colb, rowb), ...);
-}
-
-// LDS of the panel kernel; the pivot buffers first, so that their
-// addresses fit the LDS instructions' immediate offsets
-struct GjPanelLds {
-    double colb[2][2][4][16];
-    double rowb[2][2][4][16];
-    double X[GJ_NB][GJ_LD];
-    double Bl[GJ_NB][GJ_LD];
+// whole elimination, so that a step needs only 4 entries of the pivot row
+// and 4 of the pivot column per thread (broadcast LDS reads cost the full
+// LDS return bandwidth, so the volume per step is what bounds it).  Those are
+// published through LDS, double buffered by the parity of p (a buffer is
+// rewritten two steps later, after every thread has passed the barrier of
+// the step in between), so one barrier per step suffices.  Step p with
+// d = 1 / X(p, p):
+//   X(i, j) -= X(i, p) d X(p, j)   (i, j != p),   X(p, j) *= d   (j != p),
+//   X(i, p) = -X(i, p) d           (i != p),      X(p, p) = d,
+// written per element as v alpha + X(p, j) beta with (alpha, beta) = (1,
+// -X(i, p) d) off row p and (d, 0) on it.  On return X holds the inverse.
+// Returns false (uniformly) if a pivot is not positive.
+//
+// Only row and column p + 1 (mod 4) of every register block take step p's
+// update at once: they hold what step p + 1 publishes.  The other nine
+// entries take it after step p + 1's barrier, while that step's LDS reads
+// are in flight, so the chain from one barrier to the next carries seven
+// updates instead of sixteen.  Every entry still receives the same
+// operations in the same order.
+struct GjPending {
+    double beta[4];   // -X(i, p) d for the thread's rows
+    double rp[4];     // X(p, j) for the thread's columns
+    double d;
+};
+struct GjRegs {
+    double v[4][4];   // v[i][j] = X(4 rb + i, 4 cb + j)
+    bool ok;
+    GjPending pend[2];   // factors of step p, in slot p mod 2
 };
 
-__device__ bool gj_invert_block(double (*X)[GJ_LD], int w, double (*colb)[2][4][16], double (*rowb)[2][4][16]) {
+// the update of entry (I, J) of the register block by a step whose pivot
+// is row / column PR of the register blocks with rb / cb = pq (prow: rb ==
+// pq, pcol: cb == pq)
+template <int PR, int I, int J>
+__device__ __forceinline__ void gj_entry(double &x, const GjPending &f, bool prow, bool pcol) {
+    const bool onrow = I == PR && prow;
+    const double alpha = onrow ? f.d : 1.0;
+    const double be = onrow ? 0.0 : f.beta[I];
+    x = __builtin_fma(f.rp[J], be, x * alpha);
+    if (J == PR && pcol) x = onrow ? f.d : be;
+}
+
+// that update of the entries (I, J) with (I == R || J == R) == NEAR
+template <int PR, int R, bool NEAR, int... E>
+__device__ __forceinline__ void gj_entries(std::integer_sequence<int, E...>, double (&v)[4][4], const GjPending &f,
+                                           bool prow, bool pcol) {
+    ((((E >> 2) == R || (E & 3) == R) == NEAR ? gj_entry<PR, (E >> 2), (E & 3)>(v[E >> 2][E & 3], f, prow, pcol)
+                                               : void()),
+     ...);
+}
+
+// publish row and column p of the thread's register block (the threads that
+// hold them) into buffer p mod 2
+template <int P>
+__device__ __forceinline__ void gj_publish(const GjRegs &g, int rb, int cb, double (*colb)[GJ_NB],
+                                           double (*rowb)[GJ_NB]) {
+    constexpr int b = P & 1, pq = P >> 2, pr = P & 3;
+    if (cb == pq) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) colb[b][4 * rb + i] = g.v[i][pr];   // column p
+    }
+    if (rb == pq) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rowb[b][4 * cb + j] = g.v[pr][j];   // row p
+    }
+}
+
+constexpr auto gj_all = std::make_integer_sequence<int, 16>{};
+
+// keeps x's computation before this point (the compiler would otherwise
+// sink an update to its next use, past the following step's barrier)
+__device__ __forceinline__ void gj_pin(double &x) { asm volatile("" : "+v"(x)); }
+
+template <int R, int... E>
+__device__ __forceinline__ void gj_pin_far(std::integer_sequence<int, E...>, double (&v)[4][4]) {
+    (((E >> 2) != R && (E & 3) != R ? gj_pin(v[E >> 2][E & 3]) : void()), ...);
+}
+
+template <int P>
+__device__ __forceinline__ void gj_step(GjRegs &g, int w, int rb, int cb, double (*colb)[GJ_NB],
+                                        double (*rowb)[GJ_NB]) {
+    if (P >= w) return;   // identity padding: the remaining steps change nothing
+    constexpr int b = P & 1, pr = P & 3, nr = (P + 1) & 3;
+    __syncthreads();
+    // every LDS read of the step is issued first
+    const double pv = colb[b][P];
+    double cp[4];
+    GjPending &f = g.pend[P & 1];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cp[i] = colb[b][4 * rb + i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) f.rp[j] = rowb[b][4 * cb + j];
+    __builtin_amdgcn_sched_barrier(0);
+    // the previous step's pending update (entries off row and column p mod 4)
+    if constexpr (P > 0) {
+        constexpr int qq = (P - 1) >> 2;
+        gj_entries<(P - 1) & 3, pr, false>(gj_all, g.v, g.pend[(P - 1) & 1], rb == qq, cb == qq);
+        gj_pin_far<pr>(gj_all, g.v);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // ... issued while the reads are in flight
+    if (!(pv > 0.0)) g.ok = false;
+    f.d = recip(pv);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f.beta[i] = -(cp[i] * f.d);
+    // row and column p + 1 mod 4 now, then publish what step p + 1 reads
+    gj_entries<pr, nr, true>(gj_all, g.v, f, rb == (P >> 2), cb == (P >> 2));
+    gj_publish<P + 1>(g, rb, cb, colb, rowb);
+}
+
+template <int... P>
+__device__ __forceinline__ void gj_steps(std::integer_sequence<int, P...>, GjRegs &g, int w, int rb, int cb,
+                                         double (*colb)[GJ_NB], double (*rowb)[GJ_NB]) {
+    (gj_step<P>(g, w, rb, cb, colb, rowb), ...);
+}
+
+// the pending update of the last step q (q mod 4 = QR)
+template <int QR>
+__device__ __forceinline__ void gj_flush(GjRegs &g, int q, int rb, int cb) {
+    gj_entries<QR, (QR + 1) & 3, false>(gj_all, g.v, g.pend[QR & 1], rb == (q >> 2), cb == (q >> 2));
+}
+
+__device__ bool gj_invert_block(double (*X)[GJ_LD], int w) {
+    __shared__ __align__(16) double colb[2][GJ_NB];
+    __shared__ __align__(16) double rowb[2][GJ_NB];
     const int tid = threadIdx.x;
     const int rb = tid & 15, cb = tid >> 4;
     __syncthreads();
-    double v[4][4];   // v[i][j] = X(4 rb + i, 4 cb + j)
-    bool ok = true;
+    GjRegs g;
+    g.ok = true;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[i][j] = X[4 * cb + j][4 * rb + i];
-    gj_steps2(std::make_integer_sequence<int, GJ_NB / 2>{}, v, ok, w, rb, cb, colb, rowb);
+        for (int j = 0; j < 4; ++j) g.v[i][j] = X[4 * cb + j][4 * rb + i];
+    if (w > 0) {   // uniform
+        gj_publish<0>(g, rb, cb, colb, rowb);
+        gj_steps(std::make_integer_sequence<int, GJ_NB>{}, g, w, rb, cb, colb, rowb);
+        const int q = w - 1;   // the last step
+        switch (q & 3) {
+        case 0: gj_flush<0>(g, q, rb, cb); break;
+        case 1: gj_flush<1>(g, q, rb, cb); break;
+        case 2: gj_flush<2>(g, q, rb, cb); break;
+        default: gj_flush<3>(g, q, rb, cb); break;
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) X[4 * cb + j][4 * rb + i] = v[i][j];
+        for (int j = 0; j < 4; ++j) X[4 * cb + j][4 * rb + i] = g.v[i][j];
     __syncthreads();
-    return ok;   // uniform: every thread read the same pivots
+    return g.ok;   // uniform: every thread read the same pivots
 }
 
 __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict__ B, long ldb, Dim rd, int b,
                                                        double *__restrict__ Dbuf, double *__restrict__ Rrow,
                                                        double *__restrict__ Ccol, long ldc, int *status) {
-    __shared__ __align__(16) GjPanelLds sh;
-    double(*X)[GJ_LD] = sh.X;
-    double(*Bl)[GJ_LD] = sh.Bl;
+    __shared__ double X[GJ_NB][GJ_LD];
+    __shared__ double Bl[GJ_NB][GJ_LD];
     const int r = rd.get();
     const int nbk = (r + GJ_NB - 1) / GJ_NB;
     const int jb = blockIdx.x;
@@ -260,7 +268,7 @@ __global__ __launch_bounds__(256) void gj_panel_kernel(const double *__restrict_
             Bl[jc][lane] = cb[q];
         }
     }
-    const bool ok = gj_invert_block(X, wb, sh.colb, sh.rowb);   // begins and ends with a workgroup barrier
+    const bool ok = gj_invert_block(X, wb);   // begins and ends with a workgroup barrier
     if (!below) {
         // the old block column's block jb from the transpose in LDS
 #pragma unroll

@@ -175,6 +175,30 @@ def test_spdinv_parity():
         assert o.rel_fro(M, ref) <= 50 * cond * 2.2e-16 * r, r
 
 
+def test_spdinv_nearly_dependent_neighbour_columns():
+    """Every odd column of X is its even neighbour plus 1e-3 noise, so the
+    2 x 2 blocks of consecutive pivots are nearly singular (determinant
+    about 1e-6 of the diagonal product; cond(B) about 3e7).  An elimination
+    that takes such pairs as 2 x 2 pivot blocks through their explicit
+    inverse loses about four digits more here than the scalar sweep (1e-5
+    against 1e-9 relative in a float64 model at r = 63); the bound allows
+    2 r cond(B) u, which the scalar sweep meets and the pair form does not."""
+    _print_case("spdinv_neighbours")
+    rng = np.random.default_rng(11)
+    for r in (2, 63, 130, 333):
+        X = rng.standard_normal((3 * r + 7, r))
+        h = r // 2
+        X[:, 1:2 * h:2] = X[:, 0:2 * h:2] + 1e-3 * rng.standard_normal((3 * r + 7, h))
+        B = X.T @ X
+        ref = o.spd_inverse(B)
+        M = down(api.spd_inverse(up(B)))
+        assert np.array_equal(M, M.T)
+        cond = np.linalg.cond(B)
+        err = o.rel_fro(M, ref)
+        print(f"  r {r}: cond {cond:.1e}, relF vs oracle {err:.2e}", flush=True)
+        assert err <= 2 * cond * 2.2e-16 * r, r
+
+
 @pytest.mark.parametrize("r,smin", [(1153, 1e-3), (3072, 1e-3), (1153, 1e-4)])
 def test_spdinv_parity_path_sizes(r, smin):
     """The orders the whole method inverts on the RBF and SVD workloads:
