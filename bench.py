@@ -205,9 +205,13 @@ def _incremental_run(api, torch, Gd, Fd, first, batch, steps):
     m, n = Gd.shape
     k = Fd.shape[1]
     sync = torch.cuda.synchronize
-    # warm every path (workspace growth) at the full size
+    # warm every path at the full size (the context's workspace grows to what
+    # the largest factorization and the largest incremental step need, so no
+    # timed call allocates): the first columns, then all of them in one append
     for refactor in (False, True):
         inc = api.IncrementalLstsq(n, k, refactor=refactor)
+        inc.append(Gd[:, :first], Fd)
+        inc.solve()
         inc.append(Gd, Fd)
         inc.solve()
     api.lstsq(Gd, Fd)
